@@ -1,0 +1,229 @@
+"""CPU oracle for the ray tracer -- TEST INFRASTRUCTURE ONLY.
+
+A plain scalar FP64 C implementation of RadioPropa's method (paper §2:
+eq. 1/eq. 2 integrated with Cash-Karp, planar boundaries with reflection, a
+refracted secondary and Fresnel amplitudes).  Only the test suite, the smoke
+check and the CPU-baseline leg of the benchmark may import this package; the
+GPU library never does, and the two share no code.
+
+``trace(scene)`` returns the records as numpy arrays sorted by ray key, plus
+the run statistics.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "raytrace_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+MODEL_PAPER, MODEL_EXACT = 0, 1
+ST_PATH, ST_BOX, ST_TIME, ST_AMP, ST_ABSORB, ST_STEPCAP, ST_NONFINITE = range(1, 8)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with plain IEEE semantics (no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math",
+               "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm", "-lpthread"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class Region(C.Structure):
+    _fields_ = [("a", C.c_double), ("b", C.c_double), ("dn", C.c_double),
+                ("z0", C.c_double), ("z_top", C.c_double), ("z_bot", C.c_double),
+                ("use_grid", C.c_int32)]
+
+
+class Plane(C.Structure):
+    _fields_ = [("point", C.c_double * 3), ("normal", C.c_double * 3),
+                ("region_pos", C.c_int32), ("region_neg", C.c_int32),
+                ("kind", C.c_int32)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("n_regions", C.c_int32), ("regions", C.POINTER(Region)),
+                ("n_planes", C.c_int32), ("planes", C.POINTER(Plane)),
+                ("has_box", C.c_int32), ("box_lo", C.c_double * 3),
+                ("box_hi", C.c_double * 3),
+                ("grid", C.POINTER(C.c_float)), ("nx", C.c_int32),
+                ("ny", C.c_int32), ("nz", C.c_int32),
+                ("origin", C.c_double * 3), ("spacing", C.c_double * 3),
+                ("n_sources", C.c_int32), ("src_xyz", C.POINTER(C.c_double)),
+                ("n_rays", C.c_int64), ("dir_xyz", C.POINTER(C.c_double)),
+                ("ray_src", C.POINTER(C.c_int32)),
+                ("tol", C.c_double), ("h_min", C.c_double), ("h_max", C.c_double),
+                ("h_init", C.c_double), ("s_max", C.c_double), ("t_max", C.c_double),
+                ("amp_min", C.c_double), ("max_gen", C.c_int32),
+                ("model", C.c_int32), ("max_steps", C.c_int64)]
+
+
+F64_FIELDS = ["x", "y", "z", "ux", "uy", "uz", "s", "t",
+              "as_re", "as_im", "ap_re", "ap_im", "h"]
+U64_FIELDS = ["key", "parent"]
+I32_FIELDS = ["gen", "status", "n_acc", "n_rej", "n_ev", "region"]
+
+
+class Records(C.Structure):
+    _fields_ = ([(f, C.POINTER(C.c_double)) for f in F64_FIELDS]
+                + [(f, C.POINTER(C.c_uint64)) for f in U64_FIELDS]
+                + [(f, C.POINTER(C.c_int32)) for f in I32_FIELDS]
+                + [("capacity", C.c_int64)])
+
+
+STAT_FIELDS = ["accepted", "rejected", "relocation", "forced", "events", "spawned",
+               "suppressed_gen", "suppressed_amp", "records", "needed",
+               "nonfinite", "max_gen"]
+
+
+class Stats(C.Structure):
+    _fields_ = [(f, C.c_int64) for f in STAT_FIELDS]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        L.orc_trace.restype = C.c_int
+        L.orc_trace.argtypes = [C.POINTER(Problem), C.POINTER(C.c_int64), C.c_int64,
+                                C.POINTER(Records), C.POINTER(Stats), C.c_int]
+        L.orc_ck_trial.restype = None
+        L.orc_ck_trial.argtypes = [C.POINTER(Problem), C.c_int32,
+                                   C.POINTER(C.c_double), C.c_double,
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_field.restype = None
+        L.orc_field.argtypes = [C.POINTER(Problem), C.c_int32, C.POINTER(C.c_double),
+                                C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_fresnel.restype = C.c_int
+        L.orc_fresnel.argtypes = [C.c_double, C.c_double, C.c_double,
+                                  C.POINTER(C.c_double)]
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class _Prepared:
+    """Holds the ctypes problem and keeps its arrays alive."""
+
+    def __init__(self, scene):
+        lim = scene.limits
+        self.keep = []
+        regs = (Region * max(1, len(scene.regions)))()
+        for i, r in enumerate(scene.regions):
+            regs[i] = Region(r.a, r.b, r.dn, r.z0, r.z_top, r.z_bot, int(r.use_grid))
+        pls = (Plane * max(1, len(scene.planes)))()
+        for i, p in enumerate(scene.planes):
+            pls[i] = Plane((C.c_double * 3)(*p.point), (C.c_double * 3)(*p.normal),
+                           p.region_pos, p.region_neg, p.kind)
+        src = np.ascontiguousarray(scene.sources, dtype=np.float64)
+        dirs = np.ascontiguousarray(scene.dirs, dtype=np.float64)
+        rsrc = np.ascontiguousarray(scene.ray_src, dtype=np.int32)
+        self.keep += [regs, pls, src, dirs, rsrc]
+        P = Problem()
+        P.n_regions = len(scene.regions)
+        P.regions = C.cast(regs, C.POINTER(Region))
+        P.n_planes = len(scene.planes)
+        P.planes = C.cast(pls, C.POINTER(Plane))
+        if scene.box_lo is not None:
+            P.has_box = 1
+            P.box_lo = (C.c_double * 3)(*scene.box_lo)
+            P.box_hi = (C.c_double * 3)(*scene.box_hi)
+        if scene.grid is not None:
+            g = np.ascontiguousarray(scene.grid.n, dtype=np.float32)
+            self.keep.append(g)
+            P.grid = _ptr(g, C.c_float)
+            P.nz, P.ny, P.nx = g.shape
+            P.origin = (C.c_double * 3)(*scene.grid.origin)
+            P.spacing = (C.c_double * 3)(*scene.grid.spacing)
+        P.n_sources = src.shape[0]
+        P.src_xyz = _ptr(src, C.c_double)
+        P.n_rays = dirs.shape[0]
+        P.dir_xyz = _ptr(dirs, C.c_double)
+        P.ray_src = _ptr(rsrc, C.c_int32)
+        P.tol, P.h_min, P.h_max = lim.tol, lim.h_min, lim.h_max
+        P.h_init, P.s_max, P.t_max, P.amp_min = lim.h_init, lim.s_max, lim.t_max, lim.amp_min
+        P.max_gen, P.model, P.max_steps = lim.max_generations, lim.model, lim.max_steps_per_ray
+        self.P = P
+
+
+def trace(scene, roots=None, threads: int | None = None, capacity: int | None = None):
+    """Trace (a subset of the root rays of) ``scene``; records sorted by key."""
+    L = lib()
+    prep = _Prepared(scene)
+    n_roots = scene.n_rays if roots is None else len(roots)
+    if capacity is None:
+        capacity = max(16, 8 * n_roots + 64)
+    if threads is None:
+        threads = max(1, min(os.cpu_count() or 1, 16))
+    arrs = {}
+    for f in F64_FIELDS:
+        arrs[f] = np.zeros(capacity, np.float64)
+    for f in U64_FIELDS:
+        arrs[f] = np.zeros(capacity, np.uint64)
+    for f in I32_FIELDS:
+        arrs[f] = np.zeros(capacity, np.int32)
+    rec = Records(*([_ptr(arrs[f], C.c_double) for f in F64_FIELDS]
+                    + [_ptr(arrs[f], C.c_uint64) for f in U64_FIELDS]
+                    + [_ptr(arrs[f], C.c_int32) for f in I32_FIELDS]
+                    + [capacity]))
+    st = Stats()
+    rptr = None
+    if roots is not None:
+        ra = np.ascontiguousarray(roots, dtype=np.int64)
+        prep.keep.append(ra)
+        rptr = _ptr(ra, C.c_int64)
+    rc = L.orc_trace(C.byref(prep.P), rptr, n_roots, C.byref(rec), C.byref(st), threads)
+    stats = {f: int(getattr(st, f)) for f in STAT_FIELDS}
+    if rc == -2:
+        raise ValueError("oracle: unsupported problem (generations must be 1..4, planes <= 16)")
+    if rc != 0:
+        raise RuntimeError(f"oracle: record capacity {capacity} < needed {stats['needed']}")
+    n = stats["records"]
+    order = np.argsort(arrs["key"][:n], kind="stable")
+    out = {f: a[:n][order] for f, a in arrs.items()}
+    return out, stats
+
+
+def ck_trial(scene, region: int, y0, h: float):
+    L = lib()
+    prep = _Prepared(scene)
+    y0 = np.ascontiguousarray(y0, dtype=np.float64)
+    y5 = np.zeros(7)
+    dl = np.zeros(7)
+    L.orc_ck_trial(C.byref(prep.P), region, _ptr(y0, C.c_double), h,
+                   _ptr(y5, C.c_double), _ptr(dl, C.c_double))
+    return y5, dl
+
+
+def field(scene, region: int, r):
+    L = lib()
+    prep = _Prepared(scene)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    n = np.zeros(1)
+    g = np.zeros(3)
+    L.orc_field(C.byref(prep.P), region, _ptr(r, C.c_double), _ptr(n, C.c_double),
+                _ptr(g, C.c_double))
+    return float(n[0]), g
+
+
+def fresnel(n1: float, n2: float, ci: float):
+    """(rs, rp, ts, tp) as complex numbers, cos_t, tir flag."""
+    out = np.zeros(9)
+    tir = lib().orc_fresnel(n1, n2, ci, _ptr(out, C.c_double))
+    rs, rp = complex(out[0], out[1]), complex(out[2], out[3])
+    ts, tp = complex(out[4], out[5]), complex(out[6], out[7])
+    return rs, rp, ts, tp, float(out[8]), bool(tir)

@@ -1,0 +1,102 @@
+/*
+ * CPU oracle for the eikonal ray tracer (test infrastructure only).
+ *
+ * This is a plain, scalar, FP64 implementation of the method of RadioPropa
+ * (Winchen, arXiv:1810.01780) section 2: adaptive Cash-Karp integration of the
+ * ray equation (eq. 2 by default, eq. 1 on request) with planar media
+ * boundaries that reflect the ray and cast a refracted secondary carrying
+ * Fresnel amplitudes.  It exists to judge the GPU path; only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header or constant with the GPU library.
+ *
+ * Coordinates: z is depth (positive downward), the surface is z = 0.
+ */
+#ifndef RT_ORACLE_H
+#define RT_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_MODEL_PAPER = 0, ORC_MODEL_EXACT = 1 };
+enum { ORC_PLANE_FRESNEL = 0, ORC_PLANE_ABSORB = 1 };
+enum {
+  ORC_ST_PATH = 1,      /* reached the path-length limit */
+  ORC_ST_BOX = 2,       /* left the bounding box */
+  ORC_ST_TIME = 3,      /* reached the travel-time limit */
+  ORC_ST_AMP = 4,       /* amplitude fell below the cut */
+  ORC_ST_ABSORB = 5,    /* hit an absorbing plane */
+  ORC_ST_STEPCAP = 6,   /* step or event budget exhausted */
+  ORC_ST_NONFINITE = 7  /* NaN or Inf in the state */
+};
+
+/* n(z) = a + b z - dn exp(-z/z0), or the grid when use_grid != 0 */
+typedef struct {
+  double a, b, dn, z0, z_top, z_bot;
+  int32_t use_grid;
+} orc_region;
+
+typedef struct {
+  double point[3], normal[3];      /* normal need not be unit length */
+  int32_t region_pos, region_neg;  /* region on the +normal / -normal side */
+  int32_t kind;
+} orc_plane;
+
+typedef struct {
+  int32_t n_regions;
+  const orc_region* regions;
+  int32_t n_planes;
+  const orc_plane* planes;
+  int32_t has_box;
+  double box_lo[3], box_hi[3];
+  const float* grid; /* [nz][ny][nx], x fastest; may be NULL */
+  int32_t nx, ny, nz;
+  double origin[3], spacing[3];
+  int32_t n_sources;
+  const double* src_xyz;  /* [S][3] */
+  int64_t n_rays;
+  const double* dir_xyz;  /* [N][3] */
+  const int32_t* ray_src; /* [N] */
+  double tol, h_min, h_max, h_init, s_max, t_max, amp_min;
+  int32_t max_gen, model;
+  int64_t max_steps;
+} orc_problem;
+
+typedef struct {
+  double *x, *y, *z, *ux, *uy, *uz, *s, *t, *as_re, *as_im, *ap_re, *ap_im, *h;
+  uint64_t *key, *parent;
+  int32_t *gen, *status, *n_acc, *n_rej, *n_ev, *region;
+  int64_t capacity;
+} orc_records;
+
+typedef struct {
+  int64_t accepted, rejected, relocation, forced, events, spawned;
+  int64_t suppressed_gen, suppressed_amp, records, needed, nonfinite, max_gen;
+} orc_stats;
+
+/* Trace the root rays listed in roots (all rays when roots == NULL) with
+ * n_threads host threads.  Records are written in no particular order; each
+ * carries its key.  Returns 0, or -1 when the record capacity was too small
+ * (stats->needed then holds the required count). */
+int orc_trace(const orc_problem* P, const int64_t* roots, int64_t n_roots,
+              orc_records* out, orc_stats* stats, int n_threads);
+
+/* Single Cash-Karp trial step of the ray ODE from y0 (7 components) with step
+ * h in region reg: writes the 5th-order result and the embedded error vector. */
+void orc_ck_trial(const orc_problem* P, int32_t reg, const double y0[7],
+                  double h, double y5[7], double err_vec[7]);
+
+/* Refractive index and gradient of region reg at r. */
+void orc_field(const orc_problem* P, int32_t reg, const double r[3], double* n,
+               double grad[3]);
+
+/* Fresnel coefficients for incidence from n1 into n2 with cos(theta_i) = ci.
+ * out = {rs_re, rs_im, rp_re, rp_im, ts_re, ts_im, tp_re, tp_im, cos_t};
+ * returns 1 on total internal reflection (t = 0, cos_t = 0). */
+int orc_fresnel(double n1, double n2, double ci, double out[9]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
