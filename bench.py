@@ -1,0 +1,183 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the FP64 ray tracer on one MI355X.
+
+Default workload: the two-layer firn model -- 1,048,576 rays launched
+isotropically from 64 seeded sources (depths 10-1500 m), n = 1.78 -
+0.43 exp(-z/75 m) with +0.01 below the layer plane at 150 m, Fresnel surface
+and layer plane spawning secondaries up to four generations, 5 km path limit,
+Cash-Karp tolerance 1e-6, steps 1 mm - 10 m, paper model (eq. 2).
+
+A step is one raytrace_launch (initialisation and the whole ray tree) over
+the full batch, with inputs already resident in device memory.  The headline
+value is accepted Runge-Kutta steps per second over primaries and
+secondaries.  The trace kernel's own duration is measured with HIP events
+recorded on the launch stream, and the CPU oracle is timed on a bounded
+sample of the same workload.  Prints one JSON line.
+"""
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FP64 work of one Cash-Karp trial step in a stratified medium,
+# paper model (FMA = 2 FLOP; exp = 30, division/reciprocal = 8, square root =
+# 8 and pow = 65 FLOP, the operation counts of their usual range-reduction +
+# polynomial / Newton implementations).  Breakdown:
+#   6 stages x (field: 1 mul + exp 30 + n 4 + dn/dz 2; dw/ds: div 8; dtau/ds: 1)  276
+#   stage inputs of z and w_z for stages 2..6 (2 x 35)                           70
+#   fifth-order outputs (x, y: 2 FMA; z, w_z, tau: 4 FMA + 1 mul + 1 FMA each)     31
+#   error estimate (2 x 10), |w0| (5 + sqrt 8), three divisions (24)              57
+#   controller (pow 65, 2 mul, clamp 2)                                           69
+#   renormalise w (3 FMA-equivalent + sqrt 8 + div 8 + 3 mul)                     24
+#   boundary tests (2 planes x 6) and s += h                                      13
+FLOP_PER_TRIAL_STRAT_PAPER = 540
+# Gridded media, paper model: per stage 8 float4 node loads (128 B) -> 768 B
+# of node data per trial step.
+BYTES_PER_TRIAL_GRID = 768
+
+PEAK_FP64_VECTOR_TFLOPS = 78.6   # MI355X: 256 CU x 128 FLOP/clk x 2.4 GHz
+PEAK_HBM_GBS = 8000.0            # MI355X HBM3E
+
+
+def _hip():
+    # the HIP runtime torch already loaded (same soname as the library's)
+    lib = ctypes.CDLL("libamdhip64.so.7")
+    lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                        ctypes.c_void_p]
+    lib.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+    lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+    return lib
+
+
+def make_scene(name):
+    from paper_1810_01780_amd import workloads as W
+    if name == "twolayer":
+        return W.two_layer(), dict(workload="twolayer", rays=1048576, sources=64,
+                                   generations=4, tol=1e-6, s_max_m=5000, model="paper")
+    if name == "grid256":
+        return W.gridded(), dict(workload="grid256", rays=4194304, sources=256,
+                                 grid=[256, 256, 128], spacing_m=10, tol=1e-7, s_max_m=3000,
+                                 model="paper")
+    if name == "fan1024":
+        return W.point_source_fan(), dict(workload="fan1024", rays=1024, sources=1,
+                                          generations=2, tol=1e-6, s_max_m=2000, model="paper")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(scene, target_s, threads, log):
+    """Time the CPU oracle on an evenly strided sample of the root rays."""
+    import numpy as np
+    import oracle
+    n = scene.n_rays
+    probe = np.arange(0, n, max(1, n // 512), dtype=np.int64)
+    t0 = time.perf_counter()
+    _, st = oracle.trace(scene, roots=probe, threads=threads)
+    dt = time.perf_counter() - t0
+    per_root = dt / len(probe)
+    stride = max(1, int(np.ceil(n * per_root / target_s)))
+    roots = np.arange(0, n, stride, dtype=np.int64)
+    log(f"cpu baseline: {len(roots)} of {n} roots (every {stride}th), {threads} threads")
+    t0 = time.perf_counter()
+    _, st = oracle.trace(scene, roots=roots, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": st["accepted"] / dt, "unit": "ray-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"every {stride}th root ray ({len(roots)} of {n}) with its full "
+                      f"secondary tree: {st['accepted']} accepted steps in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="twolayer", choices=["twolayer", "grid256", "fan1024"])
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--refill", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-threads", type=int, default=16)
+    args = ap.parse_args()
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this tracer runs on one GPU; a multi-GPU run is not part of this "
+              "build (rays shard trivially by root index; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1810_01780_amd import binding
+
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    scene, cfg = make_scene(args.workload)
+    log(f"workload {cfg['workload']}: {scene.n_rays} rays")
+    ds = binding.DeviceScene(scene)
+    hip = _hip()
+
+    def event():
+        e = ctypes.c_void_p()
+        assert hip.hipEventCreate(ctypes.byref(e)) == 0
+        return e
+
+    def tuning(b=None, e=None):
+        return binding.rt_tuning(args.block, 0, args.refill, b, e)
+
+    for i in range(args.warmup):
+        ds.launch(tuning=tuning())
+        rec, st = ds.collect()
+        log(f"warmup {i}: {st['records']} records, {st['accepted']} accepted steps")
+    pairs = [(event(), event()) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, e in pairs:
+        ds.launch(tuning=tuning(b, e))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    _, st = ds.collect()
+    kern_ms = []
+    for b, e in pairs:
+        ms = ctypes.c_float()
+        hip.hipEventElapsedTime(ctypes.byref(ms), b, e)
+        kern_ms.append(ms.value)
+        hip.hipEventDestroy(b)
+        hip.hipEventDestroy(e)
+    kern_s = sum(kern_ms) / len(kern_ms) / 1e3
+    log(f"timed {args.steps} launches: {wall:.3f} s wall, trace kernel {kern_s * 1e3:.3f} ms avg; "
+        f"stats {st}")
+
+    trials = st["accepted"] + st["rejected"] + st["relocation"]
+    if args.workload == "grid256":
+        achieved = trials * BYTES_PER_TRIAL_GRID / kern_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+    else:
+        achieved = trials * FLOP_PER_TRIAL_STRAT_PAPER / kern_s / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
+                "traffic": None}
+    roof["kernel"] = "trace_kernel"
+    roof["kernel_ms"] = kern_s * 1e3
+
+    cfg.update(trial_steps=trials, accepted_steps=st["accepted"], records=st["records"],
+               spawned=st["spawned"])
+    value = st["accepted"] * args.steps / wall
+    out = {"metric": "accepted RK45 ray-steps/s (FP64)", "value": value, "unit": "ray-steps/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": cfg,
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(scene, args.cpu_seconds,
+                                           min(args.cpu_threads, os.cpu_count() or 1), log)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,248 @@
+/*
+ * radiotrace -- FP64 eikonal ray tracing on MI355X (gfx950).
+ *
+ * C ABI of the GPU library.  It traces very many rays through a stratified
+ * (analytic) or gridded refractive-index field with adaptive Cash-Karp
+ * Runge-Kutta 4(5) steps, and handles planar media boundaries where a ray is
+ * reflected and a refracted secondary ray is cast, both carrying Fresnel
+ * amplitudes.  This is the method of RadioPropa (T. Winchen,
+ * arXiv:1810.01780), section 2:
+ *   - eq. 2, the locally paraxial ray equation n d2r/ds2 = grad n, is the
+ *     default model (RT_MODEL_PAPER); eq. 1, the full eikonal
+ *     d/ds (n dr/ds) = grad n, is RT_MODEL_EXACT;
+ *   - the Cash-Karp solver with a tolerance and a minimum step length as the
+ *     free accuracy parameters (section 2, accuracy discussion);
+ *   - boundaries defined explicitly and handled apart from the propagation:
+ *     reflection, a refracted secondary cast from the intersection point,
+ *     Fresnel amplitudes (section 2, boundary paragraph);
+ *   - travel-time and amplitude limits (Fig. 1 example); amplitudes are not
+ *     corrected for path length (Fig. 1 caption).
+ *
+ * Coordinates: right-handed, z is DEPTH (positive downward); the surface of
+ * the example media is the plane z = 0 with air at z < 0.  Lengths in metres,
+ * times in seconds.
+ *
+ * Conventions for every entry point:
+ *   - Descriptor structs are read on the host during the call and not kept.
+ *   - Array pointers inside descriptors are DEVICE pointers (hipMalloc'ed or
+ *     torch CUDA tensors) unless the field comment says "host".
+ *   - The caller owns every buffer.  The library never allocates memory the
+ *     caller can see; raytrace_launch allocates nothing at all (its scratch
+ *     memory is the caller-provided workspace).
+ *   - No C++ exception crosses the ABI.  Functions return rt_status; on a
+ *     non-OK status rt_last_error() holds a message for the calling thread.
+ */
+#ifndef RADIOTRACE_H
+#define RADIOTRACE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RT_ABI_VERSION 1
+#define RT_MAX_REGIONS 8
+#define RT_MAX_PLANES 16
+#define RT_MAX_GENERATIONS 4 /* ray keys hold three 8-bit event ordinals */
+
+typedef enum {
+  RT_OK = 0,
+  RT_ERR_INVALID_ARG = 1, /* bad descriptor, or rays flagged RT_ST_INVALID */
+  RT_ERR_CAPACITY = 2,    /* more records than out->capacity; see stats.needed */
+  RT_ERR_DEVICE = 3,      /* a HIP call failed; message in rt_last_error() */
+  RT_ERR_UNSUPPORTED = 4  /* e.g. more than RT_MAX_GENERATIONS generations */
+} rt_status;
+
+enum { RT_MODEL_PAPER = 0, RT_MODEL_EXACT = 1 };
+enum { RT_PLANE_FRESNEL = 0, RT_PLANE_ABSORB = 1 };
+
+/* Per-record status (out->status). */
+enum {
+  RT_ST_QUEUED = -1,   /* internal: slot holds a ray waiting to be traced */
+  RT_ST_EMPTY = 0,     /* internal: slot not written */
+  RT_ST_PATH = 1,      /* reached the path-length limit s_max */
+  RT_ST_BOX = 2,       /* crossed a face of the bounding box */
+  RT_ST_TIME = 3,      /* reached the travel-time limit t_max */
+  RT_ST_AMP = 4,       /* max(|A_s|, |A_p|) fell below amp_min */
+  RT_ST_ABSORB = 5,    /* crossed an RT_PLANE_ABSORB plane */
+  RT_ST_STEPCAP = 6,   /* step budget or 255 boundary events exhausted */
+  RT_ST_NONFINITE = 7, /* NaN or Inf appeared in the state */
+  RT_ST_INVALID = 8    /* bad input ray: zero/non-finite direction, source
+                          index out of range, source within 1e-9 m of a plane
+                          or outside the box; not traced */
+};
+
+/* One stratified medium.  Analytic: n(z) = a + b*z - dn*exp(-z/z0), which
+ * covers the paper's firn profile n0 - dn*exp(-depth/z0) (section 2) and
+ * linear and constant media.  use_grid != 0: n comes from rt_field.grid.
+ * [z_top, z_bot) is used only to pick the region a primary ray starts in. */
+typedef struct {
+  double a, b, dn, z0;
+  double z_top, z_bot;
+  int32_t use_grid;
+} rt_region;
+
+/* Gridded refractive index (section 2 mentions gridded data): FP32 values
+ * n[k][j][i] at origin + (i, j, k) * spacing, x fastest.  n is trilinearly
+ * interpolated; grad n is the trilinear interpolation of node gradients
+ * taken by central differences (one-sided at the edges).  The node
+ * differences are formed in FP32, which is exact when all values lie within
+ * a factor of two of each other (true for refractive indices in [1, 2)).
+ * Positions outside the grid are clamped onto it.  nx, ny, nz >= 2. */
+typedef struct {
+  const float* n; /* device, nz*ny*nx floats */
+  int32_t nx, ny, nz;
+  double origin[3], spacing[3];
+} rt_grid;
+
+typedef struct {
+  int32_t n_regions;        /* 1..RT_MAX_REGIONS */
+  const rt_region* regions; /* host */
+  rt_grid grid;             /* used when any region has use_grid */
+} rt_field;
+
+/* A planar boundary.  The normal need not be unit length.  region_pos is the
+ * medium on the side the normal points to, region_neg the other one; a ray
+ * refracted through the plane continues in the other medium.  Stage
+ * evaluations of a step always use the ray's own medium, extended smoothly
+ * across the plane; the crossing itself is found by the event search. */
+typedef struct {
+  double point[3], normal[3];
+  int32_t region_pos, region_neg;
+  int32_t kind; /* RT_PLANE_FRESNEL or RT_PLANE_ABSORB */
+} rt_plane;
+
+typedef struct {
+  int32_t n_planes;       /* 0..RT_MAX_PLANES */
+  const rt_plane* planes; /* host */
+  int32_t has_box;        /* rays end (RT_ST_BOX) on leaving [box_lo, box_hi] */
+  double box_lo[3], box_hi[3];
+} rt_boundaries;
+
+typedef struct {
+  const double* xyz; /* device, [n][3] source positions */
+  int32_t n;
+} rt_sources;
+
+typedef struct {
+  const double* xyz;  /* device, [n][3] launch directions (any length > 0) */
+  const int32_t* src; /* device, [n] source index of each ray */
+  int64_t n;          /* number of primary rays, >= 0 */
+} rt_directions;
+
+typedef struct {
+  double h_min;   /* minimum step: a trial at h <= h_min is always accepted */
+  double h_max;   /* maximum step */
+  double h_init;  /* first step of a primary ray; 0 means h_max */
+  double s_max;   /* path-length limit (> 0) */
+  double t_max;   /* travel-time limit, 0 = off */
+  double amp_min; /* amplitude cut, 0 = off */
+  int32_t max_generations; /* 1 = primaries only ... 4 */
+  int32_t model;           /* RT_MODEL_PAPER or RT_MODEL_EXACT */
+  int64_t max_steps_per_ray; /* accepted + rejected trials per ray, >= 1 */
+} rt_step_limits;
+
+/* Launch statistics, accumulated on the device into out->stats. */
+typedef struct {
+  int64_t accepted;   /* accepted steps (the throughput unit) */
+  int64_t rejected;   /* rejected trial steps */
+  int64_t relocation; /* trial steps spent locating boundary crossings */
+  int64_t forced;     /* steps accepted at h_min above tolerance */
+  int64_t events;     /* Fresnel boundary events */
+  int64_t spawned;    /* refracted secondaries created */
+  int64_t suppressed_gen; /* secondaries not created: generation limit */
+  int64_t suppressed_amp; /* secondaries not created: amplitude cut */
+  int64_t records;    /* records written (rays finished) */
+  int64_t needed;     /* records the launch needed (primaries + spawned) */
+  int64_t nonfinite;  /* rays ended RT_ST_NONFINITE */
+  int64_t max_gen;    /* highest generation traced */
+  int64_t invalid;    /* primary rays flagged RT_ST_INVALID */
+  int64_t refills;    /* wave refill operations of the scheduler */
+  int64_t sched_errors; /* scheduler waits that timed out (must stay 0) */
+} rt_stats;
+
+/* Caller-owned output records, one per ray (primary or secondary), in no
+ * particular order; 'key' identifies a ray deterministically: bits 24..55
+ * hold the primary index, bits 16..23 / 8..15 / 0..7 the parent's event
+ * ordinal (1..255) at which the generation-1 / -2 / -3 ancestor was cast.
+ * All arrays are device arrays of 'capacity' elements.  x,y,z: final
+ * position; ux,uy,uz: final unit direction; s: path length; t: travel time;
+ * as_*, ap_*: complex s- and p-polarised amplitude factors (start 1 + 0i);
+ * h: last proposed step; parent: key of the ray that cast it (~0 for
+ * primaries); gen: generation (0 = primary); n_acc/n_rej: accepted/rejected
+ * steps of this ray; n_ev: its Fresnel events; region: medium at the end;
+ * side: bit k set when the ray is on the +normal side of boundary k. */
+typedef struct {
+  double *x, *y, *z, *ux, *uy, *uz, *s, *t;
+  double *as_re, *as_im, *ap_re, *ap_im, *h;
+  uint64_t *key, *parent;
+  int32_t *gen, *status, *n_acc, *n_rej, *n_ev, *region;
+  uint32_t* side;
+  int64_t capacity; /* >= number of primary rays */
+  rt_stats* stats;  /* device, one struct; overwritten by each launch */
+} rt_outputs;
+
+/* Optional launch tuning; NULL selects the defaults. */
+typedef struct {
+  int32_t block_size;       /* threads per block, multiple of 64, 64..1024; 0 = 256 */
+  int32_t blocks_per_cu;    /* resident blocks per CU; 0 = occupancy maximum */
+  int32_t refill_threshold; /* a wave refills when at least this many of its
+                               64 lanes are idle (1..64); 0 = 16 */
+  void* ev_trace_begin;     /* hipEvent_t recorded just before the trace
+                               kernel, or NULL */
+  void* ev_trace_end;       /* hipEvent_t recorded just after it, or NULL */
+} rt_tuning;
+
+/* ABI version (RT_ABI_VERSION of the built library). */
+int32_t rt_abi_version(void);
+
+/* Host-only validation of the descriptors (no device access): null pointers,
+ * counts and limits (1 <= n_regions <= RT_MAX_REGIONS, n_planes <=
+ * RT_MAX_PLANES, region indices in range, a zero plane normal, tol > 0,
+ * 0 < h_min <= h_max, h_init >= 0, s_max > 0, t_max >= 0, amp_min >= 0,
+ * 1 <= max_generations <= RT_MAX_GENERATIONS, model known, max_steps >= 1,
+ * grid dims >= 2 and spacing > 0 when a region uses the grid, box lo < hi).
+ * Per-ray checks need the device data and happen in raytrace_launch (rays
+ * flagged RT_ST_INVALID, counted in stats.invalid). */
+rt_status rt_validate(const rt_field* field, const rt_boundaries* boundaries,
+                      const rt_sources* sources,
+                      const rt_directions* directions, double tol,
+                      const rt_step_limits* limits);
+
+/* Bytes of device workspace raytrace_launch needs for this field: queue
+ * counters, plus the prepared grid (16 bytes per node) for gridded fields. */
+rt_status rt_workspace_bytes(const rt_field* field, size_t* bytes);
+
+/* Trace all primary rays and every secondary they cast.  Asynchronous on
+ * 'stream' (a hipStream_t; NULL = the default stream): it validates the
+ * descriptors, prepares the grid, writes the primaries into the record slots
+ * and runs the persistent trace kernel, then returns RT_OK.  Conditions found
+ * on the device land in out->stats; after synchronising, copy the stats to
+ * the host and pass them to rt_collect.  'workspace' is device memory of at
+ * least rt_workspace_bytes; it is overwritten.  Launches sharing a
+ * workspace or outputs must not overlap. */
+rt_status raytrace_launch(const rt_field* field,
+                          const rt_boundaries* boundaries,
+                          const rt_sources* sources,
+                          const rt_directions* directions, double tol,
+                          const rt_step_limits* limits, rt_outputs* out,
+                          void* workspace, size_t workspace_bytes,
+                          void* stream, const rt_tuning* tuning);
+
+/* Map the statistics of a finished launch to a status: RT_ERR_DEVICE when
+ * the scheduler reported an error, RT_ERR_INVALID_ARG when input rays were
+ * invalid, RT_ERR_CAPACITY when stats.needed exceeds
+ * capacity (records of the slots below capacity are still valid; relaunch
+ * with a capacity of at least stats.needed), else RT_OK.  Rays that ended
+ * RT_ST_NONFINITE are per-ray results and do not fail the launch. */
+rt_status rt_collect(const rt_stats* host_stats, int64_t capacity);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char* rt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RADIOTRACE_H */

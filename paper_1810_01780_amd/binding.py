@@ -1,0 +1,285 @@
+"""Thin ctypes binding of the radiotrace C ABI (include/radiotrace.h).
+
+The functions carry the C names (rt_abi_version, rt_validate,
+rt_workspace_bytes, raytrace_launch, rt_collect, rt_last_error) and only
+marshal arguments; every step of the tracing runs in the HIP kernels.  PyTorch
+supplies device memory and the stream.  The library must have been built
+(``paper_1810_01780_amd.build.build()``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+from . import workloads as W
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libradiotrace.so")
+
+RT_OK, RT_ERR_INVALID_ARG, RT_ERR_CAPACITY, RT_ERR_DEVICE, RT_ERR_UNSUPPORTED = range(5)
+RT_ST_QUEUED, RT_ST_EMPTY = -1, 0
+(RT_ST_PATH, RT_ST_BOX, RT_ST_TIME, RT_ST_AMP, RT_ST_ABSORB, RT_ST_STEPCAP,
+ RT_ST_NONFINITE, RT_ST_INVALID) = range(1, 9)
+RT_MAX_REGIONS, RT_MAX_PLANES, RT_MAX_GENERATIONS = 8, 16, 4
+
+
+class rt_region(C.Structure):
+    _fields_ = [("a", C.c_double), ("b", C.c_double), ("dn", C.c_double), ("z0", C.c_double),
+                ("z_top", C.c_double), ("z_bot", C.c_double), ("use_grid", C.c_int32)]
+
+
+class rt_grid(C.Structure):
+    _fields_ = [("n", C.c_void_p), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("origin", C.c_double * 3), ("spacing", C.c_double * 3)]
+
+
+class rt_field(C.Structure):
+    _fields_ = [("n_regions", C.c_int32), ("regions", C.POINTER(rt_region)), ("grid", rt_grid)]
+
+
+class rt_plane(C.Structure):
+    _fields_ = [("point", C.c_double * 3), ("normal", C.c_double * 3),
+                ("region_pos", C.c_int32), ("region_neg", C.c_int32), ("kind", C.c_int32)]
+
+
+class rt_boundaries(C.Structure):
+    _fields_ = [("n_planes", C.c_int32), ("planes", C.POINTER(rt_plane)),
+                ("has_box", C.c_int32), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3)]
+
+
+class rt_sources(C.Structure):
+    _fields_ = [("xyz", C.c_void_p), ("n", C.c_int32)]
+
+
+class rt_directions(C.Structure):
+    _fields_ = [("xyz", C.c_void_p), ("src", C.c_void_p), ("n", C.c_int64)]
+
+
+class rt_step_limits(C.Structure):
+    _fields_ = [("h_min", C.c_double), ("h_max", C.c_double), ("h_init", C.c_double),
+                ("s_max", C.c_double), ("t_max", C.c_double), ("amp_min", C.c_double),
+                ("max_generations", C.c_int32), ("model", C.c_int32),
+                ("max_steps_per_ray", C.c_int64)]
+
+
+STAT_FIELDS = ["accepted", "rejected", "relocation", "forced", "events", "spawned",
+               "suppressed_gen", "suppressed_amp", "records", "needed", "nonfinite",
+               "max_gen", "invalid", "refills", "sched_errors"]
+
+
+class rt_stats(C.Structure):
+    _fields_ = [(f, C.c_int64) for f in STAT_FIELDS]
+
+
+F64_FIELDS = ["x", "y", "z", "ux", "uy", "uz", "s", "t", "as_re", "as_im", "ap_re", "ap_im", "h"]
+U64_FIELDS = ["key", "parent"]
+I32_FIELDS = ["gen", "status", "n_acc", "n_rej", "n_ev", "region"]
+U32_FIELDS = ["side"]
+RECORD_FIELDS = F64_FIELDS + U64_FIELDS + I32_FIELDS + U32_FIELDS
+
+
+class rt_outputs(C.Structure):
+    _fields_ = ([(f, C.c_void_p) for f in RECORD_FIELDS]
+                + [("capacity", C.c_int64), ("stats", C.c_void_p)])
+
+
+class rt_tuning(C.Structure):
+    _fields_ = [("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("refill_threshold", C.c_int32), ("ev_trace_begin", C.c_void_p),
+                ("ev_trace_end", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libradiotrace.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                               "paper_1810_01780_amd.build.build() (no fallback path exists)")
+        # PyTorch ships its own HIP runtime under the same soname; loading torch
+        # first makes this library bind to that one runtime instead of a second
+        # copy (device pointers and streams must come from one runtime).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(_LIB_PATH)
+        L.rt_abi_version.restype = C.c_int32
+        L.rt_abi_version.argtypes = []
+        L.rt_validate.restype = C.c_int
+        L.rt_validate.argtypes = [C.POINTER(rt_field), C.POINTER(rt_boundaries),
+                                  C.POINTER(rt_sources), C.POINTER(rt_directions), C.c_double,
+                                  C.POINTER(rt_step_limits)]
+        L.rt_workspace_bytes.restype = C.c_int
+        L.rt_workspace_bytes.argtypes = [C.POINTER(rt_field), C.POINTER(C.c_size_t)]
+        L.raytrace_launch.restype = C.c_int
+        L.raytrace_launch.argtypes = [C.POINTER(rt_field), C.POINTER(rt_boundaries),
+                                      C.POINTER(rt_sources), C.POINTER(rt_directions), C.c_double,
+                                      C.POINTER(rt_step_limits), C.POINTER(rt_outputs),
+                                      C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(rt_tuning)]
+        L.rt_collect.restype = C.c_int
+        L.rt_collect.argtypes = [C.POINTER(rt_stats), C.c_int64]
+        L.rt_last_error.restype = C.c_char_p
+        L.rt_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+# --- the C entry points, same names ------------------------------------------
+def rt_abi_version() -> int:
+    return int(lib().rt_abi_version())
+
+
+def rt_validate(field, boundaries, sources, directions, tol, limits) -> int:
+    return int(lib().rt_validate(C.byref(field), C.byref(boundaries), C.byref(sources),
+                                 C.byref(directions), float(tol), C.byref(limits)))
+
+
+def rt_workspace_bytes(field) -> int:
+    n = C.c_size_t(0)
+    st = lib().rt_workspace_bytes(C.byref(field), C.byref(n))
+    if st != RT_OK:
+        raise RTError(st, rt_last_error())
+    return int(n.value)
+
+
+def raytrace_launch(field, boundaries, sources, directions, tol, limits, outputs, workspace,
+                    workspace_bytes, stream, tuning=None) -> int:
+    return int(lib().raytrace_launch(
+        C.byref(field), C.byref(boundaries), C.byref(sources), C.byref(directions), float(tol),
+        C.byref(limits), C.byref(outputs), C.c_void_p(workspace), C.c_size_t(workspace_bytes),
+        C.c_void_p(stream), C.byref(tuning) if tuning is not None else None))
+
+
+def rt_collect(stats, capacity: int) -> int:
+    return int(lib().rt_collect(C.byref(stats), C.c_int64(capacity)))
+
+
+def rt_last_error() -> str:
+    return lib().rt_last_error().decode()
+
+
+class RTError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"radiotrace status {status}: {msg}")
+        self.status = status
+
+
+# --- descriptor marshalling for workload scenes ------------------------------
+class HostDescriptors:
+    """ctypes descriptors of a Scene's host-side parts (regions, planes, box,
+    limits); device pointers are filled in by DeviceScene."""
+
+    def __init__(self, scene: W.Scene):
+        self.scene = scene
+        regs = (rt_region * max(1, len(scene.regions)))()
+        for i, r in enumerate(scene.regions):
+            regs[i] = rt_region(r.a, r.b, r.dn, r.z0, r.z_top, r.z_bot, int(r.use_grid))
+        pls = (rt_plane * max(1, len(scene.planes)))()
+        for i, p in enumerate(scene.planes):
+            pls[i] = rt_plane((C.c_double * 3)(*p.point), (C.c_double * 3)(*p.normal),
+                              p.region_pos, p.region_neg, p.kind)
+        self._keep = [regs, pls]
+        self.field = rt_field(len(scene.regions), C.cast(regs, C.POINTER(rt_region)), rt_grid())
+        if scene.grid is not None:
+            nz, ny, nx = scene.grid.n.shape
+            self.field.grid.nx, self.field.grid.ny, self.field.grid.nz = nx, ny, nz
+            self.field.grid.origin = (C.c_double * 3)(*scene.grid.origin)
+            self.field.grid.spacing = (C.c_double * 3)(*scene.grid.spacing)
+        self.bnd = rt_boundaries(len(scene.planes), C.cast(pls, C.POINTER(rt_plane)), 0)
+        if scene.box_lo is not None:
+            self.bnd.has_box = 1
+            self.bnd.box_lo = (C.c_double * 3)(*scene.box_lo)
+            self.bnd.box_hi = (C.c_double * 3)(*scene.box_hi)
+        lim = scene.limits
+        self.limits = rt_step_limits(lim.h_min, lim.h_max, lim.h_init, lim.s_max, lim.t_max,
+                                     lim.amp_min, lim.max_generations, lim.model,
+                                     lim.max_steps_per_ray)
+        self.tol = lim.tol
+        self.sources = rt_sources(None, int(scene.sources.shape[0]))
+        self.dirs = rt_directions(None, None, int(scene.n_rays))
+
+
+class DeviceScene:
+    """Device-resident inputs, outputs and workspace for one Scene (torch
+    tensors on cuda:0 by default), reusable across launches."""
+
+    def __init__(self, scene: W.Scene, capacity: Optional[int] = None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.scene = scene
+        self.desc = HostDescriptors(scene)
+        dev = torch.device(device)
+        self.device = dev
+        self.src = torch.as_tensor(np.ascontiguousarray(scene.sources, np.float64), device=dev)
+        self.dirs = torch.as_tensor(np.ascontiguousarray(scene.dirs, np.float64), device=dev)
+        self.ray_src = torch.as_tensor(np.ascontiguousarray(scene.ray_src, np.int32), device=dev)
+        self.desc.sources.xyz = self.src.data_ptr()
+        self.desc.dirs.xyz = self.dirs.data_ptr()
+        self.desc.dirs.src = self.ray_src.data_ptr()
+        if scene.grid is not None:
+            self.grid = torch.as_tensor(np.ascontiguousarray(scene.grid.n, np.float32), device=dev)
+            self.desc.field.grid.n = self.grid.data_ptr()
+        self.capacity = int(capacity if capacity is not None else scene.capacity_hint())
+        self.capacity = max(self.capacity, scene.n_rays)
+        cap = max(1, self.capacity)
+        self.rec: Dict[str, "torch.Tensor"] = {}
+        for f in F64_FIELDS:
+            self.rec[f] = torch.empty(cap, dtype=torch.float64, device=dev)
+        for f in U64_FIELDS:
+            self.rec[f] = torch.empty(cap, dtype=torch.int64, device=dev)
+        for f in I32_FIELDS + U32_FIELDS:
+            self.rec[f] = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.stats_dev = torch.zeros(len(STAT_FIELDS), dtype=torch.int64, device=dev)
+        self.out = rt_outputs(*([self.rec[f].data_ptr() for f in RECORD_FIELDS]
+                                + [self.capacity, self.stats_dev.data_ptr()]))
+        self.ws_bytes = rt_workspace_bytes(self.desc.field)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+
+    def launch(self, stream=None, tuning: Optional[rt_tuning] = None) -> None:
+        """Enqueue one full trace on the stream (torch's current stream by default)."""
+        torch = self.torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        st = raytrace_launch(self.desc.field, self.desc.bnd, self.desc.sources, self.desc.dirs,
+                             self.desc.tol, self.desc.limits, self.out, self.workspace.data_ptr(),
+                             self.ws_bytes, stream.cuda_stream, tuning)
+        if st != RT_OK:
+            raise RTError(st, rt_last_error())
+
+    def stats(self) -> Dict[str, int]:
+        v = self.stats_dev.cpu().numpy()
+        return {f: int(v[i]) for i, f in enumerate(STAT_FIELDS)}
+
+    def collect(self, check: bool = True):
+        """Synchronise, then return (records as numpy arrays in slot order,
+        stats); raises RTError on a failing status when check is set."""
+        self.torch.cuda.synchronize(self.device)
+        stats = self.stats()
+        host = rt_stats(*[stats[f] for f in STAT_FIELDS])
+        st = rt_collect(host, self.capacity)
+        if check and st != RT_OK:
+            raise RTError(st, rt_last_error())
+        n = min(stats["needed"], self.capacity)
+        out = {}
+        for f in RECORD_FIELDS:
+            a = self.rec[f][:n].cpu().numpy()
+            if f in U64_FIELDS:
+                a = a.view(np.uint64)
+            elif f in U32_FIELDS:
+                a = a.view(np.uint32)
+            out[f] = a
+        return out, stats
+
+
+def trace(scene: W.Scene, capacity: Optional[int] = None, tuning: Optional[rt_tuning] = None,
+          check: bool = True):
+    """Trace a scene on the GPU; returns (records in slot order, stats)."""
+    ds = DeviceScene(scene, capacity=capacity)
+    ds.launch(tuning=tuning)
+    return ds.collect(check=check)

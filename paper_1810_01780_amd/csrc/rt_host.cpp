@@ -1,0 +1,160 @@
+// Host-only parts of the C ABI: validation, workspace sizing, status
+// collection and the per-thread error message.  No device access here.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "rt_params.hpp"
+
+namespace rt {
+
+static thread_local char g_err[512];
+
+void set_last_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+
+bool field_uses_grid(const rt_field* f) {
+  for (int i = 0; i < f->n_regions; ++i)
+    if (f->regions[i].use_grid) return true;
+  return false;
+}
+
+static bool finite3(const double* v) {
+  return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+#define FAIL(code, ...)            \
+  do {                             \
+    set_last_error(__VA_ARGS__);   \
+    return code;                   \
+  } while (0)
+
+rt_status validate(const rt_field* field, const rt_boundaries* bnd, const rt_sources* src,
+                   const rt_directions* dirs, double tol, const rt_step_limits* L) {
+  if (!field || !bnd || !src || !dirs || !L) FAIL(RT_ERR_INVALID_ARG, "null descriptor");
+  if (field->n_regions < 1 || field->n_regions > RT_MAX_REGIONS || !field->regions)
+    FAIL(RT_ERR_INVALID_ARG, "n_regions must be 1..%d with a region array", RT_MAX_REGIONS);
+  for (int i = 0; i < field->n_regions; ++i) {
+    const rt_region& r = field->regions[i];
+    if (!std::isfinite(r.a) || !std::isfinite(r.b) || !std::isfinite(r.dn))
+      FAIL(RT_ERR_INVALID_ARG, "region %d: non-finite coefficient", i);
+    if (r.dn != 0.0 && !(std::isfinite(r.z0) && r.z0 != 0.0))
+      FAIL(RT_ERR_INVALID_ARG, "region %d: z0 must be finite and non-zero when dn != 0", i);
+    if (std::isnan(r.z_top) || std::isnan(r.z_bot) || !(r.z_top <= r.z_bot))
+      FAIL(RT_ERR_INVALID_ARG, "region %d: need z_top <= z_bot", i);
+  }
+  if (field_uses_grid(field)) {
+    const rt_grid& g = field->grid;
+    if (!g.n) FAIL(RT_ERR_INVALID_ARG, "grid: null data pointer");
+    if (g.nx < 2 || g.ny < 2 || g.nz < 2) FAIL(RT_ERR_INVALID_ARG, "grid: dims must be >= 2");
+    if ((double)g.nx * g.ny * g.nz > 4.0e9) FAIL(RT_ERR_UNSUPPORTED, "grid: too many nodes");
+    for (int a = 0; a < 3; ++a) {
+      if (!(g.spacing[a] > 0.0) || !std::isfinite(g.spacing[a]))
+        FAIL(RT_ERR_INVALID_ARG, "grid: spacing must be > 0");
+      if (!std::isfinite(g.origin[a])) FAIL(RT_ERR_INVALID_ARG, "grid: non-finite origin");
+    }
+  }
+  if (bnd->n_planes < 0 || bnd->n_planes > RT_MAX_PLANES)
+    FAIL(RT_ERR_INVALID_ARG, "n_planes must be 0..%d", RT_MAX_PLANES);
+  if (bnd->n_planes > 0 && !bnd->planes) FAIL(RT_ERR_INVALID_ARG, "null plane array");
+  for (int k = 0; k < bnd->n_planes; ++k) {
+    const rt_plane& p = bnd->planes[k];
+    if (!finite3(p.point) || !finite3(p.normal))
+      FAIL(RT_ERR_INVALID_ARG, "plane %d: non-finite point or normal", k);
+    const double l2 = p.normal[0] * p.normal[0] + p.normal[1] * p.normal[1] +
+                      p.normal[2] * p.normal[2];
+    if (!(l2 > 0.0)) FAIL(RT_ERR_INVALID_ARG, "plane %d: zero normal", k);
+    if (p.kind != RT_PLANE_FRESNEL && p.kind != RT_PLANE_ABSORB)
+      FAIL(RT_ERR_INVALID_ARG, "plane %d: unknown kind %d", k, p.kind);
+    if (p.region_pos < 0 || p.region_pos >= field->n_regions || p.region_neg < 0 ||
+        p.region_neg >= field->n_regions)
+      FAIL(RT_ERR_INVALID_ARG, "plane %d: region index out of range", k);
+  }
+  if (bnd->has_box) {
+    if (!finite3(bnd->box_lo) || !finite3(bnd->box_hi))
+      FAIL(RT_ERR_INVALID_ARG, "box: non-finite bounds");
+    for (int a = 0; a < 3; ++a)
+      if (!(bnd->box_lo[a] < bnd->box_hi[a])) FAIL(RT_ERR_INVALID_ARG, "box: need lo < hi");
+  }
+  if (src->n < 0 || (src->n > 0 && !src->xyz)) FAIL(RT_ERR_INVALID_ARG, "bad sources");
+  if (dirs->n < 0) FAIL(RT_ERR_INVALID_ARG, "negative ray count");
+  if (dirs->n > 0 && (!dirs->xyz || !dirs->src || src->n < 1))
+    FAIL(RT_ERR_INVALID_ARG, "rays need direction and source arrays and >= 1 source");
+  if (dirs->n > (int64_t)0x7fffffff) FAIL(RT_ERR_UNSUPPORTED, "more than 2^31-1 rays");
+  if (!(tol > 0.0) || !std::isfinite(tol)) FAIL(RT_ERR_INVALID_ARG, "tol must be > 0");
+  if (!(L->h_min > 0.0) || !(L->h_min <= L->h_max) || !std::isfinite(L->h_max))
+    FAIL(RT_ERR_INVALID_ARG, "need 0 < h_min <= h_max");
+  if (!(L->h_init >= 0.0) || !std::isfinite(L->h_init))
+    FAIL(RT_ERR_INVALID_ARG, "h_init must be >= 0");
+  if (!(L->s_max > 0.0) || !std::isfinite(L->s_max)) FAIL(RT_ERR_INVALID_ARG, "s_max must be > 0");
+  if (!(L->t_max >= 0.0) || !std::isfinite(L->t_max)) FAIL(RT_ERR_INVALID_ARG, "t_max must be >= 0");
+  if (!(L->amp_min >= 0.0) || !std::isfinite(L->amp_min))
+    FAIL(RT_ERR_INVALID_ARG, "amp_min must be >= 0");
+  if (L->max_generations < 1) FAIL(RT_ERR_INVALID_ARG, "max_generations must be >= 1");
+  if (L->max_generations > RT_MAX_GENERATIONS)
+    FAIL(RT_ERR_UNSUPPORTED, "max_generations above %d", RT_MAX_GENERATIONS);
+  if (L->model != RT_MODEL_PAPER && L->model != RT_MODEL_EXACT)
+    FAIL(RT_ERR_INVALID_ARG, "unknown model %d", L->model);
+  if (L->max_steps_per_ray < 1) FAIL(RT_ERR_INVALID_ARG, "max_steps_per_ray must be >= 1");
+  return RT_OK;
+}
+
+}  // namespace rt
+
+extern "C" {
+
+int32_t rt_abi_version(void) { return RT_ABI_VERSION; }
+
+rt_status rt_validate(const rt_field* field, const rt_boundaries* boundaries,
+                      const rt_sources* sources, const rt_directions* directions, double tol,
+                      const rt_step_limits* limits) {
+  return rt::validate(field, boundaries, sources, directions, tol, limits);
+}
+
+rt_status rt_workspace_bytes(const rt_field* field, size_t* bytes) {
+  if (!field || !bytes) {
+    rt::set_last_error("null argument");
+    return RT_ERR_INVALID_ARG;
+  }
+  size_t b = 4096;  // queue counters, padded
+  if (field->n_regions > 0 && field->regions && rt::field_uses_grid(field)) {
+    const rt_grid& g = field->grid;
+    if (g.nx < 2 || g.ny < 2 || g.nz < 2) {
+      rt::set_last_error("grid: dims must be >= 2");
+      return RT_ERR_INVALID_ARG;
+    }
+    b += (size_t)g.nx * g.ny * g.nz * 16;
+  }
+  *bytes = b;
+  return RT_OK;
+}
+
+rt_status rt_collect(const rt_stats* s, int64_t capacity) {
+  if (!s) {
+    rt::set_last_error("null stats");
+    return RT_ERR_INVALID_ARG;
+  }
+  if (s->sched_errors > 0) {
+    rt::set_last_error("scheduler: %lld queue waits timed out", (long long)s->sched_errors);
+    return RT_ERR_DEVICE;
+  }
+  if (s->invalid > 0) {
+    rt::set_last_error("%lld input rays invalid (status RT_ST_INVALID)", (long long)s->invalid);
+    return RT_ERR_INVALID_ARG;
+  }
+  if (s->needed > capacity) {
+    rt::set_last_error("record capacity %lld < needed %lld", (long long)capacity,
+                       (long long)s->needed);
+    return RT_ERR_CAPACITY;
+  }
+  return RT_OK;
+}
+
+const char* rt_last_error(void) { return rt::g_err; }
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Launch parameters shared by the host launcher and the kernels.  Passed to
+// the kernels by value (kernel-argument segment), so every field is plain data.
+#pragma once
+#include <stdint.h>
+
+#include "radiotrace.h"
+
+namespace rt {
+
+// user planes, then 6 box faces, then the travel-time pseudo-boundary
+constexpr int kMaxBnd = RT_MAX_PLANES + 6 + 1;
+enum BndKind : int32_t { B_FRESNEL = 0, B_ABSORB = 1, B_BOX = 2, B_TIME = 3 };
+
+// n(z) = a + b z - dn exp(-z / z0); exp is skipped when dn == 0
+struct KRegion {
+  double a, b, dn, inv_z0, dn_inv_z0;
+  double z_top, z_bot;  // launch-region lookup: z_top <= z < z_bot
+  int32_t use_grid, pad;
+};
+
+// g(r) = r . nrm - d  (unit normal); positive on the +normal side
+struct KBnd {
+  double nrm[3];
+  double d;
+  int32_t kind, reg_pos, reg_neg, pad;
+};
+
+struct Pool {
+  double *x, *y, *z, *ux, *uy, *uz, *s, *t;
+  double *as_re, *as_im, *ap_re, *ap_im, *h;
+  uint64_t *key, *parent;
+  int32_t *gen, *status, *n_acc, *n_rej, *n_ev, *region;
+  uint32_t* side;
+};
+
+struct QueueCounters {
+  uint32_t head;  // next slot to hand out
+  uint32_t tail;  // slots written or reserved (primaries + spawned)
+};
+
+struct KParams {
+  KRegion reg[RT_MAX_REGIONS];
+  KBnd bnd[kMaxBnd];
+  int32_t n_regions, n_bnd;
+  int32_t model, max_gen;
+  // grid: float4 nodes (n, Dx, Dy, Dz) with grad n = D / (2 spacing)
+  const void* nodes;
+  int32_t gnx, gny, gnz, refill;
+  double gorg[3], ginv[3], gmax[3], ghalf[3];
+  // limits
+  double tol, h_min, h_max, h_init, s_max, t_max, amp_min;
+  int64_t max_steps;
+  // record pool (= caller's outputs)
+  Pool pool;
+  int64_t capacity, n_primary;
+  QueueCounters* q;
+  rt_stats* stats;
+};
+
+// Host helpers shared by the launcher (rt_launch.hip) and rt_host.cpp.
+void set_last_error(const char* fmt, ...);
+rt_status validate(const rt_field* field, const rt_boundaries* boundaries,
+                   const rt_sources* sources, const rt_directions* directions,
+                   double tol, const rt_step_limits* limits);
+bool field_uses_grid(const rt_field* field);
+
+}  // namespace rt

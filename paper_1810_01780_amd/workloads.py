@@ -225,8 +225,10 @@ def gridded(rays_per_source: int = 16384, n_sources: int = 256,
     prof = FIRN["a"] - FIRN["dn"] * np.exp(-z / FIRN["z0"])
     grf = gaussian_random_field(rng, (nz, ny, nx), spacing, 1e-3, 50.0)
     n = (prof[:, None, None] + grf).astype(np.float32)
-    xs = rng.uniform(-500.0, 500.0, size=(n_sources, 2))
-    depths = rng.uniform(20.0, 1200.0, size=n_sources)
+    # sources at x, y within +-500 m (or 40 % of a smaller grid), depth 20-1200 m
+    half = min(500.0, 0.4 * min(-ox, -oy))
+    xs = rng.uniform(-half, half, size=(n_sources, 2))
+    depths = rng.uniform(20.0, min(1200.0, 0.9 * (nz - 1) * spacing), size=n_sources)
     sources = np.concatenate([xs, depths[:, None]], axis=1)
     dirs = isotropic(rng, n_sources * rays_per_source)
     ray_src = np.repeat(np.arange(n_sources, dtype=np.int32), rays_per_source)
@@ -241,8 +243,35 @@ def gridded(rays_per_source: int = 16384, n_sources: int = 256,
                  grid=Grid(n=n, origin=(ox, oy, 0.0), spacing=(spacing,) * 3))
 
 
+def paper_example(n_rays: int = 512, generations: int = 4,
+                  model: int = MODEL_PAPER) -> Scene:
+    """The worked example of the paper (section 2, Fig. 1).
+
+    Air above z = 0; a top layer of constant n = 1.5 from 0 to 10 m depth;
+    below it the profile 1.788 - 0.463 exp(-z/71.4 m).  Rays leave a point at
+    240 m depth in all directions of the x-z plane; they end after 5 us of
+    travel time, or when their amplitude falls below 0.05 of the initial one.
+    Both interfaces reflect and cast refracted secondaries.
+    """
+    th = (np.arange(n_rays, dtype=np.float64) + 0.5) * (2.0 * np.pi / n_rays)
+    dirs = np.stack([np.sin(th), np.zeros_like(th), -np.cos(th)], axis=1)
+    regions = [air_region(),
+               Region(a=1.5, z_top=0.0, z_bot=10.0),
+               Region(**PAPER_FIRN, z_top=10.0, z_bot=np.inf)]
+    planes = [surface_plane(ice=1, air=0),
+              Plane(point=(0.0, 0.0, 10.0), normal=(0.0, 0.0, 1.0),
+                    region_pos=2, region_neg=1)]
+    return Scene(name="paper_example", regions=regions, planes=planes,
+                 sources=np.array([[0.0, 0.0, 240.0]]),
+                 ray_src=np.zeros(n_rays, dtype=np.int32), dirs=dirs,
+                 limits=Limits(tol=1e-6, h_min=1e-3, h_max=10.0, s_max=1e4,
+                               t_max=5e-6, amp_min=0.05,
+                               max_generations=generations, model=model))
+
+
 WORKLOADS = {
     "fan1024": point_source_fan,
     "twolayer": two_layer,
     "grid256": gridded,
+    "paper_example": paper_example,
 }

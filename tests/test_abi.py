@@ -1,0 +1,156 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry
+point, validates descriptors on the host and maps statistics to statuses."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1810_01780_amd import binding as B
+from paper_1810_01780_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.lib()
+    names = declared_functions()
+    assert set(names) >= {"rt_abi_version", "rt_validate", "rt_workspace_bytes",
+                          "raytrace_launch", "rt_collect", "rt_last_error"}
+    for n in names:
+        assert hasattr(lib, n), n
+    assert B.rt_abi_version() == 1
+
+
+def test_struct_layouts_match_header():
+    # sizes follow from the header's field lists on x86-64
+    assert C.sizeof(B.rt_region) == 56
+    assert C.sizeof(B.rt_plane) == 64
+    assert C.sizeof(B.rt_step_limits) == 64
+    assert C.sizeof(B.rt_stats) == 8 * len(B.STAT_FIELDS)
+    assert C.sizeof(B.rt_outputs) == 8 * (len(B.RECORD_FIELDS) + 2)
+
+
+def _descs(scene=None, **lim):
+    scene = scene or W.point_source_fan(n_rays=8)
+    d = B.HostDescriptors(scene)
+    # fake (never dereferenced) device pointers: validation is host-only
+    d.sources.xyz = 0x1000
+    d.dirs.xyz = 0x2000
+    d.dirs.src = 0x3000
+    for k, v in lim.items():
+        setattr(d.limits, k, v)
+    return d
+
+
+def _validate(d, tol=None):
+    return B.rt_validate(d.field, d.bnd, d.sources, d.dirs, d.tol if tol is None else tol,
+                         d.limits)
+
+
+def test_validate_accepts_workloads():
+    for sc in (W.point_source_fan(n_rays=8), W.two_layer(rays_per_source=1)):
+        assert _validate(_descs(sc)) == B.RT_OK
+
+
+@pytest.mark.parametrize("change,code", [
+    (dict(h_min=0.0), B.RT_ERR_INVALID_ARG),
+    (dict(h_min=20.0), B.RT_ERR_INVALID_ARG),          # h_min > h_max
+    (dict(s_max=0.0), B.RT_ERR_INVALID_ARG),
+    (dict(t_max=-1.0), B.RT_ERR_INVALID_ARG),
+    (dict(amp_min=-0.1), B.RT_ERR_INVALID_ARG),
+    (dict(max_generations=0), B.RT_ERR_INVALID_ARG),
+    (dict(max_generations=5), B.RT_ERR_UNSUPPORTED),
+    (dict(model=7), B.RT_ERR_INVALID_ARG),
+    (dict(max_steps_per_ray=0), B.RT_ERR_INVALID_ARG),
+])
+def test_validate_rejects_bad_limits(change, code):
+    d = _descs(**change)
+    assert _validate(d) == code
+    assert B.rt_last_error()
+
+
+def test_validate_rejects_bad_descriptors():
+    d = _descs()
+    assert _validate(d, tol=0.0) == B.RT_ERR_INVALID_ARG
+    assert _validate(d, tol=float("nan")) == B.RT_ERR_INVALID_ARG
+    d = _descs()
+    d.bnd.planes[0].normal = (C.c_double * 3)(0.0, 0.0, 0.0)
+    assert _validate(d) == B.RT_ERR_INVALID_ARG and "normal" in B.rt_last_error()
+    d = _descs()
+    d.bnd.planes[0].region_pos = 9
+    assert _validate(d) == B.RT_ERR_INVALID_ARG
+    d = _descs()
+    d.bnd.planes[0].kind = 5
+    assert _validate(d) == B.RT_ERR_INVALID_ARG
+    d = _descs()
+    d.bnd.n_planes = B.RT_MAX_PLANES + 1
+    assert _validate(d) == B.RT_ERR_INVALID_ARG
+    d = _descs()
+    d.field.n_regions = 0
+    assert _validate(d) == B.RT_ERR_INVALID_ARG
+    d = _descs()
+    d.bnd.box_lo = (C.c_double * 3)(0.0, 0.0, 5.0)
+    d.bnd.box_hi = (C.c_double * 3)(1.0, 1.0, 5.0)
+    assert _validate(d) == B.RT_ERR_INVALID_ARG
+    d = _descs()
+    d.dirs.xyz = None
+    assert _validate(d) == B.RT_ERR_INVALID_ARG
+    d = _descs()
+    d.dirs.n = 0          # an empty launch is valid
+    assert _validate(d) == B.RT_OK
+
+
+def test_validate_grid_descriptor():
+    sc = W.gridded(rays_per_source=1, n_sources=2, nx=4, ny=4, nz=4)
+    d = _descs(sc)
+    assert _validate(d) == B.RT_ERR_INVALID_ARG  # grid data pointer still NULL
+    d.field.grid.n = 0x4000
+    assert _validate(d) == B.RT_OK
+    d.field.grid.nz = 1
+    assert _validate(d) == B.RT_ERR_INVALID_ARG
+    d.field.grid.nz = 4
+    d.field.grid.spacing = (C.c_double * 3)(10.0, 0.0, 10.0)
+    assert _validate(d) == B.RT_ERR_INVALID_ARG
+
+
+def test_workspace_bytes():
+    d = _descs()
+    assert B.rt_workspace_bytes(d.field) == 4096
+    sc = W.gridded(rays_per_source=1, n_sources=2, nx=4, ny=5, nz=6)
+    d = _descs(sc)
+    assert B.rt_workspace_bytes(d.field) == 4096 + 4 * 5 * 6 * 16
+
+
+def test_collect_maps_statistics():
+    s = B.rt_stats()
+    s.needed = 10
+    assert B.rt_collect(s, 10) == B.RT_OK
+    assert B.rt_collect(s, 9) == B.RT_ERR_CAPACITY
+    s.invalid = 1
+    assert B.rt_collect(s, 10) == B.RT_ERR_INVALID_ARG
+    s.sched_errors = 1
+    assert B.rt_collect(s, 10) == B.RT_ERR_DEVICE
+    s2 = B.rt_stats()
+    s2.nonfinite = 3          # per-ray status, not a launch failure
+    assert B.rt_collect(s2, 0) == B.RT_OK
+
+
+def test_launch_validates_before_touching_the_device():
+    d = _descs(h_min=-1.0)
+    out = B.rt_outputs()
+    st = B.raytrace_launch(d.field, d.bnd, d.sources, d.dirs, d.tol, d.limits, out, 0, 0, 0)
+    assert st == B.RT_ERR_INVALID_ARG
+    d = _descs()
+    st = B.raytrace_launch(d.field, d.bnd, d.sources, d.dirs, d.tol, d.limits, out, 0, 0, 0)
+    assert st == B.RT_ERR_INVALID_ARG and "null" in B.rt_last_error()
