@@ -57,6 +57,62 @@ __device__ __forceinline__ double e_sum(const double (&k)[6]) {
   return fma(kE6, k[5], fma(kE5, k[4], fma(kE4, k[3], fma(kE3, k[2], kE1 * k[0]))));
 }
 
+// ---------------------------------------------------------------------------
+// FP64 helpers: hardware estimates refined by Newton steps to within an ulp or
+// two of the correctly rounded result.
+
+// 1/x for finite non-zero x.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// 1/sqrt(x) for finite x > 0.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  double e = fma(-hx * r, r, 0.5);
+  r = fma(r, e, r);
+  e = fma(-hx * r, r, 0.5);
+  return fma(r, e, r);
+}
+
+// x^(-1/K) for x > 0: FP32 log2/exp2 seed, then two Newton steps on
+// y^-K = x, i.e. y <- y ((K + 1) - x y^K) / K.  Values beyond the FP32 range
+// give 0 (the callers clamp the resulting step).
+template <int K>
+__device__ __forceinline__ double pow_neg_inv(double x) {
+  const float l = __builtin_amdgcn_logf((float)x);
+  double y = (double)__builtin_amdgcn_exp2f(l * (-1.0f / K));
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double y2 = y * y;
+    const double yk = K == 4 ? y2 * y2 : y2 * y2 * y;
+    y = y * fma(-x, yk, (double)(K + 1)) * (1.0 / K);
+  }
+  return y;
+}
+
+// e^x for |x| <= 0.25: Taylor polynomial to degree 11 (truncation below
+// 2^-52 relative), Horner form.
+__device__ __forceinline__ double exp_small(double x) {
+  double p = 1.0 / 39916800.0;
+  p = fma(p, x, 1.0 / 3628800.0);
+  p = fma(p, x, 1.0 / 362880.0);
+  p = fma(p, x, 1.0 / 40320.0);
+  p = fma(p, x, 1.0 / 5040.0);
+  p = fma(p, x, 1.0 / 720.0);
+  p = fma(p, x, 1.0 / 120.0);
+  p = fma(p, x, 1.0 / 24.0);
+  p = fma(p, x, 1.0 / 6.0);
+  p = fma(p, x, 0.5);
+  p = fma(p, x, 1.0);
+  return fma(p, x, 1.0);
+}
+
 // Medium of one ray, kept in registers: n(z) = a + b z - dn exp(-z/z0).
 struct Medium {
   double a, b, dn, inv_z0, dn_inv_z0;
@@ -71,6 +127,21 @@ __device__ __forceinline__ Medium medium_of(const KParams& P, int r) {
 __device__ __forceinline__ void strat_field(const Medium& M, double z, double& n, double& gz) {
   double e = 0.0;
   if (M.dn != 0.0) e = exp(-z * M.inv_z0);
+  n = fma(M.b, z, M.a) - M.dn * e;
+  gz = fma(M.dn_inv_z0, e, M.b);
+}
+
+// Same at a stage point z = z0 + dz of a step starting at z0, where
+// E0 = exp(-z0/z0_medium): exp(-z/z0) = E0 exp(-dz/z0), and the second factor
+// is a short polynomial because a step moves at most a fraction of z0.
+__device__ __forceinline__ void strat_field_rel(const Medium& M, double z0, double dz, double E0,
+                                                double& n, double& gz) {
+  const double z = z0 + dz;
+  double e = 0.0;
+  if (M.dn != 0.0) {
+    const double x = -dz * M.inv_z0;
+    e = fabs(x) <= 0.25 ? E0 * exp_small(x) : exp(-z * M.inv_z0);
+  }
   n = fma(M.b, z, M.a) - M.dn * e;
   gz = fma(M.dn_inv_z0, e, M.b);
 }
@@ -123,23 +194,33 @@ __device__ __forceinline__ void grid_field(const KParams& P, double x, double y,
 //
 // Stratified media (grad n along z): in the paper model w_x, w_y are constant
 // within a step and only z, w_z, tau need stage values.
+template <int S>
+__device__ __forceinline__ double stage_inc(double h, const double (&k)[6]) {
+  double acc = ck_a(S, 0) * k[0];
+#pragma unroll
+  for (int j = 1; j < S; ++j) acc = fma(ck_a(S, j), k[j], acc);
+  return h * acc;
+}
+
 template <int MODEL>
 __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], double h,
-                                            double tol, double y5[7], double& err) {
+                                            double inv_tol, double y5[7], double& err) {
+  const double E0 = M.dn != 0.0 ? exp(-y[2] * M.inv_z0) : 0.0;
   if constexpr (MODEL == RT_MODEL_PAPER) {
+    // w = unit velocity, renormalised after every accepted step (|w| = 1)
     double kz[6], kw[6], kt[6];
 #pragma unroll
     for (int st = 0; st < 6; ++st) {
-      double zs = y[2], ws = y[5];
-      if (st == 1) { zs = stage_in<1>(y[2], h, kz); ws = stage_in<1>(y[5], h, kw); }
-      if (st == 2) { zs = stage_in<2>(y[2], h, kz); ws = stage_in<2>(y[5], h, kw); }
-      if (st == 3) { zs = stage_in<3>(y[2], h, kz); ws = stage_in<3>(y[5], h, kw); }
-      if (st == 4) { zs = stage_in<4>(y[2], h, kz); ws = stage_in<4>(y[5], h, kw); }
-      if (st == 5) { zs = stage_in<5>(y[2], h, kz); ws = stage_in<5>(y[5], h, kw); }
+      double dz = 0.0, ws = y[5];
+      if (st == 1) { dz = stage_inc<1>(h, kz); ws = stage_in<1>(y[5], h, kw); }
+      if (st == 2) { dz = stage_inc<2>(h, kz); ws = stage_in<2>(y[5], h, kw); }
+      if (st == 3) { dz = stage_inc<3>(h, kz); ws = stage_in<3>(y[5], h, kw); }
+      if (st == 4) { dz = stage_inc<4>(h, kz); ws = stage_in<4>(y[5], h, kw); }
+      if (st == 5) { dz = stage_inc<5>(h, kz); ws = stage_in<5>(y[5], h, kw); }
       double n, gz;
-      strat_field(M, zs, n, gz);
+      strat_field_rel(M, y[2], dz, E0, n, gz);
       kz[st] = ws;
-      kw[st] = gz / n;
+      kw[st] = gz * rcp_nr(n);
       kt[st] = n * kInvC0;
     }
     y5[0] = fma(h, y[3], y[0]);
@@ -149,24 +230,24 @@ __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], 
     y5[4] = y[4];
     y5[5] = fma(h, b_sum(kw), y[5]);
     y5[6] = fma(h, b_sum(kt), y[6]);
-    double dz = h * e_sum(kz), dw = h * e_sum(kw);
-    double w0 = sqrt(fma(y[3], y[3], fma(y[4], y[4], y[5] * y[5])));
-    err = fmax(fabs(dz) / h, fabs(dw) / w0) / tol;
+    // max(|dr|/h, |dw|/|w0|) / tol with |w0| = 1
+    err = fmax(fabs(e_sum(kz)), fabs(h * e_sum(kw))) * inv_tol;
   } else {
+    // w = p = n dr/ds; p_x, p_y are constant in a stratified medium
     const double px = y[3], py = y[4];
     const double pxy2 = fma(px, px, py * py);
     double kx[6], ky[6], kz[6], kp[6], kt[6];
 #pragma unroll
     for (int st = 0; st < 6; ++st) {
-      double zs = y[2], ps = y[5];
-      if (st == 1) { zs = stage_in<1>(y[2], h, kz); ps = stage_in<1>(y[5], h, kp); }
-      if (st == 2) { zs = stage_in<2>(y[2], h, kz); ps = stage_in<2>(y[5], h, kp); }
-      if (st == 3) { zs = stage_in<3>(y[2], h, kz); ps = stage_in<3>(y[5], h, kp); }
-      if (st == 4) { zs = stage_in<4>(y[2], h, kz); ps = stage_in<4>(y[5], h, kp); }
-      if (st == 5) { zs = stage_in<5>(y[2], h, kz); ps = stage_in<5>(y[5], h, kp); }
+      double dz = 0.0, ps = y[5];
+      if (st == 1) { dz = stage_inc<1>(h, kz); ps = stage_in<1>(y[5], h, kp); }
+      if (st == 2) { dz = stage_inc<2>(h, kz); ps = stage_in<2>(y[5], h, kp); }
+      if (st == 3) { dz = stage_inc<3>(h, kz); ps = stage_in<3>(y[5], h, kp); }
+      if (st == 4) { dz = stage_inc<4>(h, kz); ps = stage_in<4>(y[5], h, kp); }
+      if (st == 5) { dz = stage_inc<5>(h, kz); ps = stage_in<5>(y[5], h, kp); }
       double n, gz;
-      strat_field(M, zs, n, gz);
-      double ip = 1.0 / sqrt(fma(ps, ps, pxy2));
+      strat_field_rel(M, y[2], dz, E0, n, gz);
+      const double ip = rsqrt_nr(fma(ps, ps, pxy2));
       kx[st] = px * ip;
       ky[st] = py * ip;
       kz[st] = ps * ip;
@@ -180,11 +261,10 @@ __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], 
     y5[4] = py;
     y5[5] = fma(h, b_sum(kp), y[5]);
     y5[6] = fma(h, b_sum(kt), y[6]);
-    double dx = h * e_sum(kx), dy = h * e_sum(ky), dz = h * e_sum(kz);
-    double dp = h * e_sum(kp);
-    double dr = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
-    double p0 = sqrt(fma(y[5], y[5], pxy2));
-    err = fmax(dr / h, fabs(dp) / p0) / tol;
+    const double ex = e_sum(kx), ey = e_sum(ky), ez = e_sum(kz);
+    const double dr_h = sqrt(fma(ex, ex, fma(ey, ey, ez * ez)));  // |dr| / h
+    const double dp = h * e_sum(kp);
+    err = fmax(dr_h, fabs(dp) * rsqrt_nr(fma(y[5], y[5], pxy2))) * inv_tol;
   }
 }
 
@@ -218,7 +298,7 @@ __device__ __forceinline__ void stage_vec(const double y[7], double h, const dou
 
 template <int MODEL>
 __device__ __forceinline__ void trial_3d(const KParams& P, const Medium& M, const double y[7],
-                                         double h, double tol, double y5[7], double& err) {
+                                         double h, double inv_tol, double y5[7], double& err) {
   double k[6][6];  // [component][stage] for r (0..2) and w (3..5)
   double kt[6];
 #pragma unroll
@@ -236,7 +316,7 @@ __device__ __forceinline__ void trial_3d(const KParams& P, const Medium& M, cons
     double n, g[3];
     field3<MODEL>(P, M, ys[0], ys[1], ys[2], n, g);
     if constexpr (MODEL == RT_MODEL_PAPER) {
-      double in = 1.0 / n;
+      const double in = rcp_nr(n);
       k[0][st] = ys[3];
       k[1][st] = ys[4];
       k[2][st] = ys[5];
@@ -244,7 +324,7 @@ __device__ __forceinline__ void trial_3d(const KParams& P, const Medium& M, cons
       k[4][st] = g[1] * in;
       k[5][st] = g[2] * in;
     } else {
-      double ip = 1.0 / sqrt(fma(ys[3], ys[3], fma(ys[4], ys[4], ys[5] * ys[5])));
+      const double ip = rsqrt_nr(fma(ys[3], ys[3], fma(ys[4], ys[4], ys[5] * ys[5])));
       k[0][st] = ys[3] * ip;
       k[1][st] = ys[4] * ip;
       k[2][st] = ys[5] * ip;
@@ -261,13 +341,14 @@ __device__ __forceinline__ void trial_3d(const KParams& P, const Medium& M, cons
 #pragma unroll
     for (int j = 0; j < 6; ++j) kc[j] = k[c][j];
     y5[c] = fma(h, b_sum(kc), y[c]);
-    d[c] = h * e_sum(kc);
+    d[c] = e_sum(kc);  // error vector / h
   }
   y5[6] = fma(h, b_sum(kt), y[6]);
-  double dr = sqrt(fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2])));
-  double dw = sqrt(fma(d[3], d[3], fma(d[4], d[4], d[5] * d[5])));
-  double w0 = sqrt(fma(y[3], y[3], fma(y[4], y[4], y[5] * y[5])));
-  err = fmax(dr / h, dw / w0) / tol;
+  // max(|dr|/h, |dw|/|w0|) / tol
+  const double dr_h = sqrt(fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2])));
+  const double dw_h = sqrt(fma(d[3], d[3], fma(d[4], d[4], d[5] * d[5])));
+  const double iw0 = rsqrt_nr(fma(y[3], y[3], fma(y[4], y[4], y[5] * y[5])));
+  err = fmax(dr_h, h * dw_h * iw0) * inv_tol;
 }
 
 // ---------------------------------------------------------------------------
@@ -354,6 +435,7 @@ __device__ __forceinline__ bool fresnel(double n1, double n2, double ci, double 
 struct Counters {
   uint32_t accepted, rejected, relocation, forced, events, spawned;
   uint32_t supp_gen, supp_amp, records, nonfinite, refills, sched_err;
+  uint32_t dropped;  // children beyond the record capacity
   int32_t max_gen;
 };
 
@@ -361,43 +443,23 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return __lanemask_lt();
 }
 
-// Reserve 'count' consecutive queue slots for the calling wave's active lanes
-// (one atomic per wave); returns this lane's slot.
-__device__ __forceinline__ uint32_t wave_append(uint32_t* tail) {
-  uint64_t m = __ballot(1);
-  int leader = __ffsll((unsigned long long)m) - 1;
-  uint32_t base = 0;
+// Reserve consecutive record slots for the calling wave's active lanes (one
+// atomic per wave); returns this lane's slot index.
+__device__ __forceinline__ uint64_t wave_append(uint64_t* tail) {
+  const uint64_t m = __ballot(1);
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  unsigned long long base = 0;
   if ((int)__lane_id() == leader)
-    base = __hip_atomic_fetch_add(tail, (uint32_t)__popcll(m), __ATOMIC_RELAXED,
+    base = __hip_atomic_fetch_add(tail, (uint64_t)__popcll(m), __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
   base = __shfl(base, leader);
-  return base + (uint32_t)__popcll(m & lanemask_lt());
+  return base + (uint64_t)__popcll(m & lanemask_lt());
 }
 
-// Claim up to 'want' queued slots for a wave (called by one lane).
-__device__ __forceinline__ void queue_claim(const KParams& P, uint32_t want, uint32_t& base,
-                                            uint32_t& got) {
-  uint32_t* head = &P.q->head;
-  uint32_t* tail = &P.q->tail;
-  const uint32_t cap = (uint32_t)P.capacity;
-  uint32_t hd = __hip_atomic_load(head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  base = 0;
-  got = 0;
-  // head only grows and is bounded by the capacity, so this loop ends
-  for (;;) {
-    uint32_t tl = __hip_atomic_load(tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    tl = min(tl, cap);
-    if (hd >= tl) return;
-    uint32_t take = min(want, tl - hd);
-    uint32_t expected = hd;
-    if (__hip_atomic_compare_exchange_strong(head, &expected, hd + take, __ATOMIC_RELAXED,
-                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-      base = hd;
-      got = take;
-      return;
-    }
-    hd = expected;
-  }
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -414,7 +476,7 @@ struct Ray {
 template <int MODEL, int FIELD>
 __device__ __forceinline__ void set_direction(const KParams& P, Ray& R, double ux, double uy,
                                               double uz) {
-  double il = 1.0 / sqrt(fma(ux, ux, fma(uy, uy, uz * uz)));
+  const double il = rsqrt_nr(fma(ux, ux, fma(uy, uy, uz * uz)));
   double m = il;
   if constexpr (MODEL == RT_MODEL_EXACT) {
     double n, g[3];
@@ -445,7 +507,7 @@ __device__ __forceinline__ void write_record(const KParams& P, const Ray& R, int
                                              Counters& C) {
   const Pool& Q = P.pool;
   const int i = R.slot;
-  double il = 1.0 / sqrt(fma(R.y[3], R.y[3], fma(R.y[4], R.y[4], R.y[5] * R.y[5])));
+  const double il = rsqrt_nr(fma(R.y[3], R.y[3], fma(R.y[4], R.y[4], R.y[5] * R.y[5])));
   Q.x[i] = R.y[0];
   Q.y[i] = R.y[1];
   Q.z[i] = R.y[2];
@@ -464,28 +526,10 @@ __device__ __forceinline__ void write_record(const KParams& P, const Ray& R, int
   C.records++;
 }
 
-// Load the ray of a claimed slot; false when the slot holds an invalid ray
-// (or the wait for a secondary timed out).
+// Load the queued ray of a slot into a lane.
 template <int MODEL, int FIELD>
-__device__ __forceinline__ bool load_ray(const KParams& P, int32_t slot, Ray& R, Counters& C) {
+__device__ __forceinline__ void load_ray(const KParams& P, int32_t slot, Ray& R, Counters& C) {
   const Pool& Q = P.pool;
-  int32_t st;
-  if (slot < P.n_primary) {
-    st = Q.status[slot];
-  } else {
-    // secondaries: the producer stores the payload, then releases the status
-    uint32_t spins = 0;
-    for (;;) {
-      st = __hip_atomic_load(&Q.status[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      if (st != RT_ST_EMPTY) break;
-      if (++spins > (1u << 24)) {
-        C.sched_err++;
-        return false;
-      }
-      __builtin_amdgcn_s_sleep(2);
-    }
-  }
-  if (st != RT_ST_QUEUED) return false;
   R.slot = slot;
   R.y[0] = Q.x[slot];
   R.y[1] = Q.y[slot];
@@ -500,7 +544,6 @@ __device__ __forceinline__ bool load_ray(const KParams& P, int32_t slot, Ray& R,
   R.M = medium_of(P, R.region);
   set_direction<MODEL, FIELD>(P, R, Q.ux[slot], Q.uy[slot], Q.uz[slot]);
   C.max_gen = max(C.max_gen, R.gen);
-  return true;
 }
 
 // Checks made before every normal trial step; returns a final status or 0.
@@ -515,9 +558,9 @@ template <int MODEL, int FIELD>
 __device__ __forceinline__ void trial(const KParams& P, const Ray& R, double h, double y5[7],
                                       double& err) {
   if constexpr (FIELD == 1) {
-    trial_3d<MODEL>(P, R.M, R.y, h, P.tol, y5, err);
+    trial_3d<MODEL>(P, R.M, R.y, h, P.inv_tol, y5, err);
   } else {
-    trial_strat<MODEL>(R.M, R.y, h, P.tol, y5, err);
+    trial_strat<MODEL>(R.M, R.y, h, P.inv_tol, y5, err);
   }
 }
 
@@ -548,7 +591,7 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
 
   const double sg = ((R.side >> k) & 1u) ? 1.0 : -1.0;
   const double nin[3] = {sg * B.nrm[0], sg * B.nrm[1], sg * B.nrm[2]};
-  double il = 1.0 / sqrt(fma(R.y[3], R.y[3], fma(R.y[4], R.y[4], R.y[5] * R.y[5])));
+  const double il = rsqrt_nr(fma(R.y[3], R.y[3], fma(R.y[4], R.y[4], R.y[5] * R.y[5])));
   const double u[3] = {R.y[3] * il, R.y[4] * il, R.y[5] * il};
   double ci = -fma(u[2], nin[2], fma(u[1], nin[1], u[0] * nin[0]));
   ci = fmax(ci, 0.0);
@@ -574,8 +617,10 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
         C.supp_amp++;
       } else {
         C.spawned++;
-        const uint32_t c = wave_append(&P.q->tail);
-        if (c < (uint32_t)P.capacity) {
+        const uint64_t c = wave_append(&P.q->tail);
+        if (c >= (uint64_t)P.capacity) {
+          C.dropped++;  // no record slot: counted as finished, reported via stats.needed
+        } else {
           const double eta = n1 / n2;
           const double f = eta * ci - ct;
           const uint64_t key = Q.key[i];
@@ -656,38 +701,87 @@ __global__ void __launch_bounds__(256) trace_kernel(KParams Parg) {
   double h_next = 0.0, hp = 0.0;
   double la = 0.0, lGa = 0.0, lb = 0.0, lGb = 0.0, lc = 0.0;
   int lk = 0, llast = 0, lit = 0, lpass = 0;
-  int backoff = 0;
+
+  // Scheduler.  Record slots are handed out as tickets in slot order, one
+  // fetch_add per wave.  Slots below n_primary hold primaries written before
+  // the kernel started; later slots are filled by spawns and published by a
+  // release store of their status, so a lane may wait on its ticket for a
+  // while.  Rays that end are counted per lane and added to q->finished when
+  // the wave has nothing to step; the launch is done when finished == tail
+  // (tail counts every slot ever reserved), since only running rays spawn.
+  int32_t ticket = -1;     // -1: none, -2: tickets exhausted, else slot waited on
+  uint32_t fin_local = 0;  // rays finished here, not yet added to q->finished
+  uint32_t sleeps = 0;
+  const Pool& Q = P.pool;
 
   for (;;) {
-    // ---- refill idle lanes from the queue (wave-uniform) ----
-    const uint64_t idle = __ballot(R.slot < 0);
+    // ---- tickets for idle lanes ----
+    const bool lane_idle = R.slot < 0 && ticket == -1;
+    const uint64_t idle = __ballot(lane_idle);
+    const uint64_t busy = __ballot(R.slot >= 0);
     const int nidle = __popcll(idle);
-    if (nidle == 64 || (nidle >= P.refill && backoff == 0)) {
-      uint32_t base = 0, got = 0;
-      if (lane == 0) {
-        queue_claim(P, (uint32_t)nidle, base, got);
+    if (nidle > 0 && (nidle >= P.refill || busy == 0)) {
+      const int leader = __ffsll((unsigned long long)idle) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) {
+        base = __hip_atomic_fetch_add(&P.q->head, (uint64_t)nidle, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
         C.refills++;
       }
-      base = __shfl(base, 0);
-      got = __shfl(got, 0);
-      if (got == 0) {
-        if (nidle == 64) break;
-        backoff = 16;
-      } else {
-        const uint32_t rank = (uint32_t)__popcll(idle & lanemask_lt());
-        if (R.slot < 0 && rank < got) {
-          if (load_ray<MODEL, FIELD>(P, (int32_t)(base + rank), R, C)) {
-            mode = 0;
-            const int32_t st = pretrial_status(P, R);
-            if (st) {
-              write_record(P, R, st, C);
-              R.slot = -1;
-            }
-          }
-        }
+      base = __shfl(base, leader);
+      if (lane_idle) {
+        const uint64_t t = base + (uint64_t)__popcll(idle & lanemask_lt());
+        ticket = t < (uint64_t)P.capacity ? (int32_t)t : -2;
       }
-    } else if (backoff > 0) {
-      --backoff;
+    }
+    // ---- waiting lanes take their slot once it holds a ray ----
+    if (R.slot < 0 && ticket >= 0) {
+      int32_t st;
+      if (ticket < P.n_primary) {
+        st = Q.status[ticket];
+      } else {
+        st = __hip_atomic_load(&Q.status[ticket], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (st != RT_ST_EMPTY) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      if (st == RT_ST_QUEUED) {
+        load_ray<MODEL, FIELD>(P, ticket, R, C);
+        mode = 0;
+        const int32_t fst = pretrial_status(P, R);
+        if (fst) {
+          write_record(P, R, fst, C);
+          R.slot = -1;
+          ++fin_local;
+        }
+        ticket = -1;
+      } else if (st != RT_ST_EMPTY) {
+        ++fin_local;  // an invalid primary: its record is already final
+        ticket = -1;
+      }
+    }
+    if (__ballot(R.slot >= 0) == 0) {
+      // nothing to step: publish finished counts, stop once every ray is done
+      const unsigned long long f = wave_sum(fin_local + C.dropped);
+      fin_local = 0;
+      C.dropped = 0;
+      if (lane == 0 && f)
+        __hip_atomic_fetch_add(&P.q->finished, (uint64_t)f, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      if (__ballot(ticket == -2) == ~0ull) break;  // this wave can get no more work
+      unsigned long long done = 0;
+      if (lane == 0) {
+        const uint64_t fin_g =
+            __hip_atomic_load(&P.q->finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t tail_g =
+            __hip_atomic_load(&P.q->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        done = fin_g == tail_g;
+      }
+      if (__shfl(done, 0)) break;
+      if (++sleeps > (1u << 26)) {  // guard: never expected
+        C.sched_err++;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(4);
+      continue;
     }
     if (R.slot < 0) continue;
 
@@ -715,14 +809,14 @@ __global__ void __launch_bounds__(256) trace_kernel(KParams Parg) {
       } else if (!(err <= 1.0) && !(ht <= P.h_min)) {
         R.n_rej++;
         C.rejected++;
-        R.h = clamp_h(P, ht * fmax(kShrinkMin, kSafety * pow(err, -0.25)));
+        R.h = clamp_h(P, ht * fmax(kShrinkMin, kSafety * pow_neg_inv<4>(err)));
       } else {
         R.n_acc++;
         C.accepted++;
         if (err > 1.0) C.forced++;
-        h_next = clamp_h(P, ht * (err < kErrCon ? kGrowMax : kSafety * pow(err, -0.2)));
+        h_next = clamp_h(P, ht * (err < kErrCon ? kGrowMax : kSafety * pow_neg_inv<5>(err)));
         if constexpr (MODEL == RT_MODEL_PAPER) {
-          const double il = 1.0 / sqrt(fma(y5[3], y5[3], fma(y5[4], y5[4], y5[5] * y5[5])));
+          const double il = rsqrt_nr(fma(y5[3], y5[3], fma(y5[4], y5[4], y5[5] * y5[5])));
           y5[3] *= il;
           y5[4] *= il;
           y5[5] *= il;
@@ -818,6 +912,7 @@ __global__ void __launch_bounds__(256) trace_kernel(KParams Parg) {
       write_record(P, R, fin, C);
       R.slot = -1;
       mode = 0;
+      ++fin_local;
     }
   }
 
@@ -862,7 +957,8 @@ __global__ void reset_kernel(KParams P) {
   if (i < (int)(sizeof(rt_stats) / 8)) s64[i] = 0;
   if (i == 0) {
     P.q->head = 0;
-    P.q->tail = (uint32_t)P.n_primary;
+    P.q->tail = (uint64_t)P.n_primary;
+    P.q->finished = 0;
   }
 }
 
@@ -1089,6 +1185,7 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   P.max_gen = L->max_generations;
   P.refill = refill;
   P.tol = tol;
+  P.inv_tol = 1.0 / tol;
   P.h_min = L->h_min;
   P.h_max = L->h_max;
   P.h_init = L->h_init > 0.0 ? L->h_init : L->h_max;

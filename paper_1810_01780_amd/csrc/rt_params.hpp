@@ -34,8 +34,9 @@ struct Pool {
 };
 
 struct QueueCounters {
-  uint32_t head;  // next slot to hand out
-  uint32_t tail;  // slots written or reserved (primaries + spawned)
+  uint64_t head;      // next slot (ticket) to hand out
+  uint64_t tail;      // slots reserved so far (primaries + spawned)
+  uint64_t finished;  // rays finished (or dropped), added lazily per wave
 };
 
 struct KParams {
@@ -48,7 +49,7 @@ struct KParams {
   int32_t gnx, gny, gnz, refill;
   double gorg[3], ginv[3], gmax[3], ghalf[3];
   // limits
-  double tol, h_min, h_max, h_init, s_max, t_max, amp_min;
+  double tol, inv_tol, h_min, h_max, h_init, s_max, t_max, amp_min;
   int64_t max_steps;
   // record pool (= caller's outputs)
   Pool pool;

