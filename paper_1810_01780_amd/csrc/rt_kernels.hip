@@ -119,8 +119,15 @@ struct Medium {
   int use_grid;
 };
 
+// Media and boundary tables indexed per lane (by a ray's medium or by the
+// boundary it is searching): copied into LDS at kernel start.  Loops over all
+// boundaries use the uniform copy in the kernel arguments instead.
+__shared__ KRegion s_reg[RT_MAX_REGIONS];
+__shared__ KBnd s_bnd[kMaxBnd];
+
 __device__ __forceinline__ Medium medium_of(const KParams& P, int r) {
-  const KRegion& R = P.reg[r];
+  (void)P;
+  const KRegion& R = s_reg[r];
   return Medium{R.a, R.b, R.dn, R.inv_z0, R.dn_inv_z0, R.use_grid};
 }
 
@@ -208,7 +215,8 @@ __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], 
   const double E0 = M.dn != 0.0 ? exp(-y[2] * M.inv_z0) : 0.0;
   if constexpr (MODEL == RT_MODEL_PAPER) {
     // w = unit velocity, renormalised after every accepted step (|w| = 1)
-    double kz[6], kw[6], kt[6];
+    double kz[6], kw[6];
+    double tsum = 0.0;  // sum_j b_j n_j / c0
 #pragma unroll
     for (int st = 0; st < 6; ++st) {
       double dz = 0.0, ws = y[5];
@@ -221,7 +229,10 @@ __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], 
       strat_field_rel(M, y[2], dz, E0, n, gz);
       kz[st] = ws;
       kw[st] = gz * rcp_nr(n);
-      kt[st] = n * kInvC0;
+      if (st == 0) tsum = kB1 * n;
+      if (st == 2) tsum = fma(kB3, n, tsum);
+      if (st == 3) tsum = fma(kB4, n, tsum);
+      if (st == 5) tsum = fma(kB6, n, tsum);
     }
     y5[0] = fma(h, y[3], y[0]);
     y5[1] = fma(h, y[4], y[1]);
@@ -229,7 +240,7 @@ __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], 
     y5[3] = y[3];
     y5[4] = y[4];
     y5[5] = fma(h, b_sum(kw), y[5]);
-    y5[6] = fma(h, b_sum(kt), y[6]);
+    y5[6] = fma(h * kInvC0, tsum, y[6]);
     // max(|dr|/h, |dw|/|w0|) / tol with |w0| = 1
     err = fmax(fabs(e_sum(kz)), fabs(h * e_sum(kw))) * inv_tol;
   } else {
@@ -367,9 +378,8 @@ __device__ __forceinline__ double clamp_h(const KParams& P, double h) {
 }
 
 // Boundary function with the ray's side sign applied: > 0 before crossing.
-__device__ __forceinline__ double bnd_G(const KParams& P, int k, uint32_t side,
+__device__ __forceinline__ double bnd_G(const KParams& P, const KBnd& B, int k, uint32_t side,
                                         const double y[7]) {
-  const KBnd& B = P.bnd[k];
   if (B.kind == B_TIME) return (P.t_max - y[6]) * 299792458.0;
   double g = fma(y[2], B.nrm[2], fma(y[1], B.nrm[1], y[0] * B.nrm[0])) - B.d;
   return ((side >> k) & 1u) ? g : -g;
@@ -384,9 +394,9 @@ __device__ __forceinline__ int pick_crossing(const KParams& P, uint32_t side, co
   double best_sig = 0.0;
   for (int k = 0; k < P.n_bnd; ++k) {
     if (k == skip) continue;
-    double G1 = bnd_G(P, k, side, y1);
+    double G1 = bnd_G(P, P.bnd[k], k, side, y1);
     if (!(G1 <= 0.0)) continue;
-    double G0 = bnd_G(P, k, side, y0);
+    double G0 = bnd_G(P, P.bnd[k], k, side, y0);
     double sig = G0 <= 0.0 ? 0.0 : len * G0 / (G0 - G1);
     if (best < 0 || sig < best_sig) {
       best = k;
@@ -431,12 +441,25 @@ __device__ __forceinline__ bool fresnel(double n1, double n2, double ci, double 
   return true;
 }
 
-// Per-lane counters, summed per wave at the end of the kernel.
+// Per-wave statistics in LDS, indexed like the fields of rt_stats, plus
+// S_FIN: rays finished (or dropped for lack of a slot) that have not been
+// added to the queue's finished counter yet.  bump() adds the number of lanes
+// calling it (one LDS atomic by the first of them), so it may be used inside
+// divergent code.
+enum : int {
+  S_ACC = 0, S_REJ, S_RELOC, S_FORCED, S_EVENTS, S_SPAWNED, S_SUPP_GEN, S_SUPP_AMP,
+  S_RECORDS, S_NEEDED, S_NONFINITE, S_MAXGEN, S_INVALID, S_REFILLS, S_SCHED, S_FIN, S_COUNT
+};
 struct Counters {
-  uint32_t accepted, rejected, relocation, forced, events, spawned;
-  uint32_t supp_gen, supp_amp, records, nonfinite, refills, sched_err;
-  uint32_t dropped;  // children beyond the record capacity
-  int32_t max_gen;
+  unsigned long long* c;  // this wave's row
+  __device__ __forceinline__ void bump(int i) const {
+    const uint64_t m = __ballot(1);
+    if ((int)__lane_id() == __ffsll((unsigned long long)m) - 1)
+      atomicAdd(&c[i], (unsigned long long)__popcll(m));
+  }
+  __device__ __forceinline__ void max_gen(int g) const {
+    atomicMax(&c[S_MAXGEN], (unsigned long long)g);
+  }
 };
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
@@ -467,7 +490,6 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 struct Ray {
   double y[7];  // x, y, z, w (v or p), tau
   double s, h;
-  Medium M;
   int32_t slot, region, gen, n_acc, n_rej, n_ev;
   uint32_t side;
 };
@@ -481,9 +503,9 @@ __device__ __forceinline__ void set_direction(const KParams& P, Ray& R, double u
   if constexpr (MODEL == RT_MODEL_EXACT) {
     double n, g[3];
     if constexpr (FIELD == 1) {
-      field3<MODEL>(P, R.M, R.y[0], R.y[1], R.y[2], n, g);
+      field3<MODEL>(P, medium_of(P, R.region), R.y[0], R.y[1], R.y[2], n, g);
     } else {
-      strat_field(R.M, R.y[2], n, g[2]);
+      strat_field(medium_of(P, R.region), R.y[2], n, g[2]);
     }
     m = n * il;
   }
@@ -504,7 +526,7 @@ __device__ __forceinline__ double field_n(const KParams& P, const Medium& M, con
 }
 
 __device__ __forceinline__ void write_record(const KParams& P, const Ray& R, int32_t status,
-                                             Counters& C) {
+                                             const Counters& C) {
   const Pool& Q = P.pool;
   const int i = R.slot;
   const double il = rsqrt_nr(fma(R.y[3], R.y[3], fma(R.y[4], R.y[4], R.y[5] * R.y[5])));
@@ -523,12 +545,12 @@ __device__ __forceinline__ void write_record(const KParams& P, const Ray& R, int
   Q.region[i] = R.region;
   Q.side[i] = R.side;
   Q.status[i] = status;
-  C.records++;
+  C.bump(S_RECORDS);
 }
 
 // Load the queued ray of a slot into a lane.
 template <int MODEL, int FIELD>
-__device__ __forceinline__ void load_ray(const KParams& P, int32_t slot, Ray& R, Counters& C) {
+__device__ __forceinline__ void load_ray(const KParams& P, int32_t slot, Ray& R, const Counters& C) {
   const Pool& Q = P.pool;
   R.slot = slot;
   R.y[0] = Q.x[slot];
@@ -541,9 +563,8 @@ __device__ __forceinline__ void load_ray(const KParams& P, int32_t slot, Ray& R,
   R.region = Q.region[slot];
   R.side = Q.side[slot];
   R.n_acc = R.n_rej = R.n_ev = 0;
-  R.M = medium_of(P, R.region);
   set_direction<MODEL, FIELD>(P, R, Q.ux[slot], Q.uy[slot], Q.uz[slot]);
-  C.max_gen = max(C.max_gen, R.gen);
+  C.max_gen(R.gen);
 }
 
 // Checks made before every normal trial step; returns a final status or 0.
@@ -558,9 +579,9 @@ template <int MODEL, int FIELD>
 __device__ __forceinline__ void trial(const KParams& P, const Ray& R, double h, double y5[7],
                                       double& err) {
   if constexpr (FIELD == 1) {
-    trial_3d<MODEL>(P, R.M, R.y, h, P.inv_tol, y5, err);
+    trial_3d<MODEL>(P, medium_of(P, R.region), R.y, h, P.inv_tol, y5, err);
   } else {
-    trial_strat<MODEL>(R.M, R.y, h, P.inv_tol, y5, err);
+    trial_strat<MODEL>(medium_of(P, R.region), R.y, h, P.inv_tol, y5, err);
   }
 }
 
@@ -568,8 +589,8 @@ __device__ __forceinline__ void trial(const KParams& P, const Ray& R, double h, 
 // step); returns the final status of the ray or 0 when it continues.
 template <int MODEL, int FIELD>
 __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int k, double sig,
-                                                  double ys[7], double h_next, Counters& C) {
-  const KBnd& B = P.bnd[k];
+                                                  double ys[7], double h_next, const Counters& C) {
+  const KBnd& B = s_bnd[k];
   if (B.kind != B_TIME) {
     // snap onto the plane
     double g = fma(ys[2], B.nrm[2], fma(ys[1], B.nrm[1], ys[0] * B.nrm[0])) - B.d;
@@ -587,7 +608,7 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
   if (B.kind == B_ABSORB) return RT_ST_ABSORB;
   if (R.n_ev >= kMaxEvents) return RT_ST_STEPCAP;
   R.n_ev++;
-  C.events++;
+  C.bump(S_EVENTS);
 
   const double sg = ((R.side >> k) & 1u) ? 1.0 : -1.0;
   const double nin[3] = {sg * B.nrm[0], sg * B.nrm[1], sg * B.nrm[2]};
@@ -597,7 +618,7 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
   ci = fmax(ci, 0.0);
   const int reg_out = sg > 0.0 ? B.reg_neg : B.reg_pos;
   const Medium Mo = medium_of(P, reg_out);
-  const double n1 = field_n<MODEL, FIELD>(P, R.M, R.y);
+  const double n1 = field_n<MODEL, FIELD>(P, medium_of(P, R.region), R.y);
   const double n2 = field_n<MODEL, FIELD>(P, Mo, R.y);
   double rt[8], ct;
   const bool tir = fresnel(n1, n2, ci, rt, ct);
@@ -614,12 +635,12 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
       const double cp_im = ap_re * rt[7] + ap_im * rt[6];
       const double amax = fmax(hypot(cs_re, cs_im), hypot(cp_re, cp_im));
       if (P.amp_min > 0.0 && amax < P.amp_min) {
-        C.supp_amp++;
+        C.bump(S_SUPP_AMP);
       } else {
-        C.spawned++;
+        C.bump(S_SPAWNED);
         const uint64_t c = wave_append(&P.q->tail);
         if (c >= (uint64_t)P.capacity) {
-          C.dropped++;  // no record slot: counted as finished, reported via stats.needed
+          C.bump(S_FIN);  // no record slot: counted as finished, reported via stats.needed
         } else {
           const double eta = n1 / n2;
           const double f = eta * ci - ct;
@@ -650,7 +671,7 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
         }
       }
     } else {
-      C.supp_gen++;
+      C.bump(S_SUPP_GEN);
     }
   }
   // the parent continues as the reflected ray
@@ -672,20 +693,44 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
 
 // ---------------------------------------------------------------------------
 // Persistent trace kernel.
-template <int MODEL, int FIELD>
-__global__ void __launch_bounds__(256) trace_kernel(KParams Parg) {
-  // The parameters (boundary and medium tables, limits) are read throughout
-  // the step loop; one copy per block in LDS keeps those reads on-chip.
-  __shared__ KParams sP;
-  {
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(&Parg);
-    uint32_t* dst = reinterpret_cast<uint32_t*>(&sP);
-    for (int i = threadIdx.x; i < (int)(sizeof(KParams) / 4); i += blockDim.x) dst[i] = src[i];
-    __syncthreads();
+// Step-size factor of the controller: min(5, 0.9 err^(-1/5)) after an
+// accepted trial (exactly 5 below kErrCon), max(0.1, 0.9 err^(-1/4)) after a
+// rejected one.  One Newton-refined power serves both cases.
+__device__ __forceinline__ double step_factor(double err, bool accepted) {
+  if (accepted && err < kErrCon) return kGrowMax;
+  const float l = __builtin_amdgcn_logf((float)err);
+  const float k = accepted ? -0.2f : -0.25f;
+  double y = (double)__builtin_amdgcn_exp2f(l * k);
+  // Newton on y^-K = err: y <- y ((K + 1) - err y^K) / K
+  const double K = accepted ? 5.0 : 4.0, iK = accepted ? 0.2 : 0.25;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double y2 = y * y;
+    const double yk = accepted ? y2 * y2 * y : y2 * y2;
+    y = y * fma(-err, yk, K + 1.0) * iK;
   }
-  const KParams& P = sP;
+  const double f = kSafety * y;
+  return accepted ? f : fmax(kShrinkMin, f);
+}
+
+template <int MODEL, int FIELD>
+__global__ void __launch_bounds__(256) trace_kernel(KParams P) {
+  for (int i = threadIdx.x; i < P.n_regions; i += blockDim.x) s_reg[i] = P.reg[i];
+  for (int i = threadIdx.x; i < P.n_bnd; i += blockDim.x) s_bnd[i] = P.bnd[i];
   const int lane = (int)__lane_id();
-  Counters C = {};
+  const int tid = (int)threadIdx.x;
+  __shared__ unsigned long long s_cnt[4][S_COUNT];
+  const Counters C{s_cnt[tid / 64]};
+  if (lane < S_COUNT) C.c[lane] = 0;
+  // Crossing-search state of each lane, kept in LDS (one entry per thread,
+  // structure of arrays) so that it does not occupy registers in the step
+  // loop: bracket [a, b] with its function values, the full step length, the
+  // controller's proposal for the step after the event, the boundary being
+  // searched and (pass << 16 | iterations << 2 | last side + 1).
+  __shared__ double s_a[256], s_Ga[256], s_b[256], s_Gb[256], s_hp[256], s_hn[256];
+  __shared__ int32_t s_k[256], s_meta[256];
+  __syncthreads();
+
   Ray R;
   R.slot = -1;
   R.s = R.h = 0.0;
@@ -693,28 +738,32 @@ __global__ void __launch_bounds__(256) trace_kernel(KParams Parg) {
   R.side = 0;
 #pragma unroll
   for (int i = 0; i < 7; ++i) R.y[i] = 0.0;
-  R.M = Medium{0, 0, 0, 0, 0, 0};
-
-  // step / search state
-  int mode = 0;  // 0: normal step, 1: searching a crossing
-  int clipped = 0;
-  double h_next = 0.0, hp = 0.0;
-  double la = 0.0, lGa = 0.0, lb = 0.0, lGb = 0.0, lc = 0.0;
-  int lk = 0, llast = 0, lit = 0, lpass = 0;
+  int mode = 0;     // 0: normal step, 1: searching a crossing, 2: crossing located
+  double lc = 0.0;  // search iterate (mode 1) or located sigma (mode 2)
 
   // Scheduler.  Record slots are handed out as tickets in slot order, one
   // fetch_add per wave.  Slots below n_primary hold primaries written before
   // the kernel started; later slots are filled by spawns and published by a
   // release store of their status, so a lane may wait on its ticket for a
-  // while.  Rays that end are counted per lane and added to q->finished when
+  // while.  Rays that end are counted per wave and added to q->finished when
   // the wave has nothing to step; the launch is done when finished == tail
   // (tail counts every slot ever reserved), since only running rays spawn.
-  int32_t ticket = -1;     // -1: none, -2: tickets exhausted, else slot waited on
-  uint32_t fin_local = 0;  // rays finished here, not yet added to q->finished
+  int32_t ticket = -1;  // -1: none, -2: tickets exhausted, else slot waited on
   uint32_t sleeps = 0;
   const Pool& Q = P.pool;
 
   for (;;) {
+    // ---- boundary events located in the previous iteration ----
+    if (mode == 2) {
+      mode = 0;
+      int32_t fin = boundary_event<MODEL, FIELD>(P, R, s_k[tid], lc, R.y, s_hn[tid], C);
+      if (!fin) fin = pretrial_status(P, R);
+      if (fin) {
+        write_record(P, R, fin, C);
+        R.slot = -1;
+        C.bump(S_FIN);
+      }
+    }
     // ---- tickets for idle lanes ----
     const bool lane_idle = R.slot < 0 && ticket == -1;
     const uint64_t idle = __ballot(lane_idle);
@@ -726,7 +775,7 @@ __global__ void __launch_bounds__(256) trace_kernel(KParams Parg) {
       if (lane == leader) {
         base = __hip_atomic_fetch_add(&P.q->head, (uint64_t)nidle, __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);
-        C.refills++;
+        atomicAdd(&C.c[S_REFILLS], 1ull);
       }
       base = __shfl(base, leader);
       if (lane_idle) {
@@ -750,22 +799,24 @@ __global__ void __launch_bounds__(256) trace_kernel(KParams Parg) {
         if (fst) {
           write_record(P, R, fst, C);
           R.slot = -1;
-          ++fin_local;
+          C.bump(S_FIN);
         }
         ticket = -1;
       } else if (st != RT_ST_EMPTY) {
-        ++fin_local;  // an invalid primary: its record is already final
+        C.bump(S_FIN);  // an invalid primary: its record is already final
         ticket = -1;
       }
     }
     if (__ballot(R.slot >= 0) == 0) {
       // nothing to step: publish finished counts, stop once every ray is done
-      const unsigned long long f = wave_sum(fin_local + C.dropped);
-      fin_local = 0;
-      C.dropped = 0;
-      if (lane == 0 && f)
-        __hip_atomic_fetch_add(&P.q->finished, (uint64_t)f, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+      if (lane == 0) {
+        const unsigned long long f = C.c[S_FIN];
+        if (f) {
+          C.c[S_FIN] = 0;
+          __hip_atomic_fetch_add(&P.q->finished, (uint64_t)f, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
       if (__ballot(ticket == -2) == ~0ull) break;  // this wave can get no more work
       unsigned long long done = 0;
       if (lane == 0) {
@@ -777,7 +828,7 @@ __global__ void __launch_bounds__(256) trace_kernel(KParams Parg) {
       }
       if (__shfl(done, 0)) break;
       if (++sleeps > (1u << 26)) {  // guard: never expected
-        C.sched_err++;
+        if (lane == 0) atomicAdd(&C.c[S_SCHED], 1ull);
         break;
       }
       __builtin_amdgcn_s_sleep(4);
@@ -786,35 +837,32 @@ __global__ void __launch_bounds__(256) trace_kernel(KParams Parg) {
     if (R.slot < 0) continue;
 
     // ---- one Cash-Karp trial in every busy lane ----
-    double ht;
-    if (mode == 0) {
-      clipped = (P.s_max - R.s <= R.h);
-      ht = clipped ? P.s_max - R.s : R.h;
-    } else {
-      ht = lc;
-    }
+    const bool stepping = mode == 0;
+    const bool clipped = P.s_max - R.s <= R.h;
+    const double ht = stepping ? (clipped ? P.s_max - R.s : R.h) : lc;
     double y5[7], err;
     trial<MODEL, FIELD>(P, R, ht, y5, err);
 
     int32_t fin = 0;
     bool located = false;
     double sig = 0.0;
-    if (mode == 0) {
+    if (stepping) {
       bool finite = isfinite(err);
 #pragma unroll
       for (int i = 0; i < 7; ++i) finite = finite && isfinite(y5[i]);
+      const bool accept = err <= 1.0 || ht <= P.h_min;
+      const double hn = clamp_h(P, ht * step_factor(err, accept));
       if (!finite) {
-        C.nonfinite++;
+        C.bump(S_NONFINITE);
         fin = RT_ST_NONFINITE;
-      } else if (!(err <= 1.0) && !(ht <= P.h_min)) {
+      } else if (!accept) {
         R.n_rej++;
-        C.rejected++;
-        R.h = clamp_h(P, ht * fmax(kShrinkMin, kSafety * pow_neg_inv<4>(err)));
+        C.bump(S_REJ);
+        R.h = hn;
       } else {
         R.n_acc++;
-        C.accepted++;
-        if (err > 1.0) C.forced++;
-        h_next = clamp_h(P, ht * (err < kErrCon ? kGrowMax : kSafety * pow_neg_inv<5>(err)));
+        C.bump(S_ACC);
+        if (err > 1.0) C.bump(S_FORCED);
         if constexpr (MODEL == RT_MODEL_PAPER) {
           const double il = rsqrt_nr(fma(y5[3], y5[3], fma(y5[4], y5[4], y5[5] * y5[5])));
           y5[3] *= il;
@@ -827,84 +875,102 @@ __global__ void __launch_bounds__(256) trace_kernel(KParams Parg) {
 #pragma unroll
           for (int i = 0; i < 7; ++i) R.y[i] = y5[i];
           R.s = clipped ? P.s_max : R.s + ht;
-          R.h = h_next;
+          R.h = hn;
           if (clipped) fin = RT_ST_PATH;
         } else {
-          hp = ht;
-          lk = k;
-          lpass = 0;
+          // start the crossing search on [0, ht] (rare)
+          s_hp[tid] = ht;
+          s_hn[tid] = hn;
+          s_k[tid] = k;
           if (G0 <= 0.0) {
+            s_meta[tid] = 1;  // pass 0, no iterations, last side 0
             located = true;
             sig = 0.0;
 #pragma unroll
             for (int i = 0; i < 7; ++i) y5[i] = R.y[i];
           } else {
+            s_a[tid] = 0.0;
+            s_Ga[tid] = G0;
+            s_b[tid] = ht;
+            s_Gb[tid] = G1;
+            s_meta[tid] = 1;
+            lc = ht - G1 * ht / (G1 - G0);
             mode = 1;
-            la = 0.0;
-            lGa = G0;
-            lb = ht;
-            lGb = G1;
-            llast = 0;
-            lit = 0;
-            lc = lb - lGb * (lb - la) / (lGb - lGa);
           }
         }
       }
     } else {
-      // one iterate of the Illinois search for boundary lk
-      C.relocation++;
-      ++lit;
-      const double Gc = bnd_G(P, lk, R.side, y5);
+      // one iterate of the Illinois search (state in LDS)
+      C.bump(S_RELOC);
+      const int k = s_k[tid];
+      int meta = s_meta[tid];
+      int last = (meta & 3) - 1;
+      const int it = ((meta >> 2) & 0xff) + 1;
+      double a = s_a[tid], Ga = s_Ga[tid], b = s_b[tid], Gb = s_Gb[tid];
+      const double Gc = bnd_G(P, s_bnd[k], k, R.side, y5);
       bool done = fabs(Gc) <= kLocGTol;
       if (!done) {
         if (Gc < 0.0) {
-          lb = lc;
-          lGb = Gc;
-          if (llast == -1) lGa *= 0.5;
-          llast = -1;
+          b = lc;
+          Gb = Gc;
+          if (last == -1) Ga *= 0.5;
+          last = -1;
         } else {
-          la = lc;
-          lGa = Gc;
-          if (llast == 1) lGb *= 0.5;
-          llast = 1;
+          a = lc;
+          Ga = Gc;
+          if (last == 1) Gb *= 0.5;
+          last = 1;
         }
-        if (lb - la <= kLocWRel * hp || lit >= kLocMaxIt) done = true;
+        if (b - a <= kLocWRel * s_hp[tid] || it >= kLocMaxIt) done = true;
       }
       if (done) {
         located = true;
         sig = lc;
       } else {
-        lc = lb - lGb * (lb - la) / (lGb - lGa);
+        s_a[tid] = a;
+        s_Ga[tid] = Ga;
+        s_b[tid] = b;
+        s_Gb[tid] = Gb;
+        lc = b - Gb * (b - a) / (Gb - Ga);
       }
+      s_meta[tid] = (meta & ~0x3ff) | (it << 2) | (last + 1);
     }
 
-    // ---- a crossing was located: look for an earlier one, else act ----
-    while (located) {
-      double H0 = 0.0, H1 = 0.0;
-      const int j = lpass < kLocMaxPass ? pick_crossing(P, R.side, R.y, y5, sig, lk, H0, H1) : -1;
-      if (j >= 0) {
-        ++lpass;
-        lk = j;
+    // ---- a crossing was located: look for an earlier one, else act on it ----
+    if (located) {
+      int k = s_k[tid];
+      int pass = s_meta[tid] >> 16;
+      for (;;) {
+        double H0 = 0.0, H1 = 0.0;
+        const int j = pass < kLocMaxPass ? pick_crossing(P, R.side, R.y, y5, sig, k, H0, H1) : -1;
+        if (j < 0) {
+          // the event itself runs at the top of the next iteration, outside
+          // the post-trial branches
+          s_k[tid] = k;
+          mode = 2;
+          lc = sig;
+#pragma unroll
+          for (int i = 0; i < 7; ++i) R.y[i] = y5[i];
+          break;
+        }
+        ++pass;
+        k = j;
         if (H0 <= 0.0) {
           sig = 0.0;
 #pragma unroll
           for (int i = 0; i < 7; ++i) y5[i] = R.y[i];
           continue;
         }
+        s_k[tid] = k;
+        s_a[tid] = 0.0;
+        s_Ga[tid] = H0;
+        s_b[tid] = sig;
+        s_Gb[tid] = H1;
+        s_meta[tid] = (pass << 16) | 1;
+        lc = sig - H1 * sig / (H1 - H0);
         mode = 1;
-        la = 0.0;
-        lGa = H0;
-        lb = sig;
-        lGb = H1;
-        llast = 0;
-        lit = 0;
-        lc = lb - lGb * (lb - la) / (lGb - lGa);
-        located = false;
         break;
       }
-      located = false;
-      mode = 0;
-      fin = boundary_event<MODEL, FIELD>(P, R, lk, sig, y5, h_next, C);
     }
 
     if (!fin && mode == 0) fin = pretrial_status(P, R);
@@ -912,41 +978,18 @@ __global__ void __launch_bounds__(256) trace_kernel(KParams Parg) {
       write_record(P, R, fin, C);
       R.slot = -1;
       mode = 0;
-      ++fin_local;
+      C.bump(S_FIN);
     }
   }
 
-  // ---- per-wave statistics ----
-  rt_stats* S = P.stats;
-  auto wsum = [&](uint32_t v) -> unsigned long long {
-    unsigned long long x = v;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
-  };
-  unsigned long long v[12] = {wsum(C.accepted), wsum(C.rejected), wsum(C.relocation),
-                              wsum(C.forced),   wsum(C.events),   wsum(C.spawned),
-                              wsum(C.supp_gen), wsum(C.supp_amp), wsum(C.records),
-                              wsum(C.nonfinite), wsum(C.refills), wsum(C.sched_err)};
-  int mg = C.max_gen;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mg = max(mg, __shfl_xor(mg, o));
+  // ---- per-wave statistics into the launch's rt_stats ----
   if (lane == 0) {
-    // field order of rt_stats
-    unsigned long long* s64 = reinterpret_cast<unsigned long long*>(S);
-    atomicAdd(&s64[0], v[0]);    // accepted
-    atomicAdd(&s64[1], v[1]);    // rejected
-    atomicAdd(&s64[2], v[2]);    // relocation
-    atomicAdd(&s64[3], v[3]);    // forced
-    atomicAdd(&s64[4], v[4]);    // events
-    atomicAdd(&s64[5], v[5]);    // spawned
-    atomicAdd(&s64[6], v[6]);    // suppressed_gen
-    atomicAdd(&s64[7], v[7]);    // suppressed_amp
-    atomicAdd(&s64[8], v[8]);    // records
-    atomicAdd(&s64[10], v[9]);   // nonfinite
-    atomicMax(&s64[11], (unsigned long long)mg);  // max_gen
-    atomicAdd(&s64[13], v[10]);  // refills
-    atomicAdd(&s64[14], v[11]);  // sched_errors
+    unsigned long long* s64 = reinterpret_cast<unsigned long long*>(P.stats);
+    for (int i = 0; i < S_FIN; ++i) {
+      if (i == S_NEEDED || i == S_INVALID || C.c[i] == 0) continue;
+      if (i == S_MAXGEN) atomicMax(&s64[i], C.c[i]);
+      else atomicAdd(&s64[i], C.c[i]);
+    }
   }
 }
 
