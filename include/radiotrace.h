@@ -161,6 +161,7 @@ typedef struct {
   int64_t invalid;    /* primary rays flagged RT_ST_INVALID */
   int64_t refills;    /* wave refill operations of the scheduler */
   int64_t sched_errors; /* scheduler waits that timed out (must stay 0) */
+  int64_t spilled;    /* secondaries handed to other waves (global queue) */
 } rt_stats;
 
 /* Caller-owned output records, one per ray (primary or secondary), in no
@@ -193,6 +194,9 @@ typedef struct {
   void* ev_trace_begin;     /* hipEvent_t recorded just before the trace
                                kernel, or NULL */
   void* ev_trace_end;       /* hipEvent_t recorded just after it, or NULL */
+  int32_t local_queue;      /* secondaries a wave keeps for itself before it
+                               hands further ones to other waves: 0 = 512,
+                               -1 = none, else 1..1024 */
 } rt_tuning;
 
 /* ABI version (RT_ABI_VERSION of the built library). */
@@ -211,9 +215,11 @@ rt_status rt_validate(const rt_field* field, const rt_boundaries* boundaries,
                       const rt_directions* directions, double tol,
                       const rt_step_limits* limits);
 
-/* Bytes of device workspace raytrace_launch needs for this field: queue
- * counters, plus the prepared grid (16 bytes per node) for gridded fields. */
-rt_status rt_workspace_bytes(const rt_field* field, size_t* bytes);
+/* Bytes of device workspace raytrace_launch needs for this field and record
+ * capacity: queue counters, a queue of record indices (4 bytes per record,
+ * for secondaries shared between waves), plus the prepared grid (16 bytes
+ * per node) for gridded fields. */
+rt_status rt_workspace_bytes(const rt_field* field, int64_t capacity, size_t* bytes);
 
 /* Trace all primary rays and every secondary they cast.  Asynchronous on
  * 'stream' (a hipStream_t; NULL = the default stream): it validates the

@@ -66,7 +66,7 @@ class rt_step_limits(C.Structure):
 
 STAT_FIELDS = ["accepted", "rejected", "relocation", "forced", "events", "spawned",
                "suppressed_gen", "suppressed_amp", "records", "needed", "nonfinite",
-               "max_gen", "invalid", "refills", "sched_errors"]
+               "max_gen", "invalid", "refills", "sched_errors", "spilled"]
 
 
 class rt_stats(C.Structure):
@@ -88,7 +88,7 @@ class rt_outputs(C.Structure):
 class rt_tuning(C.Structure):
     _fields_ = [("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("refill_threshold", C.c_int32), ("ev_trace_begin", C.c_void_p),
-                ("ev_trace_end", C.c_void_p)]
+                ("ev_trace_end", C.c_void_p), ("local_queue", C.c_int32)]
 
 
 _lib = None
@@ -116,7 +116,7 @@ def lib() -> C.CDLL:
                                   C.POINTER(rt_sources), C.POINTER(rt_directions), C.c_double,
                                   C.POINTER(rt_step_limits)]
         L.rt_workspace_bytes.restype = C.c_int
-        L.rt_workspace_bytes.argtypes = [C.POINTER(rt_field), C.POINTER(C.c_size_t)]
+        L.rt_workspace_bytes.argtypes = [C.POINTER(rt_field), C.c_int64, C.POINTER(C.c_size_t)]
         L.raytrace_launch.restype = C.c_int
         L.raytrace_launch.argtypes = [C.POINTER(rt_field), C.POINTER(rt_boundaries),
                                       C.POINTER(rt_sources), C.POINTER(rt_directions), C.c_double,
@@ -140,9 +140,9 @@ def rt_validate(field, boundaries, sources, directions, tol, limits) -> int:
                                  C.byref(directions), float(tol), C.byref(limits)))
 
 
-def rt_workspace_bytes(field) -> int:
+def rt_workspace_bytes(field, capacity: int) -> int:
     n = C.c_size_t(0)
-    st = lib().rt_workspace_bytes(C.byref(field), C.byref(n))
+    st = lib().rt_workspace_bytes(C.byref(field), C.c_int64(capacity), C.byref(n))
     if st != RT_OK:
         raise RTError(st, rt_last_error())
     return int(n.value)
@@ -238,7 +238,7 @@ class DeviceScene:
         self.stats_dev = torch.zeros(len(STAT_FIELDS), dtype=torch.int64, device=dev)
         self.out = rt_outputs(*([self.rec[f].data_ptr() for f in RECORD_FIELDS]
                                 + [self.capacity, self.stats_dev.data_ptr()]))
-        self.ws_bytes = rt_workspace_bytes(self.desc.field)
+        self.ws_bytes = rt_workspace_bytes(self.desc.field, self.capacity)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
 
     def launch(self, stream=None, tuning: Optional[rt_tuning] = None) -> None:

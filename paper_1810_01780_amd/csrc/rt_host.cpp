@@ -116,12 +116,17 @@ rt_status rt_validate(const rt_field* field, const rt_boundaries* boundaries,
   return rt::validate(field, boundaries, sources, directions, tol, limits);
 }
 
-rt_status rt_workspace_bytes(const rt_field* field, size_t* bytes) {
+rt_status rt_workspace_bytes(const rt_field* field, int64_t capacity, size_t* bytes) {
   if (!field || !bytes) {
     rt::set_last_error("null argument");
     return RT_ERR_INVALID_ARG;
   }
-  size_t b = 4096;  // queue counters, padded
+  if (capacity < 0) {
+    rt::set_last_error("negative capacity");
+    return RT_ERR_INVALID_ARG;
+  }
+  size_t b = 4096;                                      // queue counters, padded
+  b += ((size_t)capacity * 4 + 4095) / 4096 * 4096;     // overflow queue
   if (field->n_regions > 0 && field->regions && rt::field_uses_grid(field)) {
     const rt_grid& g = field->grid;
     if (g.nx < 2 || g.ny < 2 || g.nz < 2) {

@@ -441,14 +441,14 @@ __device__ __forceinline__ bool fresnel(double n1, double n2, double ci, double 
   return true;
 }
 
-// Per-wave statistics in LDS, indexed like the fields of rt_stats, plus
-// S_FIN: rays finished (or dropped for lack of a slot) that have not been
-// added to the queue's finished counter yet.  bump() adds the number of lanes
-// calling it (one LDS atomic by the first of them), so it may be used inside
-// divergent code.
+// Per-wave statistics in LDS, indexed like the fields of rt_stats.  bump()
+// adds the number of lanes calling it (one LDS atomic by the first of them),
+// so it may be used inside divergent code.
 enum : int {
   S_ACC = 0, S_REJ, S_RELOC, S_FORCED, S_EVENTS, S_SPAWNED, S_SUPP_GEN, S_SUPP_AMP,
-  S_RECORDS, S_NEEDED, S_NONFINITE, S_MAXGEN, S_INVALID, S_REFILLS, S_SCHED, S_FIN, S_COUNT
+  S_RECORDS, S_NEEDED, S_NONFINITE, S_MAXGEN, S_INVALID, S_REFILLS, S_SCHED, S_SPILLED,
+  S_FIN,  // rays finished here and not yet added to q->finished (not a stat)
+  S_COUNT
 };
 struct Counters {
   unsigned long long* c;  // this wave's row
@@ -465,6 +465,19 @@ struct Counters {
 __device__ __forceinline__ uint64_t lanemask_lt() {
   return __lanemask_lt();
 }
+
+// Secondaries stay with the wave that cast them: a ring of record-slot
+// indices per wave in LDS.  Producer and consumer are the same wave, so a
+// workgroup-scope fence orders the child's record stores before the lane
+// that later takes the child reads them; no cross-CU coherence is needed
+// (the L2s of the eight XCDs are not coherent with each other, and
+// publishing through them would mean L2 write-backs).
+constexpr uint32_t kRing = 1024;  // LDS ring entries per wave (>= any local limit)
+struct WaveQueue {
+  int32_t* ring;   // kRing slot indices
+  uint32_t* head;  // next index to take
+  uint32_t* tail;  // next index to fill
+};
 
 // Reserve consecutive record slots for the calling wave's active lanes (one
 // atomic per wave); returns this lane's slot index.
@@ -546,6 +559,7 @@ __device__ __forceinline__ void write_record(const KParams& P, const Ray& R, int
   Q.side[i] = R.side;
   Q.status[i] = status;
   C.bump(S_RECORDS);
+  C.bump(S_FIN);
 }
 
 // Load the queued ray of a slot into a lane.
@@ -589,7 +603,8 @@ __device__ __forceinline__ void trial(const KParams& P, const Ray& R, double h, 
 // step); returns the final status of the ray or 0 when it continues.
 template <int MODEL, int FIELD>
 __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int k, double sig,
-                                                  double ys[7], double h_next, const Counters& C) {
+                                                  double ys[7], double h_next, const Counters& C,
+                                                  const WaveQueue& WQ) {
   const KBnd& B = s_bnd[k];
   if (B.kind != B_TIME) {
     // snap onto the plane
@@ -640,7 +655,7 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
         C.bump(S_SPAWNED);
         const uint64_t c = wave_append(&P.q->tail);
         if (c >= (uint64_t)P.capacity) {
-          C.bump(S_FIN);  // no record slot: counted as finished, reported via stats.needed
+          C.bump(S_FIN);  // no record slot: reported via stats.needed
         } else {
           const double eta = n1 / n2;
           const double f = eta * ci - ct;
@@ -666,8 +681,24 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
           Q.n_acc[c] = 0;
           Q.n_rej[c] = 0;
           Q.n_ev[c] = 0;
-          __hip_atomic_store(&Q.status[c], (int32_t)RT_ST_QUEUED, __ATOMIC_RELEASE,
-                             __HIP_MEMORY_SCOPE_AGENT);
+          Q.status[c] = RT_ST_QUEUED;
+          // Queue the child on this wave while its backlog is short; beyond
+          // local_limit queued rays, publish it on the global overflow queue
+          // so that idle waves elsewhere share a large ray tree.
+          const uint64_t m = __ballot(1);
+          const uint32_t h = *WQ.head, t = *WQ.tail;
+          const uint32_t rank = (uint32_t)__popcll(m & lanemask_lt());
+          const uint32_t room = (t - h) < P.local_limit ? P.local_limit - (t - h) : 0u;
+          const uint32_t np = min((uint32_t)__popcll(m), room);
+          if (rank < np) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            WQ.ring[(t + rank) % kRing] = (int32_t)c;
+          } else {
+            const uint64_t e = wave_append(&P.q->gq_tail);
+            __hip_atomic_store(&P.gq[e], (int32_t)c, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            C.bump(S_SPILLED);
+          }
+          if ((int)__lane_id() == __ffsll((unsigned long long)m) - 1) *WQ.tail = t + np;
         }
       }
     } else {
@@ -714,7 +745,7 @@ __device__ __forceinline__ double step_factor(double err, bool accepted) {
 }
 
 template <int MODEL, int FIELD>
-__global__ void __launch_bounds__(256) trace_kernel(KParams P) {
+__device__ __forceinline__ void trace_body(const KParams& P) {
   for (int i = threadIdx.x; i < P.n_regions; i += blockDim.x) s_reg[i] = P.reg[i];
   for (int i = threadIdx.x; i < P.n_bnd; i += blockDim.x) s_bnd[i] = P.bnd[i];
   const int lane = (int)__lane_id();
@@ -741,14 +772,30 @@ __global__ void __launch_bounds__(256) trace_kernel(KParams P) {
   int mode = 0;     // 0: normal step, 1: searching a crossing, 2: crossing located
   double lc = 0.0;  // search iterate (mode 1) or located sigma (mode 2)
 
-  // Scheduler.  Record slots are handed out as tickets in slot order, one
-  // fetch_add per wave.  Slots below n_primary hold primaries written before
-  // the kernel started; later slots are filled by spawns and published by a
-  // release store of their status, so a lane may wait on its ticket for a
-  // while.  Rays that end are counted per wave and added to q->finished when
-  // the wave has nothing to step; the launch is done when finished == tail
-  // (tail counts every slot ever reserved), since only running rays spawn.
-  int32_t ticket = -1;  // -1: none, -2: tickets exhausted, else slot waited on
+  // Scheduler.
+  //  * Primaries (record slots [0, n_primary)) are handed out in slot order,
+  //    one fetch_add on q->head per wave refill.
+  //  * A secondary gets its record slot from q->tail.  Up to local_limit
+  //    wait on the wave that cast them (ring in LDS; producer and consumer
+  //    are the same wave, so a workgroup-scope fence suffices).  Beyond that
+  //    they are published on a global overflow queue (release store of the
+  //    slot index into P.gq), from which waves without local work take
+  //    tickets, one fetch_add on q->gq_head per refill; a ticket whose entry
+  //    is not published yet waits.
+  //  * Idle lanes take, in this order: queued children of their wave,
+  //    primaries, overflow tickets.  Finished rays are counted per wave and
+  //    added to q->finished when the wave has nothing to step; the launch is
+  //    over when finished == tail (only running rays create new ones).
+  __shared__ int32_t s_ring[4][kRing];
+  __shared__ uint32_t s_rh[4], s_rt[4];
+  const int wv = tid / 64;
+  const WaveQueue WQ{s_ring[wv], &s_rh[wv], &s_rt[wv]};
+  if (lane == 0) {
+    s_rh[wv] = 0;
+    s_rt[wv] = 0;
+  }
+  bool prim_done = false;  // wave-uniform: no primaries left to claim
+  int32_t ticket = -1;     // overflow ticket: -1 none, -2 exhausted, else entry
   uint32_t sleeps = 0;
   const Pool& Q = P.pool;
 
@@ -756,59 +803,91 @@ __global__ void __launch_bounds__(256) trace_kernel(KParams P) {
     // ---- boundary events located in the previous iteration ----
     if (mode == 2) {
       mode = 0;
-      int32_t fin = boundary_event<MODEL, FIELD>(P, R, s_k[tid], lc, R.y, s_hn[tid], C);
+      int32_t fin = boundary_event<MODEL, FIELD>(P, R, s_k[tid], lc, R.y, s_hn[tid], C, WQ);
       if (!fin) fin = pretrial_status(P, R);
       if (fin) {
         write_record(P, R, fin, C);
         R.slot = -1;
-        C.bump(S_FIN);
       }
     }
-    // ---- tickets for idle lanes ----
+    // ---- refill idle lanes ----
     const bool lane_idle = R.slot < 0 && ticket == -1;
     const uint64_t idle = __ballot(lane_idle);
-    const uint64_t busy = __ballot(R.slot >= 0);
-    const int nidle = __popcll(idle);
-    if (nidle > 0 && (nidle >= P.refill || busy == 0)) {
-      const int leader = __ffsll((unsigned long long)idle) - 1;
-      unsigned long long base = 0;
-      if (lane == leader) {
-        base = __hip_atomic_fetch_add(&P.q->head, (uint64_t)nidle, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-        atomicAdd(&C.c[S_REFILLS], 1ull);
+    const uint32_t nidle = (uint32_t)__popcll(idle);
+    const uint32_t rank = (uint32_t)__popcll(idle & lanemask_lt());
+    uint32_t nr = 0;
+    if (nidle > 0) {
+      // (1) children queued on this wave
+      const uint32_t h = *WQ.head, t = *WQ.tail;
+      nr = min(nidle, t - h);
+      if (nr > 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (lane_idle && rank < nr) {
+          load_ray<MODEL, FIELD>(P, WQ.ring[(h + rank) % kRing], R, C);
+          mode = 0;
+        }
+        if (lane == 0) *WQ.head = h + nr;
       }
-      base = __shfl(base, leader);
-      if (lane_idle) {
-        const uint64_t t = base + (uint64_t)__popcll(idle & lanemask_lt());
-        ticket = t < (uint64_t)P.capacity ? (int32_t)t : -2;
+      // (2) primaries
+      const uint32_t nleft = nidle - nr;
+      if (!prim_done && nleft > 0 && (nleft >= (uint32_t)P.refill || nleft == 64)) {
+        unsigned long long base = 0;
+        if (lane == 0) {
+          base = __hip_atomic_fetch_add(&P.q->head, (uint64_t)nleft, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+          atomicAdd(&C.c[S_REFILLS], 1ull);
+        }
+        base = __shfl(base, 0);
+        if (base + nleft >= (uint64_t)P.n_primary) prim_done = true;
+        if (lane_idle && rank >= nr) {
+          const uint64_t ti = base + (rank - nr);
+          if (ti < (uint64_t)P.n_primary) {
+            if (Q.status[ti] == RT_ST_QUEUED) {
+              load_ray<MODEL, FIELD>(P, (int32_t)ti, R, C);
+              mode = 0;
+            } else {
+              C.bump(S_FIN);  // an invalid primary: its record is already final
+            }
+          }
+        }
+      }
+      // (3) overflow tickets, once the wave has nothing else to take
+      const bool lane_idle2 = R.slot < 0 && ticket == -1;
+      const uint64_t idle2 = __ballot(lane_idle2);
+      const uint32_t n2 = (uint32_t)__popcll(idle2);
+      if (prim_done && n2 > 0 && *WQ.head == *WQ.tail &&
+          (n2 >= (uint32_t)P.refill || n2 == 64)) {
+        unsigned long long base = 0;
+        if (lane == 0)
+          base = __hip_atomic_fetch_add(&P.q->gq_head, (uint64_t)n2, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+        base = __shfl(base, 0);
+        if (lane_idle2) {
+          const uint64_t e = base + (uint64_t)__popcll(idle2 & lanemask_lt());
+          ticket = e < (uint64_t)P.capacity ? (int32_t)e : -2;
+        }
       }
     }
-    // ---- waiting lanes take their slot once it holds a ray ----
+    // (4) lanes holding an overflow ticket take the ray once it is published
     if (R.slot < 0 && ticket >= 0) {
-      int32_t st;
-      if (ticket < P.n_primary) {
-        st = Q.status[ticket];
-      } else {
-        st = __hip_atomic_load(&Q.status[ticket], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (st != RT_ST_EMPTY) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      }
-      if (st == RT_ST_QUEUED) {
-        load_ray<MODEL, FIELD>(P, ticket, R, C);
+      const int32_t c = __hip_atomic_load(&P.gq[ticket], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (c >= 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        load_ray<MODEL, FIELD>(P, c, R, C);
         mode = 0;
-        const int32_t fst = pretrial_status(P, R);
-        if (fst) {
-          write_record(P, R, fst, C);
-          R.slot = -1;
-          C.bump(S_FIN);
-        }
         ticket = -1;
-      } else if (st != RT_ST_EMPTY) {
-        C.bump(S_FIN);  // an invalid primary: its record is already final
-        ticket = -1;
+      }
+    }
+    // a ray may end before its first step (path limit reached, no steps left)
+    if (R.slot >= 0 && mode == 0 && R.n_acc + R.n_rej == 0) {
+      const int32_t fst = pretrial_status(P, R);
+      if (fst) {
+        write_record(P, R, fst, C);
+        R.slot = -1;
       }
     }
     if (__ballot(R.slot >= 0) == 0) {
-      // nothing to step: publish finished counts, stop once every ray is done
+      // nothing to step: publish finished counts, stop once no work can come
       if (lane == 0) {
         const unsigned long long f = C.c[S_FIN];
         if (f) {
@@ -817,21 +896,23 @@ __global__ void __launch_bounds__(256) trace_kernel(KParams P) {
                                  __HIP_MEMORY_SCOPE_AGENT);
         }
       }
-      if (__ballot(ticket == -2) == ~0ull) break;  // this wave can get no more work
-      unsigned long long done = 0;
-      if (lane == 0) {
-        const uint64_t fin_g =
-            __hip_atomic_load(&P.q->finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t tail_g =
-            __hip_atomic_load(&P.q->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        done = fin_g == tail_g;
+      if (*WQ.head == *WQ.tail && prim_done) {
+        if (__ballot(ticket == -2) == ~0ull) break;  // no work can reach this wave
+        unsigned long long done = 0;
+        if (lane == 0) {
+          const uint64_t fin_g =
+              __hip_atomic_load(&P.q->finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const uint64_t tail_g =
+              __hip_atomic_load(&P.q->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          done = fin_g == tail_g;
+        }
+        if (__shfl(done, 0)) break;
+        if (++sleeps > (1u << 26)) {  // guard: never expected
+          if (lane == 0) atomicAdd(&C.c[S_SCHED], 1ull);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(4);
       }
-      if (__shfl(done, 0)) break;
-      if (++sleeps > (1u << 26)) {  // guard: never expected
-        if (lane == 0) atomicAdd(&C.c[S_SCHED], 1ull);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(4);
       continue;
     }
     if (R.slot < 0) continue;
@@ -978,7 +1059,6 @@ __global__ void __launch_bounds__(256) trace_kernel(KParams P) {
       write_record(P, R, fin, C);
       R.slot = -1;
       mode = 0;
-      C.bump(S_FIN);
     }
   }
 
@@ -993,6 +1073,19 @@ __global__ void __launch_bounds__(256) trace_kernel(KParams P) {
   }
 }
 
+// Persistent trace kernels.  The stratified variants are held to three
+// waves per SIMD (168 VGPRs): latency of the FP64 dependency chains is hidden
+// by occupancy, and they fit without spilling.
+template <int MODEL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+trace_strat_kernel(KParams P) {
+  trace_body<MODEL, 0>(P);
+}
+template <int MODEL>
+__global__ void __launch_bounds__(256) trace_grid_kernel(KParams P) {
+  trace_body<MODEL, 1>(P);
+}
+
 // Queue counters and statistics to their launch values.
 __global__ void reset_kernel(KParams P) {
   const int i = threadIdx.x;
@@ -1001,6 +1094,8 @@ __global__ void reset_kernel(KParams P) {
   if (i == 0) {
     P.q->head = 0;
     P.q->tail = (uint64_t)P.n_primary;
+    P.q->gq_head = 0;
+    P.q->gq_tail = 0;
     P.q->finished = 0;
   }
 }
@@ -1045,6 +1140,7 @@ __global__ void init_kernel(KParams P, const double* __restrict__ src_xyz, int32
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const Pool& Q = P.pool;
   if (i >= P.capacity) return;
+  P.gq[i] = -1;
   if (i >= P.n_primary) {
     Q.status[i] = RT_ST_EMPTY;
     return;
@@ -1107,13 +1203,20 @@ struct DeviceInfo {
 thread_local DeviceInfo g_dev;
 
 template <int MODEL, int FIELD>
+void* trace_kernel_ptr() {
+  return FIELD ? reinterpret_cast<void*>(&trace_grid_kernel<MODEL>)
+               : reinterpret_cast<void*>(&trace_strat_kernel<MODEL>);
+}
+
+template <int MODEL, int FIELD>
 int max_blocks_per_cu(int block) {
-  static thread_local int cached[2][5] = {};
-  int& c = cached[FIELD][block / 64];
+  static thread_local int cached[5] = {};
+  int& c = cached[block / 64];
   if (c == 0) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<MODEL, FIELD>, block, 0) !=
-            hipSuccess || nb < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel_ptr<MODEL, FIELD>(), block,
+                                                     0) != hipSuccess ||
+        nb < 1)
       nb = 1;
     c = nb;
   }
@@ -1122,7 +1225,10 @@ int max_blocks_per_cu(int block) {
 
 template <int MODEL, int FIELD>
 hipError_t launch_trace(const KParams& P, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL((trace_kernel<MODEL, FIELD>), dim3(grid), dim3(block), 0, s, P);
+  if constexpr (FIELD == 1)
+    hipLaunchKernelGGL((trace_grid_kernel<MODEL>), dim3(grid), dim3(block), 0, s, P);
+  else
+    hipLaunchKernelGGL((trace_strat_kernel<MODEL>), dim3(grid), dim3(block), 0, s, P);
   return hipGetLastError();
 }
 
@@ -1168,7 +1274,7 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
     return RT_ERR_INVALID_ARG;
   }
   size_t need = 0;
-  st = rt_workspace_bytes(field, &need);
+  st = rt_workspace_bytes(field, out->capacity, &need);
   if (st != RT_OK) return st;
   if (workspace_bytes < need) {
     set_last_error("workspace of %zu bytes < %zu needed", workspace_bytes, need);
@@ -1182,6 +1288,12 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   const int refill = tuning && tuning->refill_threshold ? tuning->refill_threshold : 16;
   if (refill < 1 || refill > 64) {
     set_last_error("refill_threshold must be 1..64");
+    return RT_ERR_INVALID_ARG;
+  }
+  int local = tuning && tuning->local_queue ? tuning->local_queue : 512;
+  if (local == -1) local = 0;
+  if (local < 0 || local > (int)kRing) {
+    set_last_error("local_queue must be -1, 0 or 1..%d", (int)kRing);
     return RT_ERR_INVALID_ARG;
   }
 
@@ -1227,6 +1339,7 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   P.model = L->model;
   P.max_gen = L->max_generations;
   P.refill = refill;
+  P.local_limit = (uint32_t)local;
   P.tol = tol;
   P.inv_tol = 1.0 / tol;
   P.h_min = L->h_min;
@@ -1243,11 +1356,13 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   P.capacity = out->capacity;
   P.n_primary = dirs->n;
   P.q = static_cast<QueueCounters*>(workspace);
+  P.gq = reinterpret_cast<int32_t*>(static_cast<char*>(workspace) + 4096);
+  const size_t gq_bytes = ((size_t)out->capacity * 4 + 4095) / 4096 * 4096;
   P.stats = out->stats;
   const bool grid = field_uses_grid(field);
   if (grid) {
     const rt_grid& g = field->grid;
-    P.nodes = static_cast<char*>(workspace) + 4096;
+    P.nodes = static_cast<char*>(workspace) + 4096 + gq_bytes;
     P.gnx = g.nx;
     P.gny = g.ny;
     P.gnz = g.nz;

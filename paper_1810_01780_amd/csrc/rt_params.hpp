@@ -34,9 +34,11 @@ struct Pool {
 };
 
 struct QueueCounters {
-  uint64_t head;      // next slot (ticket) to hand out
-  uint64_t tail;      // slots reserved so far (primaries + spawned)
-  uint64_t finished;  // rays finished (or dropped), added lazily per wave
+  uint64_t head;      // next primary to hand out
+  uint64_t tail;      // record slots reserved so far (primaries + spawned)
+  uint64_t gq_head;   // next overflow-queue ticket
+  uint64_t gq_tail;   // overflow-queue entries reserved
+  uint64_t finished;  // rays finished (added lazily, per wave)
 };
 
 struct KParams {
@@ -47,6 +49,7 @@ struct KParams {
   // grid: float4 nodes (n, Dx, Dy, Dz) with grad n = D / (2 spacing)
   const void* nodes;
   int32_t gnx, gny, gnz, refill;
+  uint32_t local_limit;  // children a wave keeps before publishing globally
   double gorg[3], ginv[3], gmax[3], ghalf[3];
   // limits
   double tol, inv_tol, h_min, h_max, h_init, s_max, t_max, amp_min;
@@ -55,6 +58,7 @@ struct KParams {
   Pool pool;
   int64_t capacity, n_primary;
   QueueCounters* q;
+  int32_t* gq;  // overflow queue: record slots of published secondaries, -1 = not yet
   rt_stats* stats;
 };
 

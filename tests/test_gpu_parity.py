@@ -166,3 +166,36 @@ def test_schedule_independence(gpu, block, refill):
     for f in ("key", "x", "z", "s", "t", "as_re", "n_acc", "status"):
         assert np.array_equal(a[f], b[f]), f
     assert bst["accepted"] == gst["accepted"]
+
+
+@pytest.mark.parametrize("local_queue", [-1, 1, 8])
+def test_secondaries_shared_between_waves(gpu, oracle_lib, local_queue):
+    """Secondaries handed to other waves through the global queue (all of
+    them with local_queue = -1) give the same records as the oracle and as
+    the default schedule."""
+    sc = W.two_layer(rays_per_source=32)
+    t = gpu.rt_tuning(local_queue=local_queue)
+    got, gst, ref, rst, s = run_pair(gpu, oracle_lib, sc, f"spill-{local_queue}", tuning=t)
+    assert gst["spilled"] > 0
+    if local_queue == -1:
+        assert gst["spilled"] == gst["spawned"]
+    base, bst = gpu.trace(sc)
+    a, b = sort_by_key(base), sort_by_key(got)
+    for f in ("key", "x", "z", "s", "t", "as_re", "ap_im", "n_acc", "status"):
+        assert np.array_equal(a[f], b[f]), f
+
+
+def test_two_layer_full_size_sampled(gpu, oracle_lib):
+    """The benchmark workload at full size (1,048,576 primaries, 4
+    generations) in the benchmark's launch configuration; 512 evenly spaced
+    primaries and their whole ray trees are compared with the oracle."""
+    sc = W.two_layer()
+    _announce("twolayer-full", sc)
+    got, gst = gpu.trace(sc)
+    roots = np.arange(0, sc.n_rays, sc.n_rays // 512, dtype=np.int64)
+    ref, rst = oracle_lib.trace(sc, roots=roots)
+    sel = np.isin((got["key"] >> np.uint64(24)).astype(np.int64), roots)
+    sub = {f: a[sel] for f, a in got.items()}
+    summ = compare(sub, ref, sc.limits.tol, label="twolayer-full-sample")
+    print(f"[gpu-case] twolayer-full: {summ}; stats {gst}", flush=True)
+    assert gst["records"] == gst["needed"] and gst["sched_errors"] == 0
