@@ -690,15 +690,19 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
           const uint32_t rank = (uint32_t)__popcll(m & lanemask_lt());
           const uint32_t room = (t - h) < P.local_limit ? P.local_limit - (t - h) : 0u;
           const uint32_t np = min((uint32_t)__popcll(m), room);
-          if (rank < np) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            WQ.ring[(t + rank) % kRing] = (int32_t)c;
-          } else {
-            const uint64_t e = wave_append(&P.q->gq_tail);
-            __hip_atomic_store(&P.gq[e], (int32_t)c, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            C.bump(S_SPILLED);
-          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+          if (rank < np) WQ.ring[(t + rank) % kRing] = (int32_t)c;
           if ((int)__lane_id() == __ffsll((unsigned long long)m) - 1) *WQ.tail = t + np;
+          // The agent-scope release below writes back this XCD's L2; the
+          // wave-uniform guard keeps it off the path when no lane spills.
+          if (__ballot(rank >= np) != 0) {
+            if (rank >= np) {
+              const uint64_t e = wave_append(&P.q->gq_tail);
+              __hip_atomic_store(&P.gq[e], (int32_t)c, __ATOMIC_RELEASE,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+              C.bump(S_SPILLED);
+            }
+          }
         }
       }
     } else {
@@ -869,13 +873,19 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
       }
     }
     // (4) lanes holding an overflow ticket take the ray once it is published
-    if (R.slot < 0 && ticket >= 0) {
-      const int32_t c = __hip_atomic_load(&P.gq[ticket], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (c >= 0) {
+    // (wave-uniform guards keep the agent-scope acquire, an L2 invalidate,
+    // off the common path)
+    if (__ballot(R.slot < 0 && ticket >= 0) != 0) {
+      int32_t c = -1;
+      if (R.slot < 0 && ticket >= 0)
+        c = __hip_atomic_load(&P.gq[ticket], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (__ballot(c >= 0) != 0) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        load_ray<MODEL, FIELD>(P, c, R, C);
-        mode = 0;
-        ticket = -1;
+        if (c >= 0) {
+          load_ray<MODEL, FIELD>(P, c, R, C);
+          mode = 0;
+          ticket = -1;
+        }
       }
     }
     // a ray may end before its first step (path limit reached, no steps left)
