@@ -195,7 +195,7 @@ typedef struct {
                                kernel, or NULL */
   void* ev_trace_end;       /* hipEvent_t recorded just after it, or NULL */
   int32_t local_queue;      /* secondaries a wave keeps for itself before it
-                               hands further ones to other waves: 0 = 512,
+                               hands further ones to other waves: 0 = 256,
                                -1 = none, else 1..1024 */
 } rt_tuning;
 

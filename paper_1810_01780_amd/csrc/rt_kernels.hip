@@ -1300,7 +1300,7 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
     set_last_error("refill_threshold must be 1..64");
     return RT_ERR_INVALID_ARG;
   }
-  int local = tuning && tuning->local_queue ? tuning->local_queue : 512;
+  int local = tuning && tuning->local_queue ? tuning->local_queue : 256;
   if (local == -1) local = 0;
   if (local < 0 || local > (int)kRing) {
     set_last_error("local_queue must be -1, 0 or 1..%d", (int)kRing);
