@@ -187,7 +187,7 @@ typedef struct {
 
 /* Optional launch tuning; NULL selects the defaults. */
 typedef struct {
-  int32_t block_size;       /* threads per block, multiple of 64, 64..1024; 0 = 256 */
+  int32_t block_size;       /* threads per block: 64, 128, 192 or 256; 0 = 256 */
   int32_t blocks_per_cu;    /* resident blocks per CU; 0 = occupancy maximum */
   int32_t refill_threshold; /* a wave refills when at least this many of its
                                64 lanes are idle (1..64); 0 = 16 */
