@@ -227,3 +227,54 @@ def fresnel(n1: float, n2: float, ci: float):
     rs, rp = complex(out[0], out[1]), complex(out[2], out[3])
     ts, tp = complex(out[4], out[5]), complex(out[6], out[7])
     return rs, rp, ts, tp, float(out[8]), bool(tir)
+
+
+# --- emitter -> receiver solves ---------------------------------------------
+class SolveSpec(C.Structure):
+    _fields_ = [("zs", C.POINTER(C.c_double)), ("zr", C.POINTER(C.c_double)),
+                ("dist", C.POINTER(C.c_double)), ("n_scan", C.c_int32),
+                ("max_iter", C.c_int32), ("max_brackets", C.c_int32),
+                ("miss_tol", C.c_double), ("accept_tol", C.c_double)]
+
+
+SOLVE_I32 = ["found", "shots"]
+SOLVE_F64 = ["theta", "miss", "t", "s", "as_re", "as_im", "ap_re", "ap_im"]
+
+
+class SolveOut(C.Structure):
+    _fields_ = ([(f, C.POINTER(C.c_int32)) for f in SOLVE_I32]
+                + [(f, C.POINTER(C.c_double)) for f in SOLVE_F64])
+
+
+def solve(scene, zs, zr, dist, pairs=None, n_scan=64, max_iter=60, max_brackets=4,
+          miss_tol=1e-4, accept_tol=1e-3, threads=None):
+    """Shooting solves for source/receiver pairs; arrays indexed [pair, family]
+    with family 0 = direct, 1 = reflected once at the surface."""
+    L = lib()
+    L.orc_solve.restype = C.c_int
+    L.orc_solve.argtypes = [C.POINTER(Problem), C.POINTER(SolveSpec), C.POINTER(C.c_int64),
+                            C.c_int64, C.POINTER(SolveOut), C.c_int]
+    prep = _Prepared(scene)
+    zs = np.ascontiguousarray(zs, np.float64)
+    zr = np.ascontiguousarray(zr, np.float64)
+    dist = np.ascontiguousarray(dist, np.float64)
+    prep.keep += [zs, zr, dist]
+    spec = SolveSpec(_ptr(zs, C.c_double), _ptr(zr, C.c_double), _ptr(dist, C.c_double),
+                     n_scan, max_iter, max_brackets, miss_tol, accept_tol)
+    n = len(zs)
+    arrs = {f: np.zeros(2 * n, np.int32) for f in SOLVE_I32}
+    arrs.update({f: np.zeros(2 * n, np.float64) for f in SOLVE_F64})
+    out = SolveOut(*([_ptr(arrs[f], C.c_int32) for f in SOLVE_I32]
+                     + [_ptr(arrs[f], C.c_double) for f in SOLVE_F64]))
+    rptr, n_pairs = None, n
+    if pairs is not None:
+        pa = np.ascontiguousarray(pairs, np.int64)
+        prep.keep.append(pa)
+        rptr, n_pairs = _ptr(pa, C.c_int64), len(pa)
+    if threads is None:
+        threads = max(1, min(os.cpu_count() or 1, 16))
+    rc = L.orc_solve(C.byref(prep.P), C.byref(spec), rptr, n_pairs, C.byref(out), threads)
+    if rc != 0:
+        raise ValueError("oracle: unsupported solve problem (planes[0] must be the surface; "
+                         "no box or time limit)")
+    return {f: a.reshape(n, 2) for f, a in arrs.items()}

@@ -96,6 +96,30 @@ void orc_field(const orc_problem* P, int32_t reg, const double r[3], double* n,
  * returns 1 on total internal reflection (t = 0, cos_t = 0). */
 int orc_fresnel(double n1, double n2, double ci, double out[9]);
 
+/* Emitter -> receiver solves (shooting).  Source at (0, 0, zs[i]), receiver
+ * at (dist[i], 0, zr[i]); planes[0] of the problem is the surface, the other
+ * planes are transmitted (reflected under total internal reflection).  For
+ * each pair two families are solved: DIRECT (the ray may not touch the
+ * surface) and REFLECTED (exactly one surface reflection). */
+enum { ORC_FAMILY_DIRECT = 0, ORC_FAMILY_REFLECTED = 1 };
+typedef struct {
+  const double *zs, *zr, *dist;
+  int32_t n_scan;       /* launch angles scanned per family */
+  int32_t max_iter;     /* refinement shots per bracket */
+  int32_t max_brackets; /* sign changes refined per family */
+  double miss_tol;      /* refinement stops at |miss| <= miss_tol (m) */
+  double accept_tol;    /* a root is a solution if |miss| <= accept_tol (m) */
+} orc_solve_spec;
+
+/* Outputs indexed [2 * pair + family]. */
+typedef struct {
+  int32_t *found, *shots;
+  double *theta, *miss, *t, *s, *as_re, *as_im, *ap_re, *ap_im;
+} orc_solve_out;
+
+int orc_solve(const orc_problem* P, const orc_solve_spec* spec, const int64_t* pairs,
+              int64_t n_pairs, orc_solve_out* out, int n_threads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -739,3 +739,321 @@ int orc_trace(const orc_problem* P, const int64_t* roots, int64_t n_roots,
   free(jobs);
   return counter > out->capacity ? -1 : 0;
 }
+
+/* ======================================================================== */
+/* Emitter -> receiver solves by shooting (the paper's "receiver/emitter     */
+/* locations", section 2): for a source and a receiver, find the launch     */
+/* angles of the direct ray and of the ray reflected once at the surface.   */
+
+enum { SHOT_RECV = 0, SHOT_SURF = 1, SHOT_LOST = 2 };
+#define SHOT_MISS_HIGH (-1.0e6) /* ray ended above the receiver (at the surface) */
+#define SHOT_MISS_LOW (1.0e6)   /* ray lost: never reached the receiver plane */
+
+typedef struct {
+  int32_t status;
+  double miss, t, s, as_re, as_im, ap_re, ap_im;
+} shot_t;
+
+/* One branch-following trace at launch angle theta (from the upward vertical,
+ * towards +x).  The receiver plane x = D is the last boundary of S. */
+static shot_t shoot(worker_t* W, const scene_t* S, double zs, double zr, double D, double theta,
+                    int family) {
+  const orc_problem* P = S->P;
+  const int k_recv = S->n_pl - 1;
+  const double z_surf = S->pl[0].d * S->pl[0].nrm[2];
+  const double s_max = 2.0 * (D + zs + zr) + 1000.0;
+  shot_t out;
+  memset(&out, 0, sizeof out);
+  ray_t r;
+  memset(&r, 0, sizeof r);
+  r.y[2] = zs;
+  double u0[3] = {sin(theta), 0.0, -cos(theta)};
+  for (int g = 0; g < P->n_regions; ++g)
+    if (zs >= P->regions[g].z_top && zs < P->regions[g].z_bot) {
+      r.region = g;
+      break;
+    }
+  for (int k = 0; k < S->n_pl; ++k)
+    if (bnd_g(S, k, r.y) > 0.0) r.side |= 1u << k;
+  r.as_re = r.ap_re = 1.0;
+  r.h = P->h_init > 0.0 ? P->h_init : P->h_max;
+  set_direction(P, r.region, r.y, u0);
+  int n_refl = 0;
+  for (;;) {
+    if (r.s >= s_max || (int64_t)r.n_acc + r.n_rej >= P->max_steps) break;
+    double hp = r.h;
+    int clipped = 0;
+    if (s_max - r.s <= hp) {
+      hp = s_max - r.s;
+      clipped = 1;
+    }
+    double y1[7], dl[7];
+    orc_ck_trial(P, r.region, r.y, hp, y1, dl);
+    double err = trial_error(r.y, dl, hp, P->tol);
+    if (!all_finite(y1, 7) || !isfinite(err)) break;
+    if (!(err <= 1.0) && !(hp <= P->h_min)) {
+      r.n_rej++;
+      W->st.rejected++;
+      double f = SAFETY * pow(err, -0.25);
+      if (f < SHRINK_MIN) f = SHRINK_MIN;
+      r.h = clamp_h(P, hp * f);
+      continue;
+    }
+    r.n_acc++;
+    W->st.accepted++;
+    double f = err < ERRCON ? GROW_MAX : SAFETY * pow(err, -0.2);
+    double h_next = clamp_h(P, hp * f);
+    if (P->model == ORC_MODEL_PAPER) {
+      double u[3];
+      unit_direction(y1, u);
+      y1[3] = u[0];
+      y1[4] = u[1];
+      y1[5] = u[2];
+    }
+    double G0, G1;
+    int k = pick_crossing(S, &r, r.y, y1, hp, -1, &G0, &G1);
+    if (k < 0) {
+      memcpy(r.y, y1, sizeof y1);
+      r.s = clipped ? s_max : r.s + hp;
+      r.h = h_next;
+      continue;
+    }
+    double ystar[7], sig;
+    if (G0 <= 0.0) {
+      sig = 0.0;
+      memcpy(ystar, r.y, sizeof ystar);
+    } else {
+      sig = locate(W, &r, k, 0.0, G0, hp, G1, hp, ystar);
+    }
+    for (int pass = 0; pass < LOC_MAXPASS; ++pass) {
+      double H0, H1;
+      int j = pick_crossing(S, &r, r.y, ystar, sig, k, &H0, &H1);
+      if (j < 0) break;
+      k = j;
+      if (H0 <= 0.0) {
+        sig = 0.0;
+        memcpy(ystar, r.y, sizeof ystar);
+      } else {
+        sig = locate(W, &r, k, 0.0, H0, sig, H1, hp, ystar);
+      }
+    }
+    const bplane_t* b = &S->pl[k];
+    if (b->kind != KIND_TIME) {
+      double g = bnd_g(S, k, ystar);
+      for (int i = 0; i < 3; ++i) ystar[i] -= g * b->nrm[i];
+    }
+    {
+      double u[3];
+      unit_direction(ystar, u);
+      memcpy(r.y, ystar, sizeof ystar);
+      set_direction(P, r.region, r.y, u);
+    }
+    r.s = r.s + sig;
+    r.h = h_next;
+    if (k == k_recv) {
+      /* before its reflection a ray of the reflected family is measured in
+       * the mirror image of the surface */
+      double z = r.y[2];
+      if (family == ORC_FAMILY_REFLECTED && n_refl == 0) z = 2.0 * z_surf - z;
+      out.status = SHOT_RECV;
+      out.miss = z - zr;
+      out.t = r.y[6];
+      out.s = r.s;
+      out.as_re = r.as_re;
+      out.as_im = r.as_im;
+      out.ap_re = r.ap_re;
+      out.ap_im = r.ap_im;
+      return out;
+    }
+    if (b->kind != KIND_FRESNEL) break; /* box, time or absorbing plane */
+    const int surface = (k == 0);
+    if (surface && (family == ORC_FAMILY_DIRECT || n_refl > 0)) {
+      out.status = SHOT_SURF;
+      out.miss = SHOT_MISS_HIGH;
+      return out;
+    }
+    /* Fresnel at the plane: reflect at the surface, transmit at a layer
+     * (reflect when totally reflected) */
+    double sgn = side_sign(&r, k);
+    double nin[3] = {sgn * b->nrm[0], sgn * b->nrm[1], sgn * b->nrm[2]};
+    double u[3];
+    unit_direction(r.y, u);
+    double ci = -(u[0] * nin[0] + u[1] * nin[1] + u[2] * nin[2]);
+    if (ci < 0.0) ci = 0.0;
+    int reg_out = sgn > 0.0 ? b->reg_neg : b->reg_pos;
+    double n1, n2, gtmp[3];
+    orc_field(P, r.region, r.y, &n1, gtmp);
+    orc_field(P, reg_out, r.y, &n2, gtmp);
+    double fr[9];
+    int tir = orc_fresnel(n1, n2, ci, fr);
+    if (surface || tir) {
+      double ur[3];
+      for (int i = 0; i < 3; ++i) ur[i] = u[i] + 2.0 * ci * nin[i];
+      double are = r.as_re * fr[0] - r.as_im * fr[1];
+      double aim = r.as_re * fr[1] + r.as_im * fr[0];
+      double pre = r.ap_re * fr[2] - r.ap_im * fr[3];
+      double pim = r.ap_re * fr[3] + r.ap_im * fr[2];
+      r.as_re = are;
+      r.as_im = aim;
+      r.ap_re = pre;
+      r.ap_im = pim;
+      set_direction(P, r.region, r.y, ur);
+      if (surface) n_refl++;
+    } else {
+      double eta = n1 / n2, ut[3];
+      for (int i = 0; i < 3; ++i) ut[i] = eta * u[i] + (eta * ci - fr[8]) * nin[i];
+      double are = r.as_re * fr[4] - r.as_im * fr[5];
+      double aim = r.as_re * fr[5] + r.as_im * fr[4];
+      double pre = r.ap_re * fr[6] - r.ap_im * fr[7];
+      double pim = r.ap_re * fr[7] + r.ap_im * fr[6];
+      r.as_re = are;
+      r.as_im = aim;
+      r.ap_re = pre;
+      r.ap_im = pim;
+      r.region = reg_out;
+      r.side ^= 1u << k;
+      set_direction(P, r.region, r.y, ut);
+    }
+  }
+  out.status = SHOT_LOST;
+  out.miss = SHOT_MISS_LOW;
+  return out;
+}
+
+static int miss_sign(double m) { return m < 0.0 ? -1 : 1; }
+
+/* Refine a bracket [a, b] of the miss by Illinois false position (plain
+ * bisection while an end is a failed shot). */
+static shot_t refine(worker_t* W, const scene_t* S, const orc_solve_spec* sp, double zs, double zr,
+                     double D, int family, double a, double Ga, double b, double Gb,
+                     double* theta, int* shots) {
+  shot_t sh;
+  memset(&sh, 0, sizeof sh);
+  sh.status = SHOT_LOST;
+  int last = 0;
+  double c = a;
+  for (int it = 0; it < sp->max_iter; ++it) {
+    if (fabs(Ga) >= 1.0e5 || fabs(Gb) >= 1.0e5)
+      c = 0.5 * (a + b);
+    else
+      c = b - Gb * (b - a) / (Gb - Ga);
+    sh = shoot(W, S, zs, zr, D, c, family);
+    ++*shots;
+    if (sh.status == SHOT_RECV && fabs(sh.miss) <= sp->miss_tol) break;
+    if (miss_sign(sh.miss) == miss_sign(Ga)) {
+      a = c;
+      Ga = sh.miss;
+      if (last == 1) Gb *= 0.5;
+      last = 1;
+    } else {
+      b = c;
+      Gb = sh.miss;
+      if (last == -1) Ga *= 0.5;
+      last = -1;
+    }
+    if (fabs(b - a) <= 1e-13) break;
+  }
+  *theta = c;
+  return sh;
+}
+
+typedef struct {
+  const scene_t* base;
+  const orc_solve_spec* sp;
+  const int64_t* pairs;
+  int64_t n;
+  int64_t* next;
+  orc_solve_out* out;
+  worker_t W;
+  pthread_t th;
+} solve_job_t;
+
+static void solve_one(worker_t* W, const scene_t* base, const orc_solve_spec* sp, int64_t i,
+                      orc_solve_out* out) {
+  const double zs = sp->zs[i], zr = sp->zr[i], D = sp->dist[i];
+  scene_t S = *base;
+  /* receiver plane x = D: g = D - x > 0 on the source side */
+  bplane_t* rp = &S.pl[S.n_pl++];
+  memset(rp, 0, sizeof *rp);
+  rp->nrm[0] = -1.0;
+  rp->d = -D;
+  rp->kind = KIND_ABSORB;
+  const scene_t* saved = W->S; /* crossing location reads the worker's scene */
+  W->S = &S;
+  for (int family = 0; family < 2; ++family) {
+    const int64_t o = 2 * i + family;
+    int shots = 0, found = 0, brackets = 0;
+    double best_theta = 0.0;
+    shot_t best;
+    memset(&best, 0, sizeof best);
+    shot_t prev;
+    double th_prev = 0.0;
+    for (int k = 0; k < sp->n_scan; ++k) {
+      double th = (k + 0.5) * (3.14159265358979323846 / sp->n_scan);
+      shot_t sh = shoot(W, &S, zs, zr, D, th, family);
+      ++shots;
+      if (k > 0 && miss_sign(sh.miss) != miss_sign(prev.miss)) {
+        double root;
+        shot_t rs = refine(W, &S, sp, zs, zr, D, family, th_prev, prev.miss, th, sh.miss, &root,
+                           &shots);
+        if (rs.status == SHOT_RECV && fabs(rs.miss) <= sp->accept_tol &&
+            (!found || rs.t < best.t)) {
+          best = rs;
+          best_theta = root;
+          found = 1;
+        }
+        if (++brackets >= sp->max_brackets) break;
+      }
+      prev = sh;
+      th_prev = th;
+    }
+    out->found[o] = found;
+    out->shots[o] = shots;
+    out->theta[o] = found ? best_theta : 0.0;
+    out->miss[o] = best.miss;
+    out->t[o] = best.t;
+    out->s[o] = best.s;
+    out->as_re[o] = best.as_re;
+    out->as_im[o] = best.as_im;
+    out->ap_re[o] = best.ap_re;
+    out->ap_im[o] = best.ap_im;
+  }
+  W->S = saved;
+}
+
+static void* run_solve(void* arg) {
+  solve_job_t* J = (solve_job_t*)arg;
+  for (;;) {
+    int64_t j = __atomic_fetch_add(J->next, 1, __ATOMIC_RELAXED);
+    if (j >= J->n) break;
+    solve_one(&J->W, J->base, J->sp, J->pairs ? J->pairs[j] : j, J->out);
+  }
+  return NULL;
+}
+
+int orc_solve(const orc_problem* P, const orc_solve_spec* sp, const int64_t* pairs,
+              int64_t n_pairs, orc_solve_out* out, int n_threads) {
+  if (P->n_planes < 1 || P->n_planes > 16 || P->has_box || P->t_max > 0.0) return -2;
+  scene_t S;
+  build_scene(P, &S);
+  if (n_threads < 1) n_threads = 1;
+  int64_t next = 0;
+  solve_job_t* jobs = (solve_job_t*)calloc((size_t)n_threads, sizeof(solve_job_t));
+  for (int t = 0; t < n_threads; ++t) {
+    jobs[t].base = &S;
+    jobs[t].sp = sp;
+    jobs[t].pairs = pairs;
+    jobs[t].n = n_pairs;
+    jobs[t].next = &next;
+    jobs[t].out = out;
+    jobs[t].W.S = &S;
+  }
+  if (n_threads == 1) {
+    run_solve(&jobs[0]);
+  } else {
+    for (int t = 0; t < n_threads; ++t) pthread_create(&jobs[t].th, NULL, run_solve, &jobs[t]);
+    for (int t = 0; t < n_threads; ++t) pthread_join(jobs[t].th, NULL);
+  }
+  free(jobs);
+  return 0;
+}

@@ -269,6 +269,33 @@ def paper_example(n_rays: int = 512, generations: int = 4,
                                max_generations=generations, model=model))
 
 
+@dataclasses.dataclass
+class SolvePairs:
+    """Emitter -> receiver pairs: source at (0, 0, zs), receiver at
+    (dist, 0, zr); scene gives the medium (planes[0] is the surface)."""
+    scene: Scene
+    zs: np.ndarray
+    zr: np.ndarray
+    dist: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.zs.shape[0])
+
+
+def solve_pairs(n_pairs: int = 65536, model: int = MODEL_PAPER) -> SolvePairs:
+    """Seeded source/receiver pairs in the two-layer firn model: source depth
+    50-2000 m, receiver depth 0-200 m, horizontal distance 10 m-3 km, all
+    uniform.  Each pair is solved for its direct and its surface-reflected
+    ray."""
+    rng = _rng(3)
+    zs = rng.uniform(50.0, 2000.0, size=n_pairs)
+    zr = rng.uniform(0.0, 200.0, size=n_pairs)
+    dist = rng.uniform(10.0, 3000.0, size=n_pairs)
+    scene = two_layer(rays_per_source=1, n_sources=1, generations=1, model=model)
+    return SolvePairs(scene=scene, zs=zs, zr=zr, dist=dist)
+
+
 WORKLOADS = {
     "fan1024": point_source_fan,
     "twolayer": two_layer,
