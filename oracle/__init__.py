@@ -278,3 +278,39 @@ def solve(scene, zs, zr, dist, pairs=None, n_scan=64, max_iter=60, max_brackets=
         raise ValueError("oracle: unsupported solve problem (planes[0] must be the surface; "
                          "no box or time limit)")
     return {f: a.reshape(n, 2) for f, a in arrs.items()}
+
+
+SHOT_I32 = ["status", "n_acc", "n_rej"]
+SHOT_F64 = ["miss", "t", "s", "as_re", "as_im", "ap_re", "ap_im"]
+
+
+class ShotOut(C.Structure):
+    _fields_ = ([(f, C.POINTER(C.c_int32)) for f in SHOT_I32]
+                + [(f, C.POINTER(C.c_double)) for f in SHOT_F64])
+
+
+def shoot(scene, zs, zr, dist, theta, family, threads=None):
+    """Single shots (the building block of solve): status 0 receiver plane,
+    1 surface touched where the family forbids it, 2 lost, 3 invalid."""
+    L = lib()
+    L.orc_shoot.restype = C.c_int
+    L.orc_shoot.argtypes = [C.POINTER(Problem)] + [C.POINTER(C.c_double)] * 4 + [
+        C.POINTER(C.c_int32), C.c_int64, C.POINTER(ShotOut), C.c_int]
+    prep = _Prepared(scene)
+    cols = [np.ascontiguousarray(a, np.float64) for a in (zs, zr, dist, theta)]
+    fam = np.ascontiguousarray(family, np.int32)
+    n = len(cols[0])
+    assert all(len(c) == n for c in cols) and len(fam) == n
+    prep.keep += cols + [fam]
+    arrs = {f: np.zeros(n, np.int32) for f in SHOT_I32}
+    arrs.update({f: np.zeros(n, np.float64) for f in SHOT_F64})
+    out = ShotOut(*([_ptr(arrs[f], C.c_int32) for f in SHOT_I32]
+                    + [_ptr(arrs[f], C.c_double) for f in SHOT_F64]))
+    if threads is None:
+        threads = max(1, min(os.cpu_count() or 1, 16))
+    rc = L.orc_shoot(C.byref(prep.P), *[_ptr(c, C.c_double) for c in cols],
+                     _ptr(fam, C.c_int32), n, C.byref(out), threads)
+    if rc != 0:
+        raise ValueError("oracle: unsupported shoot problem (planes[0] must be the surface; "
+                         "no box or time limit)")
+    return arrs

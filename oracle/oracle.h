@@ -120,6 +120,19 @@ typedef struct {
 int orc_solve(const orc_problem* P, const orc_solve_spec* spec, const int64_t* pairs,
               int64_t n_pairs, orc_solve_out* out, int n_threads);
 
+/* Single shots: status 0 = reached the receiver plane (miss = depth - zr,
+ * mirrored before the surface reflection for the reflected family), 1 =
+ * touched the surface where the family forbids it (miss = -1e6), 2 = never
+ * reached the receiver plane (miss = +1e6), 3 = invalid input. */
+typedef struct {
+  int32_t *status, *n_acc, *n_rej;
+  double *miss, *t, *s, *as_re, *as_im, *ap_re, *ap_im;
+} orc_shot_out;
+
+int orc_shoot(const orc_problem* P, const double* zs, const double* zr, const double* dist,
+              const double* theta, const int32_t* family, int64_t n, orc_shot_out* out,
+              int n_threads);
+
 #ifdef __cplusplus
 }
 #endif

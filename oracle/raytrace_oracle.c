@@ -745,14 +745,35 @@ int orc_trace(const orc_problem* P, const int64_t* roots, int64_t n_roots,
 /* locations", section 2): for a source and a receiver, find the launch     */
 /* angles of the direct ray and of the ray reflected once at the surface.   */
 
-enum { SHOT_RECV = 0, SHOT_SURF = 1, SHOT_LOST = 2 };
+enum { SHOT_RECV = 0, SHOT_SURF = 1, SHOT_LOST = 2, SHOT_INVALID = 3 };
 #define SHOT_MISS_HIGH (-1.0e6) /* ray ended above the receiver (at the surface) */
 #define SHOT_MISS_LOW (1.0e6)   /* ray lost: never reached the receiver plane */
 
 typedef struct {
-  int32_t status;
+  int32_t status, n_acc, n_rej;
   double miss, t, s, as_re, as_im, ap_re, ap_im;
 } shot_t;
+
+/* A source/receiver pair can be shot if every value is finite, the distance
+ * is positive and the source is not within 1e-9 m of a plane (its side of
+ * every plane must be defined). */
+static int pair_ok(const scene_t* S, double zs, double zr, double D) {
+  if (!isfinite(zs) || !isfinite(zr) || !isfinite(D) || !(D > 0.0)) return 0;
+  const double y[7] = {0.0, 0.0, zs, 0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < S->n_pl; ++k)
+    if (fabs(bnd_g(S, k, y)) <= 1e-9) return 0;
+  return 1;
+}
+
+/* Append the receiver plane x = D to a copy of the base scene:
+ * g = D - x > 0 on the source side. */
+static void add_receiver(scene_t* S, double D) {
+  bplane_t* rp = &S->pl[S->n_pl++];
+  memset(rp, 0, sizeof *rp);
+  rp->nrm[0] = -1.0;
+  rp->d = -D;
+  rp->kind = KIND_ABSORB;
+}
 
 /* One branch-following trace at launch angle theta (from the upward vertical,
  * towards +x).  The receiver plane x = D is the last boundary of S. */
@@ -856,6 +877,8 @@ static shot_t shoot(worker_t* W, const scene_t* S, double zs, double zr, double 
       double z = r.y[2];
       if (family == ORC_FAMILY_REFLECTED && n_refl == 0) z = 2.0 * z_surf - z;
       out.status = SHOT_RECV;
+      out.n_acc = r.n_acc;
+      out.n_rej = r.n_rej;
       out.miss = z - zr;
       out.t = r.y[6];
       out.s = r.s;
@@ -869,6 +892,8 @@ static shot_t shoot(worker_t* W, const scene_t* S, double zs, double zr, double 
     const int surface = (k == 0);
     if (surface && (family == ORC_FAMILY_DIRECT || n_refl > 0)) {
       out.status = SHOT_SURF;
+      out.n_acc = r.n_acc;
+      out.n_rej = r.n_rej;
       out.miss = SHOT_MISS_HIGH;
       return out;
     }
@@ -916,6 +941,8 @@ static shot_t shoot(worker_t* W, const scene_t* S, double zs, double zr, double 
     }
   }
   out.status = SHOT_LOST;
+  out.n_acc = r.n_acc;
+  out.n_rej = r.n_rej;
   out.miss = SHOT_MISS_LOW;
   return out;
 }
@@ -971,13 +998,17 @@ typedef struct {
 static void solve_one(worker_t* W, const scene_t* base, const orc_solve_spec* sp, int64_t i,
                       orc_solve_out* out) {
   const double zs = sp->zs[i], zr = sp->zr[i], D = sp->dist[i];
+  if (!pair_ok(base, zs, zr, D)) {
+    for (int family = 0; family < 2; ++family) {
+      const int64_t o = 2 * i + family;
+      out->found[o] = out->shots[o] = 0;
+      out->theta[o] = out->miss[o] = out->t[o] = out->s[o] = 0.0;
+      out->as_re[o] = out->as_im[o] = out->ap_re[o] = out->ap_im[o] = 0.0;
+    }
+    return;
+  }
   scene_t S = *base;
-  /* receiver plane x = D: g = D - x > 0 on the source side */
-  bplane_t* rp = &S.pl[S.n_pl++];
-  memset(rp, 0, sizeof *rp);
-  rp->nrm[0] = -1.0;
-  rp->d = -D;
-  rp->kind = KIND_ABSORB;
+  add_receiver(&S, D);
   const scene_t* saved = W->S; /* crossing location reads the worker's scene */
   W->S = &S;
   for (int family = 0; family < 2; ++family) {
@@ -1029,6 +1060,83 @@ static void* run_solve(void* arg) {
     solve_one(&J->W, J->base, J->sp, J->pairs ? J->pairs[j] : j, J->out);
   }
   return NULL;
+}
+
+typedef struct {
+  const scene_t* base;
+  const double *zs, *zr, *dist, *theta;
+  const int32_t* family;
+  int64_t n;
+  int64_t* next;
+  orc_shot_out* out;
+  worker_t W;
+  pthread_t th;
+} shoot_job_t;
+
+static void* run_shoot(void* arg) {
+  shoot_job_t* J = (shoot_job_t*)arg;
+  for (;;) {
+    int64_t i = __atomic_fetch_add(J->next, 1, __ATOMIC_RELAXED);
+    if (i >= J->n) break;
+    const double zs = J->zs[i], zr = J->zr[i], D = J->dist[i], th = J->theta[i];
+    const int32_t fam = J->family[i];
+    shot_t sh;
+    memset(&sh, 0, sizeof sh);
+    if (!pair_ok(J->base, zs, zr, D) || !(th > 0.0 && th < 3.14159265358979323846) ||
+        (fam != ORC_FAMILY_DIRECT && fam != ORC_FAMILY_REFLECTED)) {
+      sh.status = SHOT_INVALID;
+    } else {
+      scene_t S = *J->base;
+      add_receiver(&S, D);
+      J->W.S = &S;
+      sh = shoot(&J->W, &S, zs, zr, D, th, fam);
+      J->W.S = J->base;
+    }
+    orc_shot_out* o = J->out;
+    o->status[i] = sh.status;
+    o->n_acc[i] = sh.n_acc;
+    o->n_rej[i] = sh.n_rej;
+    o->miss[i] = sh.miss;
+    o->t[i] = sh.t;
+    o->s[i] = sh.s;
+    o->as_re[i] = sh.as_re;
+    o->as_im[i] = sh.as_im;
+    o->ap_re[i] = sh.ap_re;
+    o->ap_im[i] = sh.ap_im;
+  }
+  return NULL;
+}
+
+int orc_shoot(const orc_problem* P, const double* zs, const double* zr, const double* dist,
+              const double* theta, const int32_t* family, int64_t n, orc_shot_out* out,
+              int n_threads) {
+  if (P->n_planes < 1 || P->n_planes > 16 || P->has_box || P->t_max > 0.0) return -2;
+  scene_t S;
+  build_scene(P, &S);
+  if (n_threads < 1) n_threads = 1;
+  int64_t next = 0;
+  shoot_job_t* jobs = (shoot_job_t*)calloc((size_t)n_threads, sizeof(shoot_job_t));
+  for (int t = 0; t < n_threads; ++t) {
+    shoot_job_t* J = &jobs[t];
+    J->base = &S;
+    J->zs = zs;
+    J->zr = zr;
+    J->dist = dist;
+    J->theta = theta;
+    J->family = family;
+    J->n = n;
+    J->next = &next;
+    J->out = out;
+    J->W.S = &S;
+  }
+  if (n_threads == 1) {
+    run_shoot(&jobs[0]);
+  } else {
+    for (int t = 0; t < n_threads; ++t) pthread_create(&jobs[t].th, NULL, run_shoot, &jobs[t]);
+    for (int t = 0; t < n_threads; ++t) pthread_join(jobs[t].th, NULL);
+  }
+  free(jobs);
+  return 0;
 }
 
 int orc_solve(const orc_problem* P, const orc_solve_spec* sp, const int64_t* pairs,

@@ -141,3 +141,57 @@ def test_two_layer_pairs_are_solutions(oracle_lib):
     both = ok[:, 0] & ok[:, 1]
     assert both.sum() > 5
     assert np.all(r["t"][both, 1] > r["t"][both, 0])
+
+
+def test_constant_medium_shots(oracle_lib):
+    """Single shots in a constant medium are straight lines: the depth at the
+    receiver plane, the surface contact and the mirrored miss of the
+    reflected family follow from elementary geometry."""
+    n = 1.5
+    sc = two_media(W.Region(a=n, z_top=0.0))
+    zs, zr, D = 300.0, 80.0, 400.0
+    th = np.linspace(0.05, math.pi - 0.05, 41)
+    m = len(th)
+    for fam in (0, 1):
+        r = oracle_lib.shoot(sc, np.full(m, zs), np.full(m, zr), np.full(m, D), th,
+                             np.full(m, fam))
+        z_line = zs - D / np.tan(th)          # depth of the straight line at x = D
+        hits_surface = z_line < 0.0          # the line crosses z = 0 before x = D
+        L = D / np.sin(th)
+        for i in range(m):
+            if fam == 0 and hits_surface[i]:
+                assert r["status"][i] == 1 and r["miss"][i] == -1e6
+                continue
+            if L[i] > 2 * (D + zs + zr) + 1000.0:   # beyond the shot's path limit
+                assert r["status"][i] == 2 and r["miss"][i] == 1e6
+                continue
+            assert r["status"][i] == 0, i
+            # reflected family: mirror image (before or after the reflection)
+            want = z_line[i] - zr if fam == 0 else -z_line[i] - zr
+            assert r["miss"][i] == pytest.approx(want, abs=1e-6), i
+            assert r["s"][i] == pytest.approx(L[i], rel=1e-9), i
+            assert r["t"][i] * C0 == pytest.approx(n * L[i], rel=1e-9), i
+            if fam == 1 and hits_surface[i]:
+                ci = math.cos(th[i])
+                st2 = n * n * (1 - ci * ci)
+                if st2 < 1:
+                    ct = math.sqrt(1 - st2)
+                    assert r["as_re"][i] == pytest.approx((n * ci - ct) / (n * ci + ct), abs=1e-9)
+                else:
+                    assert math.hypot(r["as_re"][i], r["as_im"][i]) == pytest.approx(1.0, abs=1e-12)
+            else:
+                assert r["as_re"][i] == 1.0 and r["as_im"][i] == 0.0
+
+
+def test_invalid_shots(oracle_lib):
+    sc = two_media(W.Region(a=1.5, z_top=0.0))
+    zs = [300.0, 300.0, 300.0, 300.0, 0.0, float("nan"), 300.0]
+    zr = [50.0] * 7
+    D = [0.0, 100.0, 100.0, 100.0, 100.0, 100.0, 100.0]
+    th = [1.0, 0.0, math.pi, 1.0, 1.0, 1.0, 1.0]
+    fam = [0, 0, 0, 2, 0, 0, 1]
+    r = oracle_lib.shoot(sc, zs, zr, D, th, fam)
+    assert r["status"].tolist() == [3, 3, 3, 3, 3, 3, 0]
+    s = oracle_lib.solve(sc, [300.0, 0.0], [50.0, 50.0], [100.0, 100.0])
+    assert s["found"][0].tolist() == [1, 1] and s["found"][1].tolist() == [0, 0]
+    assert s["shots"][1].tolist() == [0, 0]
