@@ -1,8 +1,11 @@
-"""Thin ctypes binding of the radiotrace C ABI (include/radiotrace.h).
+"""Thin ctypes binding of the radiotrace C ABI (include/radiotrace.h and
+include/radiotrace_solve.h).
 
 The functions carry the C names (rt_abi_version, rt_validate,
-rt_workspace_bytes, raytrace_launch, rt_collect, rt_last_error) and only
-marshal arguments; every step of the tracing runs in the HIP kernels.  PyTorch
+rt_workspace_bytes, raytrace_launch, rt_collect, rt_last_error,
+rt_solve_validate, rt_solve_workspace_bytes, raytrace_solve, raytrace_shoot)
+and only marshal arguments; every step of the tracing and solving runs in the
+HIP kernels.  PyTorch
 supplies device memory and the stream.  The library must have been built
 (``paper_1810_01780_amd.build.build()``); there is no fallback.
 """
@@ -91,6 +94,49 @@ class rt_tuning(C.Structure):
                 ("ev_trace_end", C.c_void_p), ("local_queue", C.c_int32)]
 
 
+# --- emitter -> receiver solves (include/radiotrace_solve.h) -----------------
+RT_FAMILY_DIRECT, RT_FAMILY_REFLECTED = 0, 1
+RT_SHOT_RECEIVER, RT_SHOT_SURFACE, RT_SHOT_LOST, RT_SHOT_INVALID = range(4)
+
+
+class rt_pairs(C.Structure):
+    _fields_ = [("zs", C.c_void_p), ("zr", C.c_void_p), ("dist", C.c_void_p), ("n", C.c_int64)]
+
+
+class rt_solve_params(C.Structure):
+    _fields_ = [("n_scan", C.c_int32), ("max_iter", C.c_int32), ("max_brackets", C.c_int32),
+                ("miss_tol", C.c_double), ("accept_tol", C.c_double)]
+
+
+SOLVE_STAT_FIELDS = ["shots", "accepted", "rejected", "relocation", "forced", "events",
+                     "brackets", "found", "invalid"]
+
+
+class rt_solve_stats(C.Structure):
+    _fields_ = [(f, C.c_int64) for f in SOLVE_STAT_FIELDS]
+
+
+SOLVE_I32 = ["found", "shots"]
+SOLVE_F64 = ["theta", "miss", "t", "s", "as_re", "as_im", "ap_re", "ap_im"]
+
+
+class rt_solve_outputs(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in SOLVE_I32 + SOLVE_F64] + [("stats", C.c_void_p)]
+
+
+class rt_shots(C.Structure):
+    _fields_ = [("zs", C.c_void_p), ("zr", C.c_void_p), ("dist", C.c_void_p),
+                ("theta", C.c_void_p), ("family", C.c_void_p), ("n", C.c_int64)]
+
+
+SHOT_I32 = ["status", "n_acc", "n_rej"]
+SHOT_F64 = ["miss", "t", "s", "as_re", "as_im", "ap_re", "ap_im"]
+
+
+class rt_shot_outputs(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in SHOT_I32 + SHOT_F64] + [("stats", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -126,6 +172,24 @@ def lib() -> C.CDLL:
         L.rt_collect.argtypes = [C.POINTER(rt_stats), C.c_int64]
         L.rt_last_error.restype = C.c_char_p
         L.rt_last_error.argtypes = []
+        L.rt_solve_validate.restype = C.c_int
+        L.rt_solve_validate.argtypes = [C.POINTER(rt_field), C.POINTER(rt_boundaries),
+                                        C.c_double, C.POINTER(rt_step_limits),
+                                        C.POINTER(rt_solve_params)]
+        L.rt_solve_workspace_bytes.restype = C.c_int
+        L.rt_solve_workspace_bytes.argtypes = [C.POINTER(rt_field), C.c_int64,
+                                               C.POINTER(rt_solve_params),
+                                               C.POINTER(C.c_size_t)]
+        L.raytrace_solve.restype = C.c_int
+        L.raytrace_solve.argtypes = [C.POINTER(rt_field), C.POINTER(rt_boundaries), C.c_double,
+                                     C.POINTER(rt_step_limits), C.POINTER(rt_pairs),
+                                     C.POINTER(rt_solve_params), C.POINTER(rt_solve_outputs),
+                                     C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(rt_tuning)]
+        L.raytrace_shoot.restype = C.c_int
+        L.raytrace_shoot.argtypes = [C.POINTER(rt_field), C.POINTER(rt_boundaries), C.c_double,
+                                     C.POINTER(rt_step_limits), C.POINTER(rt_shots),
+                                     C.POINTER(rt_shot_outputs), C.c_void_p, C.c_size_t,
+                                     C.c_void_p, C.POINTER(rt_tuning)]
         _lib = L
     return _lib
 
@@ -283,3 +347,127 @@ def trace(scene: W.Scene, capacity: Optional[int] = None, tuning: Optional[rt_tu
     ds = DeviceScene(scene, capacity=capacity)
     ds.launch(tuning=tuning)
     return ds.collect(check=check)
+
+
+# --- emitter -> receiver solves: C entry points and device-side helpers -------
+def rt_solve_validate(field, boundaries, tol, limits, params=None) -> int:
+    return int(lib().rt_solve_validate(C.byref(field), C.byref(boundaries), float(tol),
+                                       C.byref(limits),
+                                       C.byref(params) if params is not None else None))
+
+
+def rt_solve_workspace_bytes(field, n_pairs: int, params=None) -> int:
+    n = C.c_size_t(0)
+    st = lib().rt_solve_workspace_bytes(C.byref(field), C.c_int64(n_pairs),
+                                        C.byref(params) if params is not None else None,
+                                        C.byref(n))
+    if st != RT_OK:
+        raise RTError(st, rt_last_error())
+    return int(n.value)
+
+
+def raytrace_solve(field, boundaries, tol, limits, pairs, params, outputs, workspace,
+                   workspace_bytes, stream, tuning=None) -> int:
+    return int(lib().raytrace_solve(
+        C.byref(field), C.byref(boundaries), float(tol), C.byref(limits), C.byref(pairs),
+        C.byref(params), C.byref(outputs), C.c_void_p(workspace), C.c_size_t(workspace_bytes),
+        C.c_void_p(stream), C.byref(tuning) if tuning is not None else None))
+
+
+def raytrace_shoot(field, boundaries, tol, limits, shots, outputs, workspace, workspace_bytes,
+                   stream, tuning=None) -> int:
+    return int(lib().raytrace_shoot(
+        C.byref(field), C.byref(boundaries), float(tol), C.byref(limits), C.byref(shots),
+        C.byref(outputs), C.c_void_p(workspace), C.c_size_t(workspace_bytes),
+        C.c_void_p(stream), C.byref(tuning) if tuning is not None else None))
+
+
+def solve_params(n_scan=64, max_iter=60, max_brackets=4, miss_tol=1e-4, accept_tol=1e-3):
+    return rt_solve_params(n_scan, max_iter, max_brackets, miss_tol, accept_tol)
+
+
+class DeviceSolve:
+    """Device-resident pairs, outputs and workspace for solving source /
+    receiver pairs in a scene's medium (planes[0] = surface), reusable across
+    launches and capturable into a graph."""
+
+    def __init__(self, scene: W.Scene, zs, zr, dist, params: Optional[rt_solve_params] = None,
+                 device="cuda"):
+        import torch
+        self.torch = torch
+        self.desc = HostDescriptors(scene)
+        dev = torch.device(device)
+        self.device = dev
+        self.params = params if params is not None else solve_params()
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.zs = torch.as_tensor(np.ascontiguousarray(zs, np.float64), device=dev)
+        self.zr = torch.as_tensor(np.ascontiguousarray(zr, np.float64), device=dev)
+        self.dist = torch.as_tensor(np.ascontiguousarray(dist, np.float64), device=dev)
+        n = int(self.zs.shape[0])
+        self.n = n
+        self.pairs = rt_pairs(self.zs.data_ptr(), self.zr.data_ptr(), self.dist.data_ptr(), n)
+        m = max(1, 2 * n)
+        self.res = {f: torch.zeros(m, dtype=torch.int32, device=dev) for f in SOLVE_I32}
+        self.res.update({f: torch.zeros(m, **f64) for f in SOLVE_F64})
+        self.stats_dev = torch.zeros(len(SOLVE_STAT_FIELDS), dtype=torch.int64, device=dev)
+        self.out = rt_solve_outputs(*([self.res[f].data_ptr() for f in SOLVE_I32 + SOLVE_F64]
+                                      + [self.stats_dev.data_ptr()]))
+        self.ws_bytes = rt_solve_workspace_bytes(self.desc.field, n, self.params)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+
+    def launch(self, stream=None, tuning: Optional[rt_tuning] = None) -> None:
+        torch = self.torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        st = raytrace_solve(self.desc.field, self.desc.bnd, self.desc.tol, self.desc.limits,
+                            self.pairs, self.params, self.out, self.workspace.data_ptr(),
+                            self.ws_bytes, stream.cuda_stream, tuning)
+        if st != RT_OK:
+            raise RTError(st, rt_last_error())
+
+    def stats(self) -> Dict[str, int]:
+        v = self.stats_dev.cpu().numpy()
+        return {f: int(v[i]) for i, f in enumerate(SOLVE_STAT_FIELDS)}
+
+    def collect(self):
+        """Synchronise; results as numpy arrays shaped (n, 2) [pair, family]."""
+        self.torch.cuda.synchronize(self.device)
+        out = {f: t[:2 * self.n].cpu().numpy().reshape(self.n, 2) for f, t in self.res.items()}
+        return out, self.stats()
+
+
+def solve(scene: W.Scene, zs, zr, dist, params: Optional[rt_solve_params] = None,
+          tuning: Optional[rt_tuning] = None):
+    """Solve source/receiver pairs on the GPU; returns (results shaped
+    (n, 2), stats)."""
+    ds = DeviceSolve(scene, zs, zr, dist, params)
+    ds.launch(tuning=tuning)
+    return ds.collect()
+
+
+def shoot(scene: W.Scene, zs, zr, dist, theta, family, tuning: Optional[rt_tuning] = None):
+    """Single shots on the GPU; returns (per-shot results, stats)."""
+    import torch
+    desc = HostDescriptors(scene)
+    dev = torch.device("cuda")
+    cols = [torch.as_tensor(np.ascontiguousarray(a, np.float64), device=dev)
+            for a in (zs, zr, dist, theta)]
+    fam = torch.as_tensor(np.ascontiguousarray(family, np.int32), device=dev)
+    n = int(cols[0].shape[0])
+    shots = rt_shots(*[c.data_ptr() for c in cols], fam.data_ptr(), n)
+    m = max(1, n)
+    res = {f: torch.zeros(m, dtype=torch.int32, device=dev) for f in SHOT_I32}
+    res.update({f: torch.zeros(m, dtype=torch.float64, device=dev) for f in SHOT_F64})
+    stats_dev = torch.zeros(len(SOLVE_STAT_FIELDS), dtype=torch.int64, device=dev)
+    out = rt_shot_outputs(*([res[f].data_ptr() for f in SHOT_I32 + SHOT_F64]
+                            + [stats_dev.data_ptr()]))
+    ws_bytes = rt_solve_workspace_bytes(desc.field, 0)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    st = raytrace_shoot(desc.field, desc.bnd, desc.tol, desc.limits, shots, out, ws.data_ptr(),
+                        ws_bytes, torch.cuda.current_stream().cuda_stream, tuning)
+    if st != RT_OK:
+        raise RTError(st, rt_last_error())
+    torch.cuda.synchronize()
+    v = stats_dev.cpu().numpy()
+    return ({f: t[:n].cpu().numpy() for f, t in res.items()},
+            {f: int(v[i]) for i, f in enumerate(SOLVE_STAT_FIELDS)})

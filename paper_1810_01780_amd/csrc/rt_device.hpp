@@ -1,0 +1,529 @@
+// Device building blocks shared by the trace and the solve kernels:
+// Cash-Karp trial steps in stratified and gridded media, the step-size
+// controller, boundary functions and crossing selection, Fresnel
+// coefficients, per-wave statistics rows.  FP64 throughout; gfx950.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "rt_params.hpp"
+
+namespace rt {
+
+constexpr double kInvC0 = 1.0 / 299792458.0;  // 1 / speed of light (m/s)
+
+// Cash-Karp (1990) tableau: stage matrix, fifth-order weights, and the
+// difference of the fifth- and fourth-order weights.
+__device__ constexpr double ck_a(int i, int j) {
+  return i == 1 ? (1.0 / 5.0)
+       : i == 2 ? (j == 0 ? 3.0 / 40.0 : 9.0 / 40.0)
+       : i == 3 ? (j == 0 ? 3.0 / 10.0 : j == 1 ? -9.0 / 10.0 : 6.0 / 5.0)
+       : i == 4 ? (j == 0 ? -11.0 / 54.0 : j == 1 ? 5.0 / 2.0
+                   : j == 2 ? -70.0 / 27.0 : 35.0 / 27.0)
+       : (j == 0 ? 1631.0 / 55296.0 : j == 1 ? 175.0 / 512.0
+          : j == 2 ? 575.0 / 13824.0 : j == 3 ? 44275.0 / 110592.0
+          : 253.0 / 4096.0);
+}
+constexpr double kB1 = 37.0 / 378.0, kB3 = 250.0 / 621.0,
+                 kB4 = 125.0 / 594.0, kB6 = 512.0 / 1771.0;
+constexpr double kE1 = -277.0 / 64512.0, kE3 = 6925.0 / 370944.0,
+                 kE4 = -6925.0 / 202752.0, kE5 = -277.0 / 14336.0,
+                 kE6 = 277.0 / 7084.0;
+
+// y0 + h * sum_j a[S][j] k[j]
+template <int S>
+__device__ __forceinline__ double stage_in(double y0, double h, const double (&k)[6]) {
+  double acc = ck_a(S, 0) * k[0];
+#pragma unroll
+  for (int j = 1; j < S; ++j) acc = fma(ck_a(S, j), k[j], acc);
+  return fma(h, acc, y0);
+}
+__device__ __forceinline__ double b_sum(const double (&k)[6]) {
+  return fma(kB6, k[5], fma(kB4, k[3], fma(kB3, k[2], kB1 * k[0])));
+}
+__device__ __forceinline__ double e_sum(const double (&k)[6]) {
+  return fma(kE6, k[5], fma(kE5, k[4], fma(kE4, k[3], fma(kE3, k[2], kE1 * k[0]))));
+}
+
+// ---------------------------------------------------------------------------
+// FP64 helpers: hardware estimates refined by Newton steps to within an ulp or
+// two of the correctly rounded result.
+
+// 1/x for finite non-zero x.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// 1/sqrt(x) for finite x > 0.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  double e = fma(-hx * r, r, 0.5);
+  r = fma(r, e, r);
+  e = fma(-hx * r, r, 0.5);
+  return fma(r, e, r);
+}
+
+// x^(-1/K) for x > 0: FP32 log2/exp2 seed, then two Newton steps on
+// y^-K = x, i.e. y <- y ((K + 1) - x y^K) / K.  Values beyond the FP32 range
+// give 0 (the callers clamp the resulting step).
+template <int K>
+__device__ __forceinline__ double pow_neg_inv(double x) {
+  const float l = __builtin_amdgcn_logf((float)x);
+  double y = (double)__builtin_amdgcn_exp2f(l * (-1.0f / K));
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double y2 = y * y;
+    const double yk = K == 4 ? y2 * y2 : y2 * y2 * y;
+    y = y * fma(-x, yk, (double)(K + 1)) * (1.0 / K);
+  }
+  return y;
+}
+
+// e^x for |x| <= 0.25: Taylor polynomial to degree 11 (truncation below
+// 2^-52 relative), Horner form.
+__device__ __forceinline__ double exp_small(double x) {
+  double p = 1.0 / 39916800.0;
+  p = fma(p, x, 1.0 / 3628800.0);
+  p = fma(p, x, 1.0 / 362880.0);
+  p = fma(p, x, 1.0 / 40320.0);
+  p = fma(p, x, 1.0 / 5040.0);
+  p = fma(p, x, 1.0 / 720.0);
+  p = fma(p, x, 1.0 / 120.0);
+  p = fma(p, x, 1.0 / 24.0);
+  p = fma(p, x, 1.0 / 6.0);
+  p = fma(p, x, 0.5);
+  p = fma(p, x, 1.0);
+  return fma(p, x, 1.0);
+}
+
+// Medium of one ray, kept in registers: n(z) = a + b z - dn exp(-z/z0).
+struct Medium {
+  double a, b, dn, inv_z0, dn_inv_z0;
+  int use_grid;
+};
+
+// Media and boundary tables indexed per lane (by a ray's medium or by the
+// boundary it is searching): copied into LDS at kernel start.  Loops over all
+// boundaries use the uniform copy in the kernel arguments instead.
+__shared__ KRegion s_reg[RT_MAX_REGIONS];
+__shared__ KBnd s_bnd[kMaxBnd];
+
+__device__ __forceinline__ Medium medium_of(const KParams& P, int r) {
+  (void)P;
+  const KRegion& R = s_reg[r];
+  return Medium{R.a, R.b, R.dn, R.inv_z0, R.dn_inv_z0, R.use_grid};
+}
+
+__device__ __forceinline__ void strat_field(const Medium& M, double z, double& n, double& gz) {
+  double e = 0.0;
+  if (M.dn != 0.0) e = exp(-z * M.inv_z0);
+  n = fma(M.b, z, M.a) - M.dn * e;
+  gz = fma(M.dn_inv_z0, e, M.b);
+}
+
+// Same at a stage point z = z0 + dz of a step starting at z0, where
+// E0 = exp(-z0/z0_medium): exp(-z/z0) = E0 exp(-dz/z0), and the second factor
+// is a short polynomial because a step moves at most a fraction of z0.
+__device__ __forceinline__ void strat_field_rel(const Medium& M, double z0, double dz, double E0,
+                                                double& n, double& gz) {
+  const double z = z0 + dz;
+  double e = 0.0;
+  if (M.dn != 0.0) {
+    const double x = -dz * M.inv_z0;
+    e = fabs(x) <= 0.25 ? E0 * exp_small(x) : exp(-z * M.inv_z0);
+  }
+  n = fma(M.b, z, M.a) - M.dn * e;
+  gz = fma(M.dn_inv_z0, e, M.b);
+}
+
+// Trilinear n and gradient from float4 nodes (n, Dx, Dy, Dz); positions
+// outside the grid are clamped onto it; grad n = D / (2 spacing).
+__device__ __forceinline__ void grid_field(const KParams& P, double x, double y, double z,
+                                           double& n, double g[3]) {
+  const float4* __restrict__ nodes = static_cast<const float4*>(P.nodes);
+  double f[3] = {(x - P.gorg[0]) * P.ginv[0], (y - P.gorg[1]) * P.ginv[1],
+                 (z - P.gorg[2]) * P.ginv[2]};
+  int i0[3];
+  double t[3];
+  const int dims[3] = {P.gnx, P.gny, P.gnz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double v = fmin(fmax(f[a], 0.0), P.gmax[a]);
+    int i = (int)floor(v);
+    i = min(i, dims[a] - 2);
+    i0[a] = i;
+    t[a] = v - (double)i;
+  }
+  const size_t sx = 1, sy = (size_t)P.gnx, sz = (size_t)P.gnx * P.gny;
+  const size_t base = (size_t)i0[2] * sz + (size_t)i0[1] * sy + (size_t)i0[0];
+  float4 c[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    c[q] = nodes[base + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0)];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    double w = ((q & 1) ? t[0] : 1.0 - t[0]) * ((q & 2) ? t[1] : 1.0 - t[1]) *
+               ((q & 4) ? t[2] : 1.0 - t[2]);
+    acc[0] = fma(w, (double)c[q].x, acc[0]);
+    acc[1] = fma(w, (double)c[q].y, acc[1]);
+    acc[2] = fma(w, (double)c[q].z, acc[2]);
+    acc[3] = fma(w, (double)c[q].w, acc[3]);
+  }
+  n = acc[0];
+  g[0] = acc[1] * P.ghalf[0];
+  g[1] = acc[2] * P.ghalf[1];
+  g[2] = acc[3] * P.ghalf[2];
+}
+
+// ---------------------------------------------------------------------------
+// One Cash-Karp trial step of length h from state y = (r, w, tau):
+// y5 = fifth-order result, err = max(|dr|/h, |dw|/|w0|) / tol.
+// Paper model (eq. 2): w = unit velocity, r' = w, w' = grad n / n.
+// Exact model (eq. 1): w = p, r' = p / |p|, p' = grad n.   tau' = n / c0.
+//
+// Stratified media (grad n along z): in the paper model w_x, w_y are constant
+// within a step and only z, w_z, tau need stage values.
+template <int S>
+__device__ __forceinline__ double stage_inc(double h, const double (&k)[6]) {
+  double acc = ck_a(S, 0) * k[0];
+#pragma unroll
+  for (int j = 1; j < S; ++j) acc = fma(ck_a(S, j), k[j], acc);
+  return h * acc;
+}
+
+template <int MODEL>
+__device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], double h,
+                                            double inv_tol, double y5[7], double& err) {
+  const double E0 = M.dn != 0.0 ? exp(-y[2] * M.inv_z0) : 0.0;
+  if constexpr (MODEL == RT_MODEL_PAPER) {
+    // w = unit velocity, renormalised after every accepted step (|w| = 1)
+    double kz[6], kw[6];
+    double tsum = 0.0;  // sum_j b_j n_j / c0
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+      double dz = 0.0, ws = y[5];
+      if (st == 1) { dz = stage_inc<1>(h, kz); ws = stage_in<1>(y[5], h, kw); }
+      if (st == 2) { dz = stage_inc<2>(h, kz); ws = stage_in<2>(y[5], h, kw); }
+      if (st == 3) { dz = stage_inc<3>(h, kz); ws = stage_in<3>(y[5], h, kw); }
+      if (st == 4) { dz = stage_inc<4>(h, kz); ws = stage_in<4>(y[5], h, kw); }
+      if (st == 5) { dz = stage_inc<5>(h, kz); ws = stage_in<5>(y[5], h, kw); }
+      double n, gz;
+      strat_field_rel(M, y[2], dz, E0, n, gz);
+      kz[st] = ws;
+      kw[st] = gz * rcp_nr(n);
+      if (st == 0) tsum = kB1 * n;
+      if (st == 2) tsum = fma(kB3, n, tsum);
+      if (st == 3) tsum = fma(kB4, n, tsum);
+      if (st == 5) tsum = fma(kB6, n, tsum);
+    }
+    y5[0] = fma(h, y[3], y[0]);
+    y5[1] = fma(h, y[4], y[1]);
+    y5[2] = fma(h, b_sum(kz), y[2]);
+    y5[3] = y[3];
+    y5[4] = y[4];
+    y5[5] = fma(h, b_sum(kw), y[5]);
+    y5[6] = fma(h * kInvC0, tsum, y[6]);
+    // max(|dr|/h, |dw|/|w0|) / tol with |w0| = 1
+    err = fmax(fabs(e_sum(kz)), fabs(h * e_sum(kw))) * inv_tol;
+  } else {
+    // w = p = n dr/ds; p_x, p_y are constant in a stratified medium
+    const double px = y[3], py = y[4];
+    const double pxy2 = fma(px, px, py * py);
+    double kx[6], ky[6], kz[6], kp[6], kt[6];
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+      double dz = 0.0, ps = y[5];
+      if (st == 1) { dz = stage_inc<1>(h, kz); ps = stage_in<1>(y[5], h, kp); }
+      if (st == 2) { dz = stage_inc<2>(h, kz); ps = stage_in<2>(y[5], h, kp); }
+      if (st == 3) { dz = stage_inc<3>(h, kz); ps = stage_in<3>(y[5], h, kp); }
+      if (st == 4) { dz = stage_inc<4>(h, kz); ps = stage_in<4>(y[5], h, kp); }
+      if (st == 5) { dz = stage_inc<5>(h, kz); ps = stage_in<5>(y[5], h, kp); }
+      double n, gz;
+      strat_field_rel(M, y[2], dz, E0, n, gz);
+      const double ip = rsqrt_nr(fma(ps, ps, pxy2));
+      kx[st] = px * ip;
+      ky[st] = py * ip;
+      kz[st] = ps * ip;
+      kp[st] = gz;
+      kt[st] = n * kInvC0;
+    }
+    y5[0] = fma(h, b_sum(kx), y[0]);
+    y5[1] = fma(h, b_sum(ky), y[1]);
+    y5[2] = fma(h, b_sum(kz), y[2]);
+    y5[3] = px;
+    y5[4] = py;
+    y5[5] = fma(h, b_sum(kp), y[5]);
+    y5[6] = fma(h, b_sum(kt), y[6]);
+    const double ex = e_sum(kx), ey = e_sum(ky), ez = e_sum(kz);
+    const double dr_h = sqrt(fma(ex, ex, fma(ey, ey, ez * ez)));  // |dr| / h
+    const double dp = h * e_sum(kp);
+    err = fmax(dr_h, fabs(dp) * rsqrt_nr(fma(y[5], y[5], pxy2))) * inv_tol;
+  }
+}
+
+// General 3-D gradient (gridded media, or analytic media inside the grid
+// kernel).
+template <int MODEL>
+__device__ __forceinline__ void field3(const KParams& P, const Medium& M, double x, double y,
+                                       double z, double& n, double g[3]) {
+  if (M.use_grid) {
+    grid_field(P, x, y, z, n, g);
+  } else {
+    double gz;
+    strat_field(M, z, n, gz);
+    g[0] = 0.0;
+    g[1] = 0.0;
+    g[2] = gz;
+  }
+}
+
+template <int S>
+__device__ __forceinline__ void stage_vec(const double y[7], double h, const double (&k)[6][6],
+                                          double ys[6]) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    double kc[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) kc[j] = k[c][j];
+    ys[c] = stage_in<S>(y[c], h, kc);
+  }
+}
+
+template <int MODEL>
+__device__ __forceinline__ void trial_3d(const KParams& P, const Medium& M, const double y[7],
+                                         double h, double inv_tol, double y5[7], double& err) {
+  double k[6][6];  // [component][stage] for r (0..2) and w (3..5)
+  double kt[6];
+#pragma unroll
+  for (int st = 0; st < 6; ++st) {
+    double ys[6];
+    if (st == 0) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) ys[c] = y[c];
+    }
+    if (st == 1) stage_vec<1>(y, h, k, ys);
+    if (st == 2) stage_vec<2>(y, h, k, ys);
+    if (st == 3) stage_vec<3>(y, h, k, ys);
+    if (st == 4) stage_vec<4>(y, h, k, ys);
+    if (st == 5) stage_vec<5>(y, h, k, ys);
+    double n, g[3];
+    field3<MODEL>(P, M, ys[0], ys[1], ys[2], n, g);
+    if constexpr (MODEL == RT_MODEL_PAPER) {
+      const double in = rcp_nr(n);
+      k[0][st] = ys[3];
+      k[1][st] = ys[4];
+      k[2][st] = ys[5];
+      k[3][st] = g[0] * in;
+      k[4][st] = g[1] * in;
+      k[5][st] = g[2] * in;
+    } else {
+      const double ip = rsqrt_nr(fma(ys[3], ys[3], fma(ys[4], ys[4], ys[5] * ys[5])));
+      k[0][st] = ys[3] * ip;
+      k[1][st] = ys[4] * ip;
+      k[2][st] = ys[5] * ip;
+      k[3][st] = g[0];
+      k[4][st] = g[1];
+      k[5][st] = g[2];
+    }
+    kt[st] = n * kInvC0;
+  }
+  double d[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    double kc[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) kc[j] = k[c][j];
+    y5[c] = fma(h, b_sum(kc), y[c]);
+    d[c] = e_sum(kc);  // error vector / h
+  }
+  y5[6] = fma(h, b_sum(kt), y[6]);
+  // max(|dr|/h, |dw|/|w0|) / tol
+  const double dr_h = sqrt(fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2])));
+  const double dw_h = sqrt(fma(d[3], d[3], fma(d[4], d[4], d[5] * d[5])));
+  const double iw0 = rsqrt_nr(fma(y[3], y[3], fma(y[4], y[4], y[5] * y[5])));
+  err = fmax(dr_h, h * dw_h * iw0) * inv_tol;
+}
+
+// ---------------------------------------------------------------------------
+// Step-size controller (standard embedded-RK control): safety 0.9, growth
+// at most 5 (exactly 5 below err = (0.9/5)^5), shrink at most 10, exponents
+// -1/5 after an accepted and -1/4 after a rejected trial, clamp to
+// [h_min, h_max].
+constexpr double kSafety = 0.9, kGrowMax = 5.0, kShrinkMin = 0.1;
+constexpr double kErrCon = 1.889568e-4;
+// Crossing search (Illinois false position) limits.
+constexpr double kLocGTol = 1e-10, kLocWRel = 1e-14;
+constexpr int kLocMaxIt = 60, kLocMaxPass = 8, kMaxEvents = 255;
+
+__device__ __forceinline__ double clamp_h(const KParams& P, double h) {
+  return fmin(fmax(h, P.h_min), P.h_max);
+}
+
+// Boundary function with the ray's side sign applied: > 0 before crossing.
+__device__ __forceinline__ double bnd_G(const KParams& P, const KBnd& B, int k, uint32_t side,
+                                        const double y[7]) {
+  if (B.kind == B_TIME) return (P.t_max - y[6]) * 299792458.0;
+  double g = fma(y[2], B.nrm[2], fma(y[1], B.nrm[1], y[0] * B.nrm[0])) - B.d;
+  return ((side >> k) & 1u) ? g : -g;
+}
+
+// Earliest (by linear estimate) boundary crossed at the end of a step of
+// length len from y0 to y1, skipping boundary 'skip'; -1 if none.
+__device__ __forceinline__ int pick_crossing(const KParams& P, uint32_t side, const double y0[7],
+                                             const double y1[7], double len, int skip,
+                                             double& G0o, double& G1o) {
+  int best = -1;
+  double best_sig = 0.0;
+  for (int k = 0; k < P.n_bnd; ++k) {
+    if (k == skip) continue;
+    double G1 = bnd_G(P, P.bnd[k], k, side, y1);
+    if (!(G1 <= 0.0)) continue;
+    double G0 = bnd_G(P, P.bnd[k], k, side, y0);
+    double sig = G0 <= 0.0 ? 0.0 : len * G0 / (G0 - G1);
+    if (best < 0 || sig < best_sig) {
+      best = k;
+      best_sig = sig;
+      G0o = G0;
+      G1o = G1;
+    }
+  }
+  return best;
+}
+
+// Fresnel equations for incidence from n1 into n2, cos(theta_i) = ci >= 0.
+// r/t = (rs, rp, ts, tp) as (re, im); returns true on total reflection.
+__device__ __forceinline__ bool fresnel(double n1, double n2, double ci, double rt[8],
+                                        double& ct) {
+  double eta = n1 / n2;
+  double st2 = eta * eta * (1.0 - ci * ci);
+  if (st2 <= 1.0) {
+    ct = sqrt(1.0 - st2);
+    double a1 = n1 * ci, a2 = n2 * ct, b1 = n2 * ci, b2 = n1 * ct;
+    double is = 1.0 / (a1 + a2), ip = 1.0 / (b1 + b2);
+    rt[0] = (a1 - a2) * is;
+    rt[1] = 0.0;
+    rt[2] = (b1 - b2) * ip;
+    rt[3] = 0.0;
+    rt[4] = 2.0 * a1 * is;
+    rt[5] = 0.0;
+    rt[6] = 2.0 * a1 * ip;
+    rt[7] = 0.0;
+    return false;
+  }
+  // beyond the critical angle: cos(theta_t) = i kappa, r = (x - i y)/(x + i y)
+  double kap = sqrt(st2 - 1.0);
+  double xs = n1 * ci, ys = n2 * kap, xp = n2 * ci, yp = n1 * kap;
+  double qs = 1.0 / fma(xs, xs, ys * ys), qp = 1.0 / fma(xp, xp, yp * yp);
+  rt[0] = (xs * xs - ys * ys) * qs;
+  rt[1] = -2.0 * xs * ys * qs;
+  rt[2] = (xp * xp - yp * yp) * qp;
+  rt[3] = -2.0 * xp * yp * qp;
+  rt[4] = rt[5] = rt[6] = rt[7] = 0.0;
+  ct = 0.0;
+  return true;
+}
+
+// Per-wave statistics rows in LDS.  bump() adds the number of lanes
+// calling it (one LDS atomic by the first of them), so it may be used
+// inside divergent code.
+struct Counters {
+  unsigned long long* c;  // this wave's row
+  __device__ __forceinline__ void bump(int i) const {
+    const uint64_t m = __ballot(1);
+    if ((int)__lane_id() == __ffsll((unsigned long long)m) - 1)
+      atomicAdd(&c[i], (unsigned long long)__popcll(m));
+  }
+  __device__ __forceinline__ void max(int i, unsigned long long v) const {
+    atomicMax(&c[i], v);
+  }
+};
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  return __lanemask_lt();
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Ray held by one lane.
+struct Ray {
+  double y[7];  // x, y, z, w (v or p), tau
+  double s, h;
+  int32_t slot, region, gen, n_acc, n_rej, n_ev;
+  uint32_t side;
+};
+
+// Direction state from a direction u: v = u/|u| (paper) or p = n(r) u/|u|.
+template <int MODEL, int FIELD>
+__device__ __forceinline__ void set_direction(const KParams& P, Ray& R, double ux, double uy,
+                                              double uz) {
+  const double il = rsqrt_nr(fma(ux, ux, fma(uy, uy, uz * uz)));
+  double m = il;
+  if constexpr (MODEL == RT_MODEL_EXACT) {
+    double n, g[3];
+    if constexpr (FIELD == 1) {
+      field3<MODEL>(P, medium_of(P, R.region), R.y[0], R.y[1], R.y[2], n, g);
+    } else {
+      strat_field(medium_of(P, R.region), R.y[2], n, g[2]);
+    }
+    m = n * il;
+  }
+  R.y[3] = ux * m;
+  R.y[4] = uy * m;
+  R.y[5] = uz * m;
+}
+
+template <int MODEL, int FIELD>
+__device__ __forceinline__ double field_n(const KParams& P, const Medium& M, const double y[7]) {
+  double n, g[3];
+  if constexpr (FIELD == 1) {
+    field3<MODEL>(P, M, y[0], y[1], y[2], n, g);
+  } else {
+    strat_field(M, y[2], n, g[2]);
+  }
+  return n;
+}
+
+template <int MODEL, int FIELD>
+__device__ __forceinline__ void trial(const KParams& P, const Ray& R, double h, double y5[7],
+                                      double& err) {
+  if constexpr (FIELD == 1) {
+    trial_3d<MODEL>(P, medium_of(P, R.region), R.y, h, P.inv_tol, y5, err);
+  } else {
+    trial_strat<MODEL>(medium_of(P, R.region), R.y, h, P.inv_tol, y5, err);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step-size factor of the controller: min(5, 0.9 err^(-1/5)) after an
+// accepted trial (exactly 5 below kErrCon), max(0.1, 0.9 err^(-1/4)) after a
+// rejected one.  One Newton-refined power serves both cases.
+__device__ __forceinline__ double step_factor(double err, bool accepted) {
+  if (accepted && err < kErrCon) return kGrowMax;
+  const float l = __builtin_amdgcn_logf((float)err);
+  const float k = accepted ? -0.2f : -0.25f;
+  double y = (double)__builtin_amdgcn_exp2f(l * k);
+  // Newton on y^-K = err: y <- y ((K + 1) - err y^K) / K
+  const double K = accepted ? 5.0 : 4.0, iK = accepted ? 0.2 : 0.25;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double y2 = y * y;
+    const double yk = accepted ? y2 * y2 * y : y2 * y2;
+    y = y * fma(-err, yk, K + 1.0) * iK;
+  }
+  const double f = kSafety * y;
+  return accepted ? f : fmax(kShrinkMin, f);
+}
+
+}  // namespace rt

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 
+#include "radiotrace_solve.h"
 #include "rt_params.hpp"
 
 namespace rt {
@@ -157,6 +158,82 @@ rt_status rt_collect(const rt_stats* s, int64_t capacity) {
                        (long long)s->needed);
     return RT_ERR_CAPACITY;
   }
+  return RT_OK;
+}
+
+rt_status rt_solve_validate(const rt_field* field, const rt_boundaries* bnd, double tol,
+                            const rt_step_limits* L, const rt_solve_params* prm) {
+  if (!field || !bnd || !L) {
+    rt::set_last_error("null descriptor");
+    return RT_ERR_INVALID_ARG;
+  }
+  // shots have no sources, directions, path limit, amplitude cut or
+  // secondaries: check the rest as for a trace
+  rt_step_limits lim = *L;
+  lim.s_max = 1.0;
+  lim.amp_min = 0.0;
+  lim.max_generations = 1;
+  const rt_sources no_src = {nullptr, 0};
+  const rt_directions no_dirs = {nullptr, nullptr, 0};
+  rt_status st = rt::validate(field, bnd, &no_src, &no_dirs, tol, &lim);
+  if (st != RT_OK) return st;
+  if (rt::field_uses_grid(field)) {
+    rt::set_last_error("solves support stratified (analytic) fields only");
+    return RT_ERR_UNSUPPORTED;
+  }
+  if (L->t_max != 0.0) {
+    rt::set_last_error("solves need t_max = 0 (shots end at the receiver plane)");
+    return RT_ERR_INVALID_ARG;
+  }
+  if (bnd->has_box) {
+    rt::set_last_error("solves need has_box = 0 (shots end at the receiver plane)");
+    return RT_ERR_INVALID_ARG;
+  }
+  if (bnd->n_planes < 1 || bnd->planes[0].kind != RT_PLANE_FRESNEL) {
+    rt::set_last_error("solves need planes[0] = the surface, of kind RT_PLANE_FRESNEL");
+    return RT_ERR_INVALID_ARG;
+  }
+  if (prm) {
+    if (prm->n_scan < 2 || prm->n_scan > 4096 || prm->max_iter < 1 || prm->max_iter > 1000 ||
+        prm->max_brackets < 1 || prm->max_brackets > 16) {
+      rt::set_last_error("need 2 <= n_scan <= 4096, 1 <= max_iter <= 1000, "
+                         "1 <= max_brackets <= 16");
+      return RT_ERR_INVALID_ARG;
+    }
+    if (!(prm->miss_tol > 0.0) || !(prm->accept_tol >= prm->miss_tol) ||
+        !std::isfinite(prm->accept_tol)) {
+      rt::set_last_error("need 0 < miss_tol <= accept_tol < inf");
+      return RT_ERR_INVALID_ARG;
+    }
+  }
+  return RT_OK;
+}
+
+rt_status rt_solve_workspace_bytes(const rt_field* field, int64_t n_pairs,
+                                   const rt_solve_params* prm, size_t* bytes) {
+  if (!field || !bytes || (n_pairs > 0 && !prm)) {
+    rt::set_last_error("null argument");
+    return RT_ERR_INVALID_ARG;
+  }
+  if (n_pairs < 0) {
+    rt::set_last_error("negative pair count");
+    return RT_ERR_INVALID_ARG;
+  }
+  size_t b = 4096;  // counters, padded
+  if (n_pairs > 0) {
+    const size_t pf = 2 * (size_t)n_pairs;
+    b += (pf * (size_t)prm->n_scan * 8 + 4095) / 4096 * 4096;       // scan misses
+    b += (pf * (size_t)prm->max_brackets * 80 + 4095) / 4096 * 4096; // bracket results
+  }
+  if (field->n_regions > 0 && field->regions && rt::field_uses_grid(field)) {
+    const rt_grid& g = field->grid;
+    if (g.nx < 2 || g.ny < 2 || g.nz < 2) {
+      rt::set_last_error("grid: dims must be >= 2");
+      return RT_ERR_INVALID_ARG;
+    }
+    b += (size_t)g.nx * g.ny * g.nz * 16;
+  }
+  *bytes = b;
   return RT_OK;
 }
 

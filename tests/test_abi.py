@@ -156,3 +156,75 @@ def test_launch_validates_before_touching_the_device():
     d = _descs()
     st = B.raytrace_launch(d.field, d.bnd, d.sources, d.dirs, d.tol, d.limits, out, 0, 0, 0)
     assert st == B.RT_ERR_INVALID_ARG and "null" in B.rt_last_error()
+
+
+# --- emitter -> receiver solves ---------------------------------------------
+def _solve_descs(**lim):
+    d = B.HostDescriptors(W.solve_pairs(8).scene)
+    for k, v in lim.items():
+        setattr(d.limits, k, v)
+    return d
+
+
+def test_solve_validate():
+    d = _solve_descs()
+    p = B.solve_params()
+    assert B.rt_solve_validate(d.field, d.bnd, d.tol, d.limits, p) == B.RT_OK
+    assert B.rt_solve_validate(d.field, d.bnd, d.tol, d.limits, None) == B.RT_OK
+    # unused by shots: s_max, amp_min, max_generations
+    d2 = _solve_descs(s_max=0.0, amp_min=-1.0, max_generations=9)
+    assert B.rt_solve_validate(d2.field, d2.bnd, d2.tol, d2.limits, p) == B.RT_OK
+    d3 = _solve_descs(t_max=1e-6)
+    assert B.rt_solve_validate(d3.field, d3.bnd, d3.tol, d3.limits, p) == B.RT_ERR_INVALID_ARG
+    assert B.rt_solve_validate(d.field, d.bnd, 0.0, d.limits, p) == B.RT_ERR_INVALID_ARG
+    for bad in (dict(n_scan=1), dict(n_scan=5000), dict(max_iter=0), dict(max_brackets=17),
+                dict(miss_tol=0.0), dict(miss_tol=1e-3, accept_tol=1e-4)):
+        q = B.solve_params(**bad)
+        assert B.rt_solve_validate(d.field, d.bnd, d.tol, d.limits, q) == B.RT_ERR_INVALID_ARG
+        assert B.rt_last_error()
+
+
+def test_solve_validate_boundaries():
+    p = B.solve_params()
+    d = _solve_descs()
+    d.bnd.has_box = 1
+    d.bnd.box_lo = (C.c_double * 3)(-1.0, -1.0, -1.0)
+    d.bnd.box_hi = (C.c_double * 3)(1.0, 1.0, 1.0)
+    assert B.rt_solve_validate(d.field, d.bnd, d.tol, d.limits, p) == B.RT_ERR_INVALID_ARG
+    d = _solve_descs()
+    d.bnd.planes[0].kind = 1     # RT_PLANE_ABSORB: not a reflecting surface
+    assert B.rt_solve_validate(d.field, d.bnd, d.tol, d.limits, p) == B.RT_ERR_INVALID_ARG
+    d = _solve_descs()
+    d.bnd.n_planes = 0
+    assert B.rt_solve_validate(d.field, d.bnd, d.tol, d.limits, p) == B.RT_ERR_INVALID_ARG
+    g = B.HostDescriptors(W.gridded(rays_per_source=1, n_sources=2, nx=4, ny=4, nz=4))
+    g.field.grid.n = 0x4000
+    g.bnd.has_box = 0
+    g.limits.t_max = 0.0
+    assert B.rt_solve_validate(g.field, g.bnd, g.tol, g.limits, p) == B.RT_ERR_UNSUPPORTED
+
+
+def test_solve_workspace_bytes():
+    d = _solve_descs()
+    p = B.solve_params(n_scan=64, max_brackets=4)
+    assert B.rt_solve_workspace_bytes(d.field, 0) == 4096
+    # 20 (pair, family) entries: 64 misses x 8 B = 10240 -> 12288; 4 brackets x 80 B = 6400 -> 8192
+    assert B.rt_solve_workspace_bytes(d.field, 10, p) == 4096 + 12288 + 8192
+    with pytest.raises(B.RTError):
+        B.rt_solve_workspace_bytes(d.field, 10, None)
+
+
+def test_solve_and_shoot_validate_before_touching_the_device():
+    d = _solve_descs()
+    p = B.solve_params()
+    pairs = B.rt_pairs(0x1000, 0x2000, 0x3000, 4)
+    out = B.rt_solve_outputs()
+    st = B.raytrace_solve(d.field, d.bnd, d.tol, d.limits, pairs, p, out, 0, 0, 0)
+    assert st == B.RT_ERR_INVALID_ARG and "null" in B.rt_last_error()
+    shots = B.rt_shots(0x1000, 0x2000, 0x3000, 0x4000, 0x5000, 4)
+    sout = B.rt_shot_outputs()
+    st = B.raytrace_shoot(d.field, d.bnd, d.tol, d.limits, shots, sout, 0, 0, 0)
+    assert st == B.RT_ERR_INVALID_ARG and "null" in B.rt_last_error()
+    bad = B.solve_params(max_iter=0)
+    st = B.raytrace_solve(d.field, d.bnd, d.tol, d.limits, pairs, bad, out, 0, 0, 0)
+    assert st == B.RT_ERR_INVALID_ARG

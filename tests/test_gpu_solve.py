@@ -1,0 +1,245 @@
+"""GPU parity of emitter -> receiver solves: single shots against the oracle's
+shots element by element, solves against the oracle's solves, graph replay.
+
+Bars.  A shot is one trace, held to the trace bars: positions (here the miss)
+within 1e-9 of the path length, s and t within 1e-9 relative, amplitudes
+within 1e-9.  A solve ends when a shot meets |miss| <= miss_tol, so two
+correct solvers may stop at different shots of the same root: both
+solutions are checked to be solutions (the oracle re-shoots the GPU's angle
+and finds the GPU's miss), and their travel times may differ by at most the
+time a ray needs to cover the two misses: n_max / c0 (|m_gpu| + |m_oracle|),
+since the travel time to a point on the receiver plane changes by at most
+n / c0 per metre the point moves (Fermat).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1810_01780_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+C0 = 299792458.0
+N_MAX = 1.8  # largest refractive index of the workloads
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_01780_amd import binding
+    binding.lib()
+    return binding
+
+
+def _announce(name, n):
+    print(f"\n[gpu-case] {name}: {n} entries", flush=True)
+    sys.stdout.flush()
+
+
+def _shot_inputs(n, seed=11):
+    rng = np.random.default_rng(seed)
+    zs = rng.uniform(50.0, 2000.0, n)
+    zr = rng.uniform(0.0, 200.0, n)
+    D = rng.uniform(10.0, 3000.0, n)
+    th = rng.uniform(0.02, math.pi - 0.02, n)
+    fam = rng.integers(0, 2, n).astype(np.int32)
+    return zs, zr, D, th, fam
+
+
+def compare_shots(g, o, label, max_flip_frac=2e-3):
+    assert np.array_equal(g["status"], o["status"]), f"{label}: status differs"
+    recv = o["status"] == 0
+    same = (g["n_acc"] == o["n_acc"]) & (g["n_rej"] == o["n_rej"])
+    flips = int((~same).sum())
+    assert flips <= max_flip_frac * len(same) + 1, f"{label}: {flips} step-count flips"
+    ok = recv & same
+    s = np.maximum(o["s"], 1.0)
+    dm = np.abs(g["miss"] - o["miss"]) / s
+    ds = np.abs(g["s"] - o["s"]) / s
+    dt = np.abs(g["t"] - o["t"]) / np.maximum(o["t"], 1e-300)
+    da = np.max(np.abs(np.stack([g[f] - o[f] for f in ("as_re", "as_im", "ap_re", "ap_im")])),
+                axis=0)
+    summ = dict(n=len(s), recv=int(recv.sum()), flips=flips, miss=float(dm[ok].max(initial=0)),
+                s=float(ds[ok].max(initial=0)), t=float(dt[ok].max(initial=0)),
+                amp=float(da[ok].max(initial=0)))
+    print(f"[gpu-case] {label}: {summ}", flush=True)
+    assert summ["miss"] <= 1e-9 and summ["s"] <= 1e-9 and summ["t"] <= 1e-9, summ
+    assert summ["amp"] <= 1e-9, summ
+    # shots that end elsewhere carry the fixed miss codes
+    assert np.array_equal(g["miss"][~recv], o["miss"][~recv])
+    return summ
+
+
+@pytest.mark.parametrize("model", [W.MODEL_PAPER, W.MODEL_EXACT])
+def test_shots_match_oracle(gpu, oracle_lib, model):
+    """2,048 random shots (both families) in the two-layer firn model."""
+    sc = W.solve_pairs(1, model=model).scene
+    zs, zr, D, th, fam = _shot_inputs(2048)
+    _announce(f"shots-m{model}", len(zs))
+    g, gst = gpu.shoot(sc, zs, zr, D, th, fam)
+    o = oracle_lib.shoot(sc, zs, zr, D, th, fam)
+    s = compare_shots(g, o, f"shots-m{model}")
+    assert s["recv"] > 200 and gst["shots"] == len(zs)
+    assert gst["accepted"] == int(g["n_acc"].sum())
+
+
+def test_constant_medium_shots(gpu):
+    """Straight lines in a constant medium: closed-form miss, path and time."""
+    n = 1.5
+    sc = W.Scene(name="const", regions=[W.air_region(), W.Region(a=n, z_top=0.0)],
+                 planes=[W.surface_plane(ice=1, air=0)], sources=np.zeros((1, 3)),
+                 ray_src=np.zeros(1, np.int32), dirs=np.array([[1.0, 0.0, 0.0]]),
+                 limits=W.Limits(tol=1e-9, h_min=1e-3, h_max=10.0, s_max=1e4,
+                                 max_generations=1, model=W.MODEL_EXACT))
+    zs, zr, D = 300.0, 80.0, 400.0
+    th = np.linspace(0.1, math.pi / 2, 24)
+    m = len(th)
+    for fam in (0, 1):
+        _announce(f"const-shots-f{fam}", m)
+        r, _ = gpu.shoot(sc, np.full(m, zs), np.full(m, zr), np.full(m, D), th, np.full(m, fam))
+        z_line = zs - D / np.tan(th)
+        L = D / np.sin(th)
+        hit = z_line < 0.0
+        for i in range(m):
+            if fam == 0 and hit[i]:
+                assert r["status"][i] == gpu.RT_SHOT_SURFACE and r["miss"][i] == -1e6
+                continue
+            if L[i] > 2 * (D + zs + zr) + 1000.0:   # beyond the shot's path limit
+                assert r["status"][i] == gpu.RT_SHOT_LOST and r["miss"][i] == 1e6
+                continue
+            assert r["status"][i] == gpu.RT_SHOT_RECEIVER
+            want = z_line[i] - zr if fam == 0 else -z_line[i] - zr
+            assert r["miss"][i] == pytest.approx(want, abs=1e-6)
+            assert r["s"][i] == pytest.approx(L[i], rel=1e-9)
+            assert r["t"][i] * C0 == pytest.approx(n * L[i], rel=1e-9)
+
+
+def test_invalid_shots(gpu):
+    sc = W.solve_pairs(1).scene
+    zs = [300.0, 300.0, 300.0, 300.0, 0.0, float("nan"), 300.0]
+    zr = [50.0] * 7
+    D = [0.0, 100.0, 100.0, 100.0, 100.0, 100.0, 100.0]
+    th = [1.0, 0.0, math.pi, 1.0, 1.0, 1.0, 1.0]
+    fam = [0, 0, 0, 2, 0, 0, 1]
+    _announce("invalid-shots", 7)
+    r, st = gpu.shoot(sc, zs, zr, D, th, fam)
+    assert r["status"].tolist() == [3, 3, 3, 3, 3, 3, 0]
+    assert st["invalid"] == 6 and st["shots"] == 1
+
+
+def compare_solves(oracle_lib, g, o, sc, pairs, label, max_found_mismatch=0.005):
+    """Found flags agree (up to rare roots at the acceptance threshold);
+    common solutions are solutions of the oracle's shots and agree in time."""
+    fg, fo = g["found"] == 1, o["found"] == 1
+    mism = int((fg != fo).sum())
+    both = fg & fo
+    assert mism <= max_found_mismatch * fg.size + 1, f"{label}: {mism} found flags differ"
+    # the GPU's solutions, re-shot by the oracle
+    idx = np.argwhere(fg)
+    zs, zr, D = pairs
+    rs = oracle_lib.shoot(sc, zs[idx[:, 0]], zr[idx[:, 0]], D[idx[:, 0]],
+                          g["theta"][fg], idx[:, 1].astype(np.int32))
+    assert np.all(rs["status"] == 0), f"{label}: a GPU solution does not reach the receiver"
+    s = np.maximum(rs["s"], 1.0)
+    re_miss = np.abs(rs["miss"] - g["miss"][fg]) / s
+    assert re_miss.max(initial=0) <= 1e-9, f"{label}: oracle re-shot miss {re_miss.max()}"
+    assert np.all(np.abs(g["miss"][fg]) <= 1e-3)
+    bar = N_MAX / C0 * (np.abs(g["miss"][both]) + np.abs(o["miss"][both])) \
+        + 1e-9 * o["t"][both]
+    dt = np.abs(g["t"][both] - o["t"][both])
+    summ = dict(entries=int(fg.size), found_gpu=int(fg.sum()), found_oracle=int(fo.sum()),
+                mismatch=mism, dt_excess=float((dt - bar).max(initial=-1.0)),
+                dtheta=float(np.abs(g["theta"][both] - o["theta"][both]).max(initial=0.0)),
+                shots_equal=float((g["shots"] == o["shots"]).mean()))
+    print(f"[gpu-case] {label}: {summ}", flush=True)
+    assert summ["dt_excess"] <= 0.0, summ
+    assert summ["dtheta"] <= 1e-4, summ
+    assert summ["shots_equal"] >= 0.9, summ
+    return summ
+
+
+@pytest.mark.parametrize("model", [W.MODEL_PAPER, W.MODEL_EXACT])
+def test_solves_match_oracle(gpu, oracle_lib, model):
+    """192 pairs of the two-layer workload, both families."""
+    sp = W.solve_pairs(192, model=model)
+    _announce(f"solve-m{model}", sp.n)
+    g, gst = gpu.solve(sp.scene, sp.zs, sp.zr, sp.dist)
+    o = oracle_lib.solve(sp.scene, sp.zs, sp.zr, sp.dist)
+    s = compare_solves(oracle_lib, g, o, sp.scene, (sp.zs, sp.zr, sp.dist), f"solve-m{model}")
+    assert s["found_gpu"] > 150
+    assert gst["found"] == s["found_gpu"] and gst["invalid"] == 0
+    assert gst["shots"] >= 2 * sp.n * 64
+
+
+def test_solve_invalid_and_empty(gpu):
+    sc = W.solve_pairs(1).scene
+    zs = np.array([500.0, float("nan"), 500.0, 0.0, 700.0])
+    zr = np.array([100.0, 100.0, 100.0, 100.0, 60.0])
+    D = np.array([800.0, 800.0, -5.0, 800.0, 300.0])
+    _announce("solve-invalid", 5)
+    g, st = gpu.solve(sc, zs, zr, D)
+    assert g["found"][[1, 2, 3]].sum() == 0 and g["shots"][[1, 2, 3]].sum() == 0
+    assert g["found"][0, 0] == 1 and g["found"][4, 0] == 1
+    assert st["invalid"] == 3
+    g0, st0 = gpu.solve(sc, np.zeros(0), np.zeros(0), np.zeros(0))
+    assert g0["found"].shape == (0, 2) and st0["shots"] == 0
+
+
+def test_solve_graph_replay(gpu):
+    """The whole solve captured into a graph and replayed: every replay gives
+    the eager result exactly (the same shots run, whichever lane runs them)."""
+    import torch
+    sp = W.solve_pairs(128)
+    _announce("solve-graph", sp.n)
+    ds = gpu.DeviceSolve(sp.scene, sp.zs, sp.zr, sp.dist)
+    ds.launch()
+    ref, ref_st = ds.collect()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ds.launch(stream=s)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        ds.launch()
+    for rep in range(3):
+        for t in ds.res.values():
+            t.fill_(-7)  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        got, st = ds.collect()
+        for f in ref:
+            assert np.array_equal(got[f], ref[f]), (rep, f)
+        assert st == ref_st, rep
+
+
+@pytest.mark.parametrize("block,refill", [(64, 1), (128, 64), (192, 7)])
+def test_solve_schedule_independence(gpu, block, refill):
+    sp = W.solve_pairs(96)
+    _announce(f"solve-sched-{block}-{refill}", sp.n)
+    base, bst = gpu.solve(sp.scene, sp.zs, sp.zr, sp.dist)
+    got, gst = gpu.solve(sp.scene, sp.zs, sp.zr, sp.dist,
+                         tuning=gpu.rt_tuning(block_size=block, refill_threshold=refill))
+    for f in base:
+        assert np.array_equal(base[f], got[f]), f
+    assert bst == gst
+
+
+def test_solve_full_size_sampled(gpu, oracle_lib):
+    """All 65,536 pairs in one call (the benchmark configuration); 256 sampled
+    pairs against the oracle."""
+    sp = W.solve_pairs()
+    _announce("solve-full", sp.n)
+    g, st = gpu.solve(sp.scene, sp.zs, sp.zr, sp.dist)
+    rng = np.random.default_rng(5)
+    pick = np.sort(rng.choice(sp.n, 256, replace=False))
+    o = oracle_lib.solve(sp.scene, sp.zs, sp.zr, sp.dist, pairs=pick)
+    os_ = {f: a[pick] for f, a in o.items()}
+    gs = {f: a[pick] for f, a in g.items()}
+    compare_solves(oracle_lib, gs, os_, sp.scene, (sp.zs[pick], sp.zr[pick], sp.dist[pick]), "solve-full")
+    assert st["found"] == int(g["found"].sum()) and st["invalid"] == 0
