@@ -92,12 +92,124 @@ def cpu_baseline(scene, target_s, threads, log):
                       f"secondary tree: {st['accepted']} accepted steps in {dt:.1f} s"}
 
 
+def cpu_solve_baseline(sp, target_s, threads, log):
+    """Time the CPU oracle's solves on an evenly strided sample of the pairs."""
+    import numpy as np
+    import oracle
+    n = sp.n
+    probe = np.arange(0, n, max(1, n // 256), dtype=np.int64)
+    t0 = time.perf_counter()
+    oracle.solve(sp.scene, sp.zs, sp.zr, sp.dist, pairs=probe, threads=threads)
+    per_pair = (time.perf_counter() - t0) / len(probe)
+    stride = max(1, int(np.ceil(n * per_pair / target_s)))
+    pick = np.arange(0, n, stride, dtype=np.int64)
+    log(f"cpu baseline: {len(pick)} of {n} pairs (every {stride}th), {threads} threads")
+    t0 = time.perf_counter()
+    oracle.solve(sp.scene, sp.zs, sp.zr, sp.dist, pairs=pick, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": len(pick) / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}th pair ({len(pick)} of {n}), both families, "
+                      f"in {dt:.1f} s"}
+
+
+def bench_solve(args, log):
+    """Batched emitter -> receiver solves: 65,536 seeded pairs (source depth
+    50-2000 m, receiver depth 0-200 m, distance 10 m - 3 km) in the two-layer
+    firn model, direct and surface-reflected solution of each.  A step is one
+    raytrace_solve of the whole batch replayed from a captured graph, with the
+    launch tuning chosen by rt_solve_autotune on a 16,384-pair sample."""
+    import torch
+    from paper_1810_01780_amd import binding
+    from paper_1810_01780_amd import workloads as W
+    sp = W.solve_pairs()
+    prm = binding.solve_params()
+    cfg = dict(workload="solve65536", pairs=sp.n, n_scan=prm.n_scan, max_iter=prm.max_iter,
+               max_brackets=prm.max_brackets, miss_tol_m=prm.miss_tol,
+               accept_tol_m=prm.accept_tol, slope_max_m_per_rad=prm.slope_max,
+               tol=sp.scene.limits.tol, model="paper")
+    log(f"workload solve65536: {sp.n} pairs")
+    if args.block or args.refill:
+        tun = binding.rt_tuning(args.block, 0, args.refill, None, None)
+        cfg["tuning"] = "fixed"
+    else:
+        m = 16384
+        sample = binding.DeviceSolve(sp.scene, sp.zs[:m], sp.zr[:m], sp.dist[:m], prm)
+        tun, ms = sample.autotune()
+        log(f"autotune on {m} pairs: block {tun.block_size} refill {tun.refill_threshold} "
+            f"({ms:.2f} ms)")
+        cfg["tuning"] = "autotuned"
+        del sample
+    cfg.update(block=tun.block_size, refill=tun.refill_threshold)
+    ds = binding.DeviceSolve(sp.scene, sp.zs, sp.zr, sp.dist, prm)
+    hip = _hip()
+
+    def event():
+        e = ctypes.c_void_p()
+        assert hip.hipEventCreate(ctypes.byref(e)) == 0
+        return e
+
+    def elapsed(b, e):
+        ms = ctypes.c_float()
+        hip.hipEventElapsedTime(ctypes.byref(ms), b, e)
+        return ms.value
+
+    # shot-kernel time (scan + refinement) from eager launches, events on the stream
+    kern = []
+    for i in range(args.warmup + 1):
+        b, e = event(), event()
+        ds.launch(tuning=binding.rt_tuning(tun.block_size, 0, tun.refill_threshold, b, e))
+        res, st = ds.collect()
+        if i >= args.warmup:
+            kern.append(elapsed(b, e))
+        log(f"eager {i}: found {st['found']} of {2 * sp.n}, {st['shots']} shots, "
+            f"{elapsed(b, e):.2f} ms shot kernels")
+    # capture the whole solve and time graph replays
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ds.launch(stream=s, tuning=tun)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        ds.launch(tuning=tun)
+    g.replay()
+    torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    res2, st2 = ds.collect()
+    assert st2 == st, "graph replay differs from the eager solve"
+    kern_s = sum(kern) / len(kern) / 1e3
+    trials = st["accepted"] + st["rejected"] + st["relocation"]
+    achieved = trials * FLOP_PER_TRIAL_STRAT_PAPER / kern_s / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+            "kernel": "shot_kernel (scan + refine)", "kernel_ms": kern_s * 1e3}
+    cfg.update(shots=st["shots"], trial_steps=trials, accepted_steps=st["accepted"],
+               found=st["found"], brackets=st["brackets"])
+    log(f"timed {args.steps} graph replays: {wall:.3f} s; shot kernels {kern_s * 1e3:.2f} ms")
+    out = {"metric": "emitter->receiver solves/s (FP64 tracer)",
+           "value": sp.n * args.steps / wall, "unit": "solves/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": cfg, "roofline": roof}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_solve_baseline(sp, args.cpu_seconds,
+                                                 min(args.cpu_threads, os.cpu_count() or 1), log)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="twolayer", choices=["twolayer", "grid256", "fan1024"])
+    ap.add_argument("--workload", default="twolayer",
+                    choices=["twolayer", "grid256", "fan1024", "solve"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -116,6 +228,8 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
+    if args.workload == "solve":
+        return bench_solve(args, log)
     scene, cfg = make_scene(args.workload)
     log(f"workload {cfg['workload']}: {scene.n_rays} rays")
     ds = binding.DeviceScene(scene)

@@ -36,8 +36,14 @@
  *   bracket (the first max_brackets, in k order, are refined).  A bracket is
  *   refined by Illinois false position on the miss (bisection while an end
  *   has |miss| >= 1e5), stopping when a shot reaches the receiver plane with
- *   |miss| <= miss_tol, when the bracket is narrower than 1e-13 rad, or after
- *   max_iter shots.  A refined root is a solution if its last shot reached
+ *   |miss| <= miss_tol, when the bracket is narrower than 1e-9 rad, after
+ *   max_iter shots, or when the bracket cannot hold a root: a miss that is
+ *   continuous with slope at most slope_max (m/rad) and vanishes in [a, b]
+ *   has |miss(a)| + |miss(b)| <= slope_max (b - a) (ends with |miss| >= 1e5
+ *   count zero); brackets around jumps of the miss -- shots starting to
+ *   touch the surface or to get lost, total reflection setting in at a
+ *   layer -- end this way.  1e7 m/rad (10 m of miss per mrad of launch
+ *   angle, about 900 times the longest shot path) is the suggested value.  A refined root is a solution if its last shot reached
  *   the receiver plane with |miss| <= accept_tol; the solution reported is
  *   the one with the smallest travel time (the first in bracket order among
  *   equal times).
@@ -83,6 +89,7 @@ typedef struct {
   int32_t max_brackets; /* brackets refined per family, 1..16 */
   double miss_tol;      /* refinement stops at |miss| <= miss_tol (m), > 0 */
   double accept_tol;    /* solution if |miss| <= accept_tol (m), >= miss_tol */
+  double slope_max;     /* bracket stop (m/rad, see above); 0 = off */
 } rt_solve_params;
 
 /* Device-side totals of a solve or shoot call. */
@@ -163,6 +170,21 @@ rt_status raytrace_shoot(const rt_field* field, const rt_boundaries* boundaries,
                          const rt_step_limits* limits, const rt_shots* shots,
                          rt_shot_outputs* out, void* workspace, size_t workspace_bytes,
                          void* stream, const rt_tuning* tuning);
+
+/* Pick launch tuning for raytrace_solve by measurement: every combination of
+ * block_size in {64, 128, 192, 256} and refill_threshold in {4, 16, 32, 64}
+ * runs raytrace_solve once on 'pairs' (a representative sample; its results
+ * land in 'out' and are overwritten by each candidate) after one untimed
+ * call, timed with HIP events on 'stream'; the fastest is written to *best
+ * (other fields zero) and its time in ms to *best_ms (may be NULL).  This
+ * call blocks the host until each candidate finishes, so it cannot be
+ * captured into a graph: tune first, then capture raytrace_solve with the
+ * result. */
+rt_status rt_solve_autotune(const rt_field* field, const rt_boundaries* boundaries, double tol,
+                            const rt_step_limits* limits, const rt_pairs* pairs,
+                            const rt_solve_params* params, rt_solve_outputs* out,
+                            void* workspace, size_t workspace_bytes, void* stream,
+                            rt_tuning* best, float* best_ms);
 
 #ifdef __cplusplus
 }

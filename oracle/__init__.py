@@ -234,7 +234,8 @@ class SolveSpec(C.Structure):
     _fields_ = [("zs", C.POINTER(C.c_double)), ("zr", C.POINTER(C.c_double)),
                 ("dist", C.POINTER(C.c_double)), ("n_scan", C.c_int32),
                 ("max_iter", C.c_int32), ("max_brackets", C.c_int32),
-                ("miss_tol", C.c_double), ("accept_tol", C.c_double)]
+                ("miss_tol", C.c_double), ("accept_tol", C.c_double),
+                ("slope_max", C.c_double)]
 
 
 SOLVE_I32 = ["found", "shots"]
@@ -247,7 +248,7 @@ class SolveOut(C.Structure):
 
 
 def solve(scene, zs, zr, dist, pairs=None, n_scan=64, max_iter=60, max_brackets=4,
-          miss_tol=1e-4, accept_tol=1e-3, threads=None):
+          miss_tol=1e-4, accept_tol=1e-3, slope_max=1e7, threads=None):
     """Shooting solves for source/receiver pairs; arrays indexed [pair, family]
     with family 0 = direct, 1 = reflected once at the surface."""
     L = lib()
@@ -260,7 +261,7 @@ def solve(scene, zs, zr, dist, pairs=None, n_scan=64, max_iter=60, max_brackets=
     dist = np.ascontiguousarray(dist, np.float64)
     prep.keep += [zs, zr, dist]
     spec = SolveSpec(_ptr(zs, C.c_double), _ptr(zr, C.c_double), _ptr(dist, C.c_double),
-                     n_scan, max_iter, max_brackets, miss_tol, accept_tol)
+                     n_scan, max_iter, max_brackets, miss_tol, accept_tol, slope_max)
     n = len(zs)
     arrs = {f: np.zeros(2 * n, np.int32) for f in SOLVE_I32}
     arrs.update({f: np.zeros(2 * n, np.float64) for f in SOLVE_F64})

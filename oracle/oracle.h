@@ -109,6 +109,8 @@ typedef struct {
   int32_t max_brackets; /* sign changes refined per family */
   double miss_tol;      /* refinement stops at |miss| <= miss_tol (m) */
   double accept_tol;    /* a root is a solution if |miss| <= accept_tol (m) */
+  double slope_max;     /* bracket stop: finite end misses above slope_max *
+                           width (m/rad) hold no root; 0 = off */
 } orc_solve_spec;
 
 /* Outputs indexed [2 * pair + family]. */

@@ -949,6 +949,17 @@ static shot_t shoot(worker_t* W, const scene_t* S, double zs, double zr, double 
 
 static int miss_sign(double m) { return m < 0.0 ? -1 : 1; }
 
+/* Refinement of a bracket stops when it is narrower than SOLVE_WIDTH_MIN
+ * (rad), or when its end misses cannot belong to a root: a miss that is
+ * continuous on [a, b] with |d miss / d theta| <= slope_max and a zero
+ * inside has |miss(a)| + |miss(b)| <= slope_max (b - a); ends that are
+ * failed shots (|miss| >= 1e5) contribute nothing.  Brackets around jumps of
+ * the miss (a shot starting to touch the surface or to get lost, total
+ * reflection setting in at a layer) end this way instead of being bisected
+ * down to rounding. */
+#define SOLVE_WIDTH_MIN 1.0e-9
+static double finite_miss(double m) { return fabs(m) < 1.0e5 ? fabs(m) : 0.0; }
+
 /* Refine a bracket [a, b] of the miss by Illinois false position (plain
  * bisection while an end is a failed shot). */
 static shot_t refine(worker_t* W, const scene_t* S, const orc_solve_spec* sp, double zs, double zr,
@@ -959,6 +970,7 @@ static shot_t refine(worker_t* W, const scene_t* S, const orc_solve_spec* sp, do
   sh.status = SHOT_LOST;
   int last = 0;
   double c = a;
+  double ma = Ga, mb = Gb; /* misses at the ends (Ga, Gb get scaled) */
   for (int it = 0; it < sp->max_iter; ++it) {
     if (fabs(Ga) >= 1.0e5 || fabs(Gb) >= 1.0e5)
       c = 0.5 * (a + b);
@@ -969,16 +981,18 @@ static shot_t refine(worker_t* W, const scene_t* S, const orc_solve_spec* sp, do
     if (sh.status == SHOT_RECV && fabs(sh.miss) <= sp->miss_tol) break;
     if (miss_sign(sh.miss) == miss_sign(Ga)) {
       a = c;
-      Ga = sh.miss;
+      Ga = ma = sh.miss;
       if (last == 1) Gb *= 0.5;
       last = 1;
     } else {
       b = c;
-      Gb = sh.miss;
+      Gb = mb = sh.miss;
       if (last == -1) Ga *= 0.5;
       last = -1;
     }
-    if (fabs(b - a) <= 1e-13) break;
+    if (fabs(b - a) <= SOLVE_WIDTH_MIN) break;
+    if (sp->slope_max > 0.0 && finite_miss(ma) + finite_miss(mb) > sp->slope_max * fabs(b - a))
+      break;
   }
   *theta = c;
   return sh;

@@ -3,7 +3,8 @@ include/radiotrace_solve.h).
 
 The functions carry the C names (rt_abi_version, rt_validate,
 rt_workspace_bytes, raytrace_launch, rt_collect, rt_last_error,
-rt_solve_validate, rt_solve_workspace_bytes, raytrace_solve, raytrace_shoot)
+rt_solve_validate, rt_solve_workspace_bytes, raytrace_solve, raytrace_shoot,
+rt_solve_autotune)
 and only marshal arguments; every step of the tracing and solving runs in the
 HIP kernels.  PyTorch
 supplies device memory and the stream.  The library must have been built
@@ -105,7 +106,8 @@ class rt_pairs(C.Structure):
 
 class rt_solve_params(C.Structure):
     _fields_ = [("n_scan", C.c_int32), ("max_iter", C.c_int32), ("max_brackets", C.c_int32),
-                ("miss_tol", C.c_double), ("accept_tol", C.c_double)]
+                ("miss_tol", C.c_double), ("accept_tol", C.c_double),
+                ("slope_max", C.c_double)]
 
 
 SOLVE_STAT_FIELDS = ["shots", "accepted", "rejected", "relocation", "forced", "events",
@@ -190,6 +192,13 @@ def lib() -> C.CDLL:
                                      C.POINTER(rt_step_limits), C.POINTER(rt_shots),
                                      C.POINTER(rt_shot_outputs), C.c_void_p, C.c_size_t,
                                      C.c_void_p, C.POINTER(rt_tuning)]
+        L.rt_solve_autotune.restype = C.c_int
+        L.rt_solve_autotune.argtypes = [C.POINTER(rt_field), C.POINTER(rt_boundaries),
+                                        C.c_double, C.POINTER(rt_step_limits),
+                                        C.POINTER(rt_pairs), C.POINTER(rt_solve_params),
+                                        C.POINTER(rt_solve_outputs), C.c_void_p, C.c_size_t,
+                                        C.c_void_p, C.POINTER(rt_tuning),
+                                        C.POINTER(C.c_float)]
         _lib = L
     return _lib
 
@@ -382,8 +391,21 @@ def raytrace_shoot(field, boundaries, tol, limits, shots, outputs, workspace, wo
         C.c_void_p(stream), C.byref(tuning) if tuning is not None else None))
 
 
-def solve_params(n_scan=64, max_iter=60, max_brackets=4, miss_tol=1e-4, accept_tol=1e-3):
-    return rt_solve_params(n_scan, max_iter, max_brackets, miss_tol, accept_tol)
+def rt_solve_autotune(field, boundaries, tol, limits, pairs, params, outputs, workspace,
+                      workspace_bytes, stream):
+    """Returns (status, best rt_tuning, its time in ms)."""
+    best = rt_tuning()
+    ms = C.c_float(0.0)
+    st = lib().rt_solve_autotune(
+        C.byref(field), C.byref(boundaries), float(tol), C.byref(limits), C.byref(pairs),
+        C.byref(params), C.byref(outputs), C.c_void_p(workspace), C.c_size_t(workspace_bytes),
+        C.c_void_p(stream), C.byref(best), C.byref(ms))
+    return int(st), best, float(ms.value)
+
+
+def solve_params(n_scan=64, max_iter=60, max_brackets=4, miss_tol=1e-4, accept_tol=1e-3,
+                 slope_max=1e7):
+    return rt_solve_params(n_scan, max_iter, max_brackets, miss_tol, accept_tol, slope_max)
 
 
 class DeviceSolve:
@@ -424,6 +446,19 @@ class DeviceSolve:
                             self.ws_bytes, stream.cuda_stream, tuning)
         if st != RT_OK:
             raise RTError(st, rt_last_error())
+
+    def autotune(self, stream=None):
+        """Measure the launch tunings on these pairs; returns (rt_tuning, ms)."""
+        torch = self.torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        st, best, ms = rt_solve_autotune(self.desc.field, self.desc.bnd, self.desc.tol,
+                                         self.desc.limits, self.pairs, self.params, self.out,
+                                         self.workspace.data_ptr(), self.ws_bytes,
+                                         stream.cuda_stream)
+        if st != RT_OK:
+            raise RTError(st, rt_last_error())
+        return best, ms
 
     def stats(self) -> Dict[str, int]:
         v = self.stats_dev.cpu().numpy()

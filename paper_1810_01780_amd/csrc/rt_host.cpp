@@ -200,6 +200,10 @@ rt_status rt_solve_validate(const rt_field* field, const rt_boundaries* bnd, dou
                          "1 <= max_brackets <= 16");
       return RT_ERR_INVALID_ARG;
     }
+    if (!(prm->slope_max >= 0.0) || !std::isfinite(prm->slope_max)) {
+      rt::set_last_error("slope_max must be >= 0 (0 = off)");
+      return RT_ERR_INVALID_ARG;
+    }
     if (!(prm->miss_tol > 0.0) || !(prm->accept_tol >= prm->miss_tol) ||
         !std::isfinite(prm->accept_tol)) {
       rt::set_last_error("need 0 < miss_tol <= accept_tol < inf");

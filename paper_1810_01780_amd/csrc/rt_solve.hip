@@ -34,7 +34,13 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kMissAbove = -1.0e6;  // touched the surface: passed above the receiver
 constexpr double kMissLost = 1.0e6;    // never met the receiver plane
 constexpr double kBisectAbove = 1.0e5; // |miss| from which an end counts as a failed shot
-constexpr double kBracketMin = 1e-13;  // refinement stops below this bracket width (rad)
+// Refinement of a bracket stops below kBracketMin (rad), or when its end
+// misses cannot belong to a root: a miss continuous on [a, b] with slope at
+// most slope_max (m/rad) and a zero inside has |m(a)| + |m(b)| <=
+// slope_max (b - a); failed-shot ends (|miss| >= kBisectAbove) count zero.
+// Brackets around jumps of the miss (surface contact or loss setting in,
+// total reflection at a layer) end this way.
+constexpr double kBracketMin = 1e-9;
 constexpr int kRecv = kMaxBnd;         // boundary index of the receiver plane
 
 // Statistics rows, in the order of rt_solve_stats.
@@ -53,7 +59,7 @@ struct KSolve {
   int64_t n;                     // pairs or shots
   int64_t n_tasks;
   int32_t n_scan, max_iter, max_brackets, refill;
-  double miss_tol, accept_tol, dtheta;
+  double miss_tol, accept_tol, slope_max, dtheta;
   uint64_t* tickets;  // one counter per phase
   double* scan_miss;  // [2 n][n_scan]
   // per bracket, [max_brackets][2 n]; b_status -1 = no such bracket
@@ -217,6 +223,9 @@ __device__ __forceinline__ ShotEnd shot_event(const KParams& P, const KSolve& V,
 }
 
 __device__ __forceinline__ int miss_sign(double m) { return m < 0.0 ? -1 : 1; }
+__device__ __forceinline__ double finite_miss(double m) {
+  return fabs(m) < kBisectAbove ? fabs(m) : 0.0;
+}
 
 // Next Illinois iterate of a bracket (bisection while an end is a failed
 // shot).
@@ -244,6 +253,7 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
   __shared__ double s_ra[PHASE == PH_REFINE ? 256 : 1], s_rGa[PHASE == PH_REFINE ? 256 : 1];
   __shared__ double s_rb[PHASE == PH_REFINE ? 256 : 1], s_rGb[PHASE == PH_REFINE ? 256 : 1];
   __shared__ double s_rc[PHASE == PH_REFINE ? 256 : 1];
+  __shared__ double s_rma[PHASE == PH_REFINE ? 256 : 1], s_rmb[PHASE == PH_REFINE ? 256 : 1];
   __shared__ int32_t s_rm[PHASE == PH_REFINE ? 256 : 1];
   __syncthreads();
 
@@ -297,21 +307,25 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
         int last = (meta & 3) - 1;
         const int it = (meta >> 2) + 1;
         double a = s_ra[tid], Ga = s_rGa[tid], b = s_rb[tid], Gb = s_rGb[tid];
+        double ma = s_rma[tid], mb = s_rmb[tid];
         const double c = s_rc[tid];
         bool done = fin.status == RT_SHOT_RECEIVER && fabs(fin.miss) <= V.miss_tol;
         if (!done) {
           if (miss_sign(fin.miss) == miss_sign(Ga)) {
             a = c;
-            Ga = fin.miss;
+            Ga = ma = fin.miss;
             if (last == 1) Gb *= 0.5;
             last = 1;
           } else {
             b = c;
-            Gb = fin.miss;
+            Gb = mb = fin.miss;
             if (last == -1) Ga *= 0.5;
             last = -1;
           }
-          if (fabs(b - a) <= kBracketMin || it >= V.max_iter) done = true;
+          if (fabs(b - a) <= kBracketMin || it >= V.max_iter ||
+              (V.slope_max > 0.0 &&
+               finite_miss(ma) + finite_miss(mb) > V.slope_max * fabs(b - a)))
+            done = true;
         }
         if (done) {
           V.b_theta[t] = c;
@@ -330,6 +344,8 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
           s_rGa[tid] = Ga;
           s_rb[tid] = b;
           s_rGb[tid] = Gb;
+          s_rma[tid] = ma;
+          s_rmb[tid] = mb;
           s_rm[tid] = (it << 2) | (last + 1);
           const double cn = illinois_next(a, Ga, b, Gb);
           s_rc[tid] = cn;
@@ -424,6 +440,8 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
               s_rGa[tid] = Ga;
               s_rb[tid] = bb;
               s_rGb[tid] = Gb;
+              s_rma[tid] = Ga;
+              s_rmb[tid] = Gb;
               s_rm[tid] = 1;  // no iterations, last side 0
               theta = illinois_next(a, Ga, bb, Gb);
               s_rc[tid] = theta;
@@ -842,6 +860,7 @@ extern "C" rt_status raytrace_solve(const rt_field* field, const rt_boundaries* 
   V.refill = refill;
   V.miss_tol = prm->miss_tol;
   V.accept_tol = prm->accept_tol;
+  V.slope_max = prm->slope_max;
   V.dtheta = kPi / (double)prm->n_scan;
   char* w = static_cast<char*>(workspace);
   V.tickets = reinterpret_cast<uint64_t*>(w);
@@ -939,4 +958,62 @@ extern "C" rt_status raytrace_shoot(const rt_field* field, const rt_boundaries* 
   if (tuning && tuning->ev_trace_end)
     HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(tuning->ev_trace_end), s));
   return RT_OK;
+}
+
+extern "C" rt_status rt_solve_autotune(const rt_field* field, const rt_boundaries* bnd,
+                                       double tol, const rt_step_limits* L,
+                                       const rt_pairs* pairs, const rt_solve_params* prm,
+                                       rt_solve_outputs* out, void* workspace,
+                                       size_t workspace_bytes, void* stream, rt_tuning* best,
+                                       float* best_ms) {
+  using namespace rt;
+  if (!best) {
+    set_last_error("null tuning output");
+    return RT_ERR_INVALID_ARG;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    set_last_error("hipEventCreate failed");
+    return RT_ERR_DEVICE;
+  }
+  static const int kBlocks[] = {64, 128, 192, 256};
+  static const int kRefill[] = {4, 16, 32, 64};
+  rt_status st = RT_OK;
+  float best_t = -1.0f;
+  rt_tuning cand;
+  memset(&cand, 0, sizeof cand);
+  // one untimed call first (code load, caches)
+  cand.block_size = 256;
+  cand.refill_threshold = 16;
+  st = raytrace_solve(field, bnd, tol, L, pairs, prm, out, workspace, workspace_bytes, stream,
+                      &cand);
+  for (int bi = 0; st == RT_OK && bi < 4; ++bi)
+    for (int ri = 0; st == RT_OK && ri < 4; ++ri) {
+      cand.block_size = kBlocks[bi];
+      cand.refill_threshold = kRefill[ri];
+      hipError_t e = hipEventRecord(e0, s);
+      if (e == hipSuccess)
+        st = raytrace_solve(field, bnd, tol, L, pairs, prm, out, workspace, workspace_bytes,
+                            stream, &cand);
+      if (e == hipSuccess && st == RT_OK) e = hipEventRecord(e1, s);
+      if (e == hipSuccess && st == RT_OK) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess && st == RT_OK) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        set_last_error("autotune timing: %s", hipGetErrorString(e));
+        st = RT_ERR_DEVICE;
+        break;
+      }
+      if (st == RT_OK && (best_t < 0.0f || ms < best_t)) {
+        best_t = ms;
+        *best = cand;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == RT_OK && best_ms) *best_ms = best_t;
+  return st;
 }

@@ -178,7 +178,8 @@ def test_solve_validate():
     assert B.rt_solve_validate(d3.field, d3.bnd, d3.tol, d3.limits, p) == B.RT_ERR_INVALID_ARG
     assert B.rt_solve_validate(d.field, d.bnd, 0.0, d.limits, p) == B.RT_ERR_INVALID_ARG
     for bad in (dict(n_scan=1), dict(n_scan=5000), dict(max_iter=0), dict(max_brackets=17),
-                dict(miss_tol=0.0), dict(miss_tol=1e-3, accept_tol=1e-4)):
+                dict(miss_tol=0.0), dict(miss_tol=1e-3, accept_tol=1e-4),
+                dict(slope_max=-1.0), dict(slope_max=float("inf"))):
         q = B.solve_params(**bad)
         assert B.rt_solve_validate(d.field, d.bnd, d.tol, d.limits, q) == B.RT_ERR_INVALID_ARG
         assert B.rt_last_error()

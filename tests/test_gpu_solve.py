@@ -175,6 +175,15 @@ def test_solves_match_oracle(gpu, oracle_lib, model):
     assert gst["shots"] >= 2 * sp.n * 64
 
 
+def test_solve_without_slope_bound(gpu, oracle_lib):
+    """slope_max = 0 (brackets refined down to the width limit) on both sides."""
+    sp = W.solve_pairs(64)
+    _announce("solve-noslope", sp.n)
+    g, gst = gpu.solve(sp.scene, sp.zs, sp.zr, sp.dist, params=gpu.solve_params(slope_max=0.0))
+    o = oracle_lib.solve(sp.scene, sp.zs, sp.zr, sp.dist, slope_max=0.0)
+    compare_solves(oracle_lib, g, o, sp.scene, (sp.zs, sp.zr, sp.dist), "solve-noslope")
+
+
 def test_solve_invalid_and_empty(gpu):
     sc = W.solve_pairs(1).scene
     zs = np.array([500.0, float("nan"), 500.0, 0.0, 700.0])

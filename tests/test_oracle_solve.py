@@ -195,3 +195,18 @@ def test_invalid_shots(oracle_lib):
     s = oracle_lib.solve(sc, [300.0, 0.0], [50.0, 50.0], [100.0, 100.0])
     assert s["found"][0].tolist() == [1, 1] and s["found"][1].tolist() == [0, 0]
     assert s["shots"][1].tolist() == [0, 0]
+
+
+def test_slope_bound_only_drops_jumps(oracle_lib):
+    """The bracket stop on the slope bound ends refinements around jumps of
+    the miss early and loses no solution: with and without it the same
+    entries are solved, by the same shots."""
+    sp = W.solve_pairs(192)
+    on = oracle_lib.solve(sp.scene, sp.zs, sp.zr, sp.dist, slope_max=1e7)
+    off = oracle_lib.solve(sp.scene, sp.zs, sp.zr, sp.dist, slope_max=0.0)
+    assert np.array_equal(on["found"], off["found"])
+    f = on["found"] == 1
+    for k in ("theta", "miss", "t", "s", "as_re", "ap_re"):
+        assert np.array_equal(on[k][f], off[k][f]), k
+    # both take the same scan shots; the refinement shots drop
+    assert (on["shots"] - 64).sum() < 0.5 * (off["shots"] - 64).sum()
