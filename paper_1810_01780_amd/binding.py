@@ -139,6 +139,15 @@ class rt_shot_outputs(C.Structure):
     _fields_ = [(f, C.c_void_p) for f in SHOT_I32 + SHOT_F64] + [("stats", C.c_void_p)]
 
 
+# --- surrogate network (include/radiotrace_mlp.h) ---------------------------
+RT_MLP_IN, RT_MLP_WIDTH, RT_MLP_HIDDEN, RT_MLP_OUT, RT_MLP_TARGETS = 5, 256, 4, 10, 8
+
+
+class rt_adam(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
+
+
 _lib = None
 
 
@@ -199,6 +208,21 @@ def lib() -> C.CDLL:
                                         C.POINTER(rt_solve_outputs), C.c_void_p, C.c_size_t,
                                         C.c_void_p, C.POINTER(rt_tuning),
                                         C.POINTER(C.c_float)]
+        L.rt_mlp_param_count.restype = C.c_int64
+        L.rt_mlp_param_count.argtypes = []
+        L.rt_mlp_workspace_bytes.restype = C.c_int
+        L.rt_mlp_workspace_bytes.argtypes = [C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
+        L.rt_mlp_pack.restype = C.c_int
+        L.rt_mlp_pack.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.rt_mlp_forward.restype = C.c_int
+        L.rt_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
+                                     C.c_size_t, C.c_void_p]
+        L.rt_mlp_gradients.restype = C.c_int
+        L.rt_mlp_gradients.argtypes = [C.c_void_p] * 4 + [C.c_int64, C.c_void_p, C.c_void_p,
+                                                         C.c_void_p, C.c_size_t, C.c_void_p]
+        L.rt_mlp_adam.restype = C.c_int
+        L.rt_mlp_adam.argtypes = [C.c_void_p] * 4 + [C.c_int64, C.POINTER(rt_adam), C.c_void_p,
+                                                    C.c_size_t, C.c_void_p]
         _lib = L
     return _lib
 
@@ -506,3 +530,104 @@ def shoot(scene: W.Scene, zs, zr, dist, theta, family, tuning: Optional[rt_tunin
     v = stats_dev.cpu().numpy()
     return ({f: t[:n].cpu().numpy() for f, t in res.items()},
             {f: int(v[i]) for i, f in enumerate(SOLVE_STAT_FIELDS)})
+
+
+# --- surrogate network: C entry points and a device-side holder ---------------
+def rt_mlp_param_count() -> int:
+    return int(lib().rt_mlp_param_count())
+
+
+def rt_mlp_workspace_bytes(batch: int, training: bool) -> int:
+    n = C.c_size_t(0)
+    st = lib().rt_mlp_workspace_bytes(C.c_int64(batch), C.c_int32(1 if training else 0),
+                                      C.byref(n))
+    if st != RT_OK:
+        raise RTError(st, rt_last_error())
+    return int(n.value)
+
+
+def rt_mlp_pack(params, workspace, workspace_bytes, stream) -> int:
+    return int(lib().rt_mlp_pack(C.c_void_p(params), C.c_void_p(workspace),
+                                 C.c_size_t(workspace_bytes), C.c_void_p(stream)))
+
+
+def rt_mlp_forward(params, x, batch, y, workspace, workspace_bytes, stream) -> int:
+    return int(lib().rt_mlp_forward(C.c_void_p(params), C.c_void_p(x), C.c_int64(batch),
+                                    C.c_void_p(y), C.c_void_p(workspace),
+                                    C.c_size_t(workspace_bytes), C.c_void_p(stream)))
+
+
+def rt_mlp_gradients(params, x, targets, mask, batch, grad, loss, workspace, workspace_bytes,
+                     stream) -> int:
+    return int(lib().rt_mlp_gradients(
+        C.c_void_p(params), C.c_void_p(x), C.c_void_p(targets), C.c_void_p(mask),
+        C.c_int64(batch), C.c_void_p(grad), C.c_void_p(loss), C.c_void_p(workspace),
+        C.c_size_t(workspace_bytes), C.c_void_p(stream)))
+
+
+def rt_mlp_adam(params, m, v, grad, step, hp, workspace, workspace_bytes, stream) -> int:
+    return int(lib().rt_mlp_adam(C.c_void_p(params), C.c_void_p(m), C.c_void_p(v),
+                                 C.c_void_p(grad), C.c_int64(step), C.byref(hp),
+                                 C.c_void_p(workspace), C.c_size_t(workspace_bytes),
+                                 C.c_void_p(stream)))
+
+
+class DeviceMLP:
+    """FP32 parameters, Adam moments, gradient and workspace of the surrogate
+    network on the GPU (torch tensors), for batches of up to max_batch rows."""
+
+    def __init__(self, params, max_batch: int, training: bool = True, device="cuda"):
+        import torch
+        self.torch = torch
+        dev = torch.device(device)
+        self.device = dev
+        n = rt_mlp_param_count()
+        p = np.ascontiguousarray(params, np.float32)
+        assert p.shape == (n,), f"expected {n} parameters"
+        self.params = torch.as_tensor(p.copy(), device=dev)
+        self.training = training
+        self.max_batch = int(max_batch)
+        self.ws_bytes = rt_mlp_workspace_bytes(self.max_batch, training)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        if training:
+            self.m = torch.zeros(n, dtype=torch.float32, device=dev)
+            self.v = torch.zeros(n, dtype=torch.float32, device=dev)
+            self.grad = torch.zeros(n, dtype=torch.float32, device=dev)
+            self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+            self.step = 0
+        self.pack()
+
+    def _stream(self):
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def _check(self, st):
+        if st != RT_OK:
+            raise RTError(st, rt_last_error())
+
+    def pack(self):
+        self._check(rt_mlp_pack(self.params.data_ptr(), self.workspace.data_ptr(),
+                                self.ws_bytes, self._stream()))
+
+    def forward(self, x, y):
+        """x: device FP32 [B][5] tensor; y: device FP32 [B][10] tensor (written)."""
+        B = int(x.shape[0])
+        self._check(rt_mlp_forward(self.params.data_ptr(), x.data_ptr(), B, y.data_ptr(),
+                                   self.workspace.data_ptr(), self.ws_bytes, self._stream()))
+
+    def gradients(self, x, t, m):
+        """Fills self.grad and self.loss for a batch of device tensors."""
+        B = int(x.shape[0])
+        self._check(rt_mlp_gradients(self.params.data_ptr(), x.data_ptr(), t.data_ptr(),
+                                     m.data_ptr(), B, self.grad.data_ptr(), self.loss.data_ptr(),
+                                     self.workspace.data_ptr(), self.ws_bytes, self._stream()))
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step += 1
+        hp = rt_adam(lr, beta1, beta2, eps)
+        self._check(rt_mlp_adam(self.params.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                                self.grad.data_ptr(), self.step, hp, self.workspace.data_ptr(),
+                                self.ws_bytes, self._stream()))
+
+    def train_step(self, x, t, m, lr):
+        self.gradients(x, t, m)
+        self.adam(lr)

@@ -302,3 +302,19 @@ WORKLOADS = {
     "grid256": gridded,
     "paper_example": paper_example,
 }
+
+
+# --- surrogate network inputs -----------------------------------------------
+MLP_DIMS = [(5, 256), (256, 256), (256, 256), (256, 256), (256, 10)]
+
+
+def mlp_init_params(seed: int = 0) -> np.ndarray:
+    """Seeded initial parameters of the surrogate network, FP32, in the
+    layout of the C header (per layer W [n_out][n_in], then b [n_out]):
+    normal weights with variance 2 / n_in (He), zero biases."""
+    rng = np.random.default_rng(np.random.SeedSequence([MASTER_SEED, 4, seed]))
+    parts = []
+    for n_in, n_out in MLP_DIMS:
+        parts.append((rng.standard_normal(n_in * n_out) * np.sqrt(2.0 / n_in)).astype(np.float32))
+        parts.append(np.zeros(n_out, np.float32))
+    return np.concatenate(parts)
