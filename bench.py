@@ -203,13 +203,112 @@ def bench_solve(args, log):
     print(json.dumps(out), flush=True)
 
 
+def bench_surrogate(args, log):
+    """Surrogate-seeded solves of the 65,536-pair workload: the network is
+    trained first on the GPU (tracer solves of 128 profiles x 8,192 pairs,
+    6,000 Adam steps; not timed), then a step is one replay of the captured
+    raytrace_solve_surrogate graph (network, seeded secant with shot
+    verification, tracer fallback).  The tracer's own graph is timed beside
+    it on the same pairs."""
+    import torch
+    from paper_1810_01780_amd import binding
+    from paper_1810_01780_amd import surrogate
+    from paper_1810_01780_amd import workloads as W
+    t0 = time.perf_counter()
+    net, losses = surrogate.default_model(seed=0, n_profiles=128, pairs_per_profile=8192,
+                                          steps=6000, log=log)
+    train_s = time.perf_counter() - t0
+    sp = W.solve_pairs()
+    prm = binding.solve_params()
+    spar = binding.surrogate_params(z0=75.0, dn=0.43)
+    ds = binding.DeviceSurrogateSolve(sp.scene, sp.zs, sp.zr, sp.dist, spar, prm)
+    tr = binding.DeviceSolve(sp.scene, sp.zs, sp.zr, sp.dist, prm)
+
+    def graph_of(fn):
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn(s)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            fn(None)
+        return g
+
+    g_su = graph_of(lambda s: ds.launch(net.params, stream=s))
+    g_tr = graph_of(lambda s: tr.launch(stream=s))
+
+    def timed(g):
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / args.steps
+    t_su = timed(g_su)
+    t_tr = timed(g_tr)
+    res, st = ds.collect()
+    rres, rst = tr.collect()
+    path = res["path"]
+    found_s, found_t = int(res["found"].sum()), int(rres["found"].sum())
+    false_absent = int(((path == binding.RT_PATH_ABSENT) & (rres["found"] == 1)).sum())
+    # network forward alone (events on the stream), for its matrix-core rate
+    hip = _hip()
+    e0, e1 = ctypes.c_void_p(), ctypes.c_void_p()
+    hip.hipEventCreate(ctypes.byref(e0))
+    hip.hipEventCreate(ctypes.byref(e1))
+    inf = binding.DeviceMLP(net.params.cpu().numpy(), max_batch=sp.n, training=False)
+    x = torch.randn((sp.n, 5), device="cuda")
+    y = torch.empty((sp.n, 10), device="cuda")
+    inf.forward(x, y)
+    stream = torch.cuda.current_stream().cuda_stream
+    hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    hip.hipEventRecord(e0, ctypes.c_void_p(stream))
+    for _ in range(10):
+        inf.forward(x, y)
+    hip.hipEventRecord(e1, ctypes.c_void_p(stream))
+    hip.hipEventSynchronize(e1)
+    ms = ctypes.c_float()
+    hip.hipEventElapsedTime(ctypes.byref(ms), e0, e1)
+    mlp_s = ms.value / 10 / 1e3
+    mlp_flop = 2.0 * sp.n * (5 * 256 + 3 * 256 * 256 + 256 * 10)
+    trials = st["accepted"] + st["rejected"] + st["relocation"]
+    achieved = trials * FLOP_PER_TRIAL_STRAT_PAPER / t_su / 1e12
+    cfg = dict(workload="solve65536-surrogate", pairs=sp.n, network="5-256x4-10 SiLU, BF16 MFMA",
+               training_pairs=128 * 8192, training_steps=6000, training_s=round(train_s, 1),
+               final_loss=losses[-1][1], verify_tol_m=spar.verify_tol, max_shots=spar.max_shots,
+               absent_logit=spar.absent_logit, fallback_pairs=st["fallback_pairs"],
+               found=found_s, tracer_found=found_t, false_absent=false_absent,
+               shots=st["shots"], tracer_shots=rst["shots"],
+               tracer_solves_per_s=sp.n / t_tr, gain_vs_tracer=t_tr / t_su,
+               mlp_forward_ms=mlp_s * 1e3, mlp_tflops=mlp_flop / mlp_s / 1e12)
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+            "kernel": "shot_kernel (seeded + fallback), whole-launch time",
+            "kernel_ms": t_su * 1e3}
+    log(f"surrogate {t_su * 1e3:.2f} ms vs tracer {t_tr * 1e3:.2f} ms per 65,536 pairs; "
+        f"{st['fallback_pairs']} fallback pairs")
+    out = {"metric": "emitter->receiver solves/s (surrogate-seeded, shot-verified)",
+           "value": sp.n / t_su, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": t_su * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64+bf16", "data": "synthetic",
+           "config": cfg, "roofline": roof}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_solve_baseline(sp, args.cpu_seconds,
+                                                 min(args.cpu_threads, os.cpu_count() or 1), log)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="twolayer",
-                    choices=["twolayer", "grid256", "fan1024", "solve"])
+                    choices=["twolayer", "grid256", "fan1024", "solve", "surrogate"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -230,6 +329,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "solve":
         return bench_solve(args, log)
+    if args.workload == "surrogate":
+        return bench_surrogate(args, log)
     scene, cfg = make_scene(args.workload)
     log(f"workload {cfg['workload']}: {scene.n_rays} rays")
     ds = binding.DeviceScene(scene)

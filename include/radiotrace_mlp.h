@@ -37,6 +37,7 @@
 #define RADIOTRACE_MLP_H
 
 #include "radiotrace.h"
+#include "radiotrace_solve.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -83,6 +84,86 @@ typedef struct {
 rt_status rt_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t step,
                       const rt_adam* hp, void* workspace, size_t workspace_bytes,
                       void* stream);
+
+/* ------------------------------------------------------------------------
+ * Surrogate-seeded solves.
+ *
+ * Normalisation of the network's inputs and outputs (the definition the
+ * feature, target and decode kernels implement):
+ *   features  x0 = (zs - 1025)/975, x1 = (zr - 100)/100,
+ *             x2 = (dist - 1505)/1495, x3 = (z0 - 80)/40,
+ *             x4 = (dn - 0.425)/0.075
+ *             (z0, dn: scale depth and index contrast of the firn profile
+ *             n = a - dn exp(-z/z0); the ranges map to [-1, 1])
+ *   targets   per family f (outputs 4f .. 4f+3):
+ *             theta / (pi/2) - 1, c0 t / 3000 m - 1, s / 3000 m - 1,
+ *             2 A - 1 with A = sqrt((|A_s|^2 + |A_p|^2) / 2);
+ *             mask m_f = 1 where the tracer found the solution
+ *   logits    outputs 8 + f: existence of family f's solution.
+ *
+ * Seeded secant of one (pair, family) entry: shot at the seed theta0, then
+ * at theta0 + dseed (theta0 - dseed if that leaves (0, pi)), then secant
+ * steps theta_{k+1} = theta_k - m_k (theta_k - theta_{k-1}) / (m_k -
+ * m_{k-1}); the entry is solved by the first shot that meets the receiver
+ * plane with |miss| <= verify_tol (that shot is its verification), and
+ * fails at a shot that does not meet the receiver plane, a step outside
+ * (0, pi), or after max_shots shots. */
+typedef struct {
+  double z0, dn;       /* profile features of the medium */
+  double verify_tol;   /* |miss| of the verifying shot (m), > 0 */
+  double dseed;        /* second shot offset (rad), > 0 */
+  int32_t max_shots;   /* shots per seeded entry, 2..64 */
+  float absent_logit;  /* existence logit at or below which an entry is
+                          declared absent without tracing */
+} rt_surrogate_params;
+
+/* How each entry [2 pair + family] of a surrogate solve was decided. */
+enum {
+  RT_PATH_SURROGATE = 0, /* network seed, verified by a shot */
+  RT_PATH_TRACER = 1,    /* the pair went to the tracer's full solve */
+  RT_PATH_ABSENT = 2     /* declared absent by the network (not traced) */
+};
+
+/* Seeded secant (above) of every entry [2 n] with seed_try != 0: results
+ * into out (found = verified; the other fields those of the verifying
+ * shot), verify[2 n] = 1 (verified) or 0 (not) for the tried entries,
+ * untouched otherwise.  Workspace: 4 KiB. */
+rt_status raytrace_solve_seeded(const rt_field* field, const rt_boundaries* boundaries,
+                                double tol, const rt_step_limits* limits,
+                                const rt_pairs* pairs, const double* seed,
+                                const int32_t* seed_try, const rt_surrogate_params* sp,
+                                rt_solve_outputs* out, int32_t* verify, void* workspace,
+                                size_t workspace_bytes, void* stream, const rt_tuning* tuning);
+
+/* Features [n][5] (FP32) of the pairs in the profile (z0, dn). */
+rt_status rt_surrogate_features(const rt_pairs* pairs, double z0, double dn, float* x,
+                                void* stream);
+
+/* Training targets [n][8] and masks [n][2] (FP32) from solve results. */
+rt_status rt_surrogate_targets(const rt_solve_outputs* solved, int64_t n, float* targets,
+                               float* mask, void* stream);
+
+/* Workspace bytes of raytrace_solve_surrogate for n_pairs pairs. */
+rt_status rt_surrogate_workspace_bytes(const rt_field* field, int64_t n_pairs,
+                                       const rt_solve_params* fallback, size_t* bytes);
+
+/* Solve every pair with the network as seed: features -> network
+ * (mlp_params, FP32 device array) -> per entry either declared absent
+ * (logit <= absent_logit) or tried by the seeded secant; a pair with an
+ * entry that was tried and not verified is solved again, both families, by
+ * the tracer's full solve (raytrace_solve with 'fallback'), on the device
+ * (no host synchronisation).  Results in out as for raytrace_solve; path
+ * [2 n] (device) receives RT_PATH_*; *fallback_pairs (device, one int64)
+ * the number of pairs solved by the tracer; out->stats the shots and steps
+ * of the seeded phase plus the fallback solve. */
+rt_status raytrace_solve_surrogate(const rt_field* field, const rt_boundaries* boundaries,
+                                   double tol, const rt_step_limits* limits,
+                                   const rt_pairs* pairs, const rt_solve_params* fallback,
+                                   const rt_surrogate_params* sp, const float* mlp_params,
+                                   rt_solve_outputs* out, int32_t* path,
+                                   int64_t* fallback_pairs, void* workspace,
+                                   size_t workspace_bytes, void* stream,
+                                   const rt_tuning* tuning);
 
 #ifdef __cplusplus
 }

@@ -315,3 +315,40 @@ def shoot(scene, zs, zr, dist, theta, family, threads=None):
         raise ValueError("oracle: unsupported shoot problem (planes[0] must be the surface; "
                          "no box or time limit)")
     return arrs
+
+
+class SeedSpec(C.Structure):
+    _fields_ = [("verify_tol", C.c_double), ("dseed", C.c_double), ("max_shots", C.c_int32)]
+
+
+def solve_seeded(scene, zs, zr, dist, seed, try_, verify_tol=0.01, dseed=1e-4, max_shots=6,
+                 threads=None):
+    """Seeded secant per entry (seed and try_ shaped [n, 2]); results shaped
+    [n, 2] plus 'verify' (1 verified, 0 not, -1 not tried)."""
+    L = lib()
+    L.orc_solve_seeded.restype = C.c_int
+    L.orc_solve_seeded.argtypes = [C.POINTER(Problem)] + [C.POINTER(C.c_double)] * 3 + [
+        C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(SeedSpec),
+        C.POINTER(SolveOut), C.POINTER(C.c_int32), C.c_int]
+    prep = _Prepared(scene)
+    cols = [np.ascontiguousarray(a, np.float64) for a in (zs, zr, dist)]
+    n = len(cols[0])
+    sd = np.ascontiguousarray(np.asarray(seed, np.float64).reshape(2 * n))
+    tr = np.ascontiguousarray(np.asarray(try_, np.int32).reshape(2 * n))
+    prep.keep += cols + [sd, tr]
+    arrs = {f: np.zeros(2 * n, np.int32) for f in SOLVE_I32}
+    arrs.update({f: np.zeros(2 * n, np.float64) for f in SOLVE_F64})
+    verify = np.full(2 * n, -1, np.int32)
+    out = SolveOut(*([_ptr(arrs[f], C.c_int32) for f in SOLVE_I32]
+                     + [_ptr(arrs[f], C.c_double) for f in SOLVE_F64]))
+    spec = SeedSpec(verify_tol, dseed, max_shots)
+    if threads is None:
+        threads = max(1, min(os.cpu_count() or 1, 16))
+    rc = L.orc_solve_seeded(C.byref(prep.P), *[_ptr(c, C.c_double) for c in cols], n,
+                            _ptr(sd, C.c_double), _ptr(tr, C.c_int32), C.byref(spec),
+                            C.byref(out), _ptr(verify, C.c_int32), threads)
+    if rc != 0:
+        raise ValueError("oracle: unsupported solve problem")
+    res = {f: a.reshape(n, 2) for f, a in arrs.items()}
+    res["verify"] = verify.reshape(n, 2)
+    return res

@@ -135,6 +135,21 @@ int orc_shoot(const orc_problem* P, const double* zs, const double* zr, const do
               const double* theta, const int32_t* family, int64_t n, orc_shot_out* out,
               int n_threads);
 
+/* Seeded secant per entry [2 pair + family] with try_[e] != 0: shots at the
+ * seed, at seed + dseed (seed - dseed if that leaves (0, pi)), then secant
+ * steps; solved by the first shot that meets the receiver plane with
+ * |miss| <= verify_tol; fails at a shot that does not, a step outside
+ * (0, pi), or after max_shots shots.  verify[e] = 1 / 0 for tried entries. */
+typedef struct {
+  double verify_tol, dseed;
+  int32_t max_shots;
+} orc_seed_spec;
+
+int orc_solve_seeded(const orc_problem* P, const double* zs, const double* zr,
+                     const double* dist, int64_t n_pairs, const double* seed,
+                     const int32_t* try_, const orc_seed_spec* spec, orc_solve_out* out,
+                     int32_t* verify, int n_threads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1153,6 +1153,114 @@ int orc_shoot(const orc_problem* P, const double* zs, const double* zr, const do
   return 0;
 }
 
+/* Seeded secant of one entry (see oracle.h). */
+static void seeded_one(worker_t* W, const scene_t* base, const double* zs_, const double* zr_,
+                       const double* dist_, const double* seed, const orc_seed_spec* sp,
+                       int64_t e, orc_solve_out* out, int32_t* verify) {
+  const double PI = 3.14159265358979323846;
+  const int64_t i = e / 2;
+  const int family = (int)(e % 2);
+  const double zs = zs_[i], zr = zr_[i], D = dist_[i];
+  double c = seed[e];
+  int shots = 0, success = 0;
+  shot_t sh;
+  memset(&sh, 0, sizeof sh);
+  if (pair_ok(base, zs, zr, D) && c > 0.0 && c < PI) {
+    scene_t S = *base;
+    add_receiver(&S, D);
+    const scene_t* saved = W->S;
+    W->S = &S;
+    double cp = 0.0, mp = 0.0;
+    for (;;) {
+      sh = shoot(W, &S, zs, zr, D, c, family);
+      ++shots;
+      const int recv = sh.status == SHOT_RECV;
+      success = recv && fabs(sh.miss) <= sp->verify_tol;
+      if (success || !recv || shots >= sp->max_shots) break;
+      double cn;
+      if (shots == 1)
+        cn = c + sp->dseed < PI ? c + sp->dseed : c - sp->dseed;
+      else
+        cn = c - sh.miss * (c - cp) / (sh.miss - mp);
+      if (!(cn > 0.0 && cn < PI)) break;
+      cp = c;
+      mp = sh.miss;
+      c = cn;
+    }
+    W->S = saved;
+  }
+  out->found[e] = success;
+  out->shots[e] = shots;
+  out->theta[e] = success ? c : 0.0;
+  out->miss[e] = success ? sh.miss : 0.0;
+  out->t[e] = success ? sh.t : 0.0;
+  out->s[e] = success ? sh.s : 0.0;
+  out->as_re[e] = success ? sh.as_re : 0.0;
+  out->as_im[e] = success ? sh.as_im : 0.0;
+  out->ap_re[e] = success ? sh.ap_re : 0.0;
+  out->ap_im[e] = success ? sh.ap_im : 0.0;
+  verify[e] = success;
+}
+
+typedef struct {
+  const scene_t* base;
+  const double *zs, *zr, *dist, *seed;
+  const int32_t* try_;
+  const orc_seed_spec* sp;
+  int64_t n;
+  int64_t* next;
+  orc_solve_out* out;
+  int32_t* verify;
+  worker_t W;
+  pthread_t th;
+} seeded_job_t;
+
+static void* run_seeded(void* arg) {
+  seeded_job_t* J = (seeded_job_t*)arg;
+  for (;;) {
+    int64_t e = __atomic_fetch_add(J->next, 1, __ATOMIC_RELAXED);
+    if (e >= J->n) break;
+    if (J->try_[e])
+      seeded_one(&J->W, J->base, J->zs, J->zr, J->dist, J->seed, J->sp, e, J->out, J->verify);
+  }
+  return NULL;
+}
+
+int orc_solve_seeded(const orc_problem* P, const double* zs, const double* zr,
+                     const double* dist, int64_t n_pairs, const double* seed,
+                     const int32_t* try_, const orc_seed_spec* spec, orc_solve_out* out,
+                     int32_t* verify, int n_threads) {
+  if (P->n_planes < 1 || P->n_planes > 16 || P->has_box || P->t_max > 0.0) return -2;
+  scene_t S;
+  build_scene(P, &S);
+  if (n_threads < 1) n_threads = 1;
+  int64_t next = 0;
+  seeded_job_t* jobs = (seeded_job_t*)calloc((size_t)n_threads, sizeof(seeded_job_t));
+  for (int t = 0; t < n_threads; ++t) {
+    seeded_job_t* J = &jobs[t];
+    J->base = &S;
+    J->zs = zs;
+    J->zr = zr;
+    J->dist = dist;
+    J->seed = seed;
+    J->try_ = try_;
+    J->sp = spec;
+    J->n = 2 * n_pairs;
+    J->next = &next;
+    J->out = out;
+    J->verify = verify;
+    J->W.S = &S;
+  }
+  if (n_threads == 1) {
+    run_seeded(&jobs[0]);
+  } else {
+    for (int t = 0; t < n_threads; ++t) pthread_create(&jobs[t].th, NULL, run_seeded, &jobs[t]);
+    for (int t = 0; t < n_threads; ++t) pthread_join(jobs[t].th, NULL);
+  }
+  free(jobs);
+  return 0;
+}
+
 int orc_solve(const orc_problem* P, const orc_solve_spec* sp, const int64_t* pairs,
               int64_t n_pairs, orc_solve_out* out, int n_threads) {
   if (P->n_planes < 1 || P->n_planes > 16 || P->has_box || P->t_max > 0.0) return -2;

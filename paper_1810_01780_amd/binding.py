@@ -148,6 +148,14 @@ class rt_adam(C.Structure):
                 ("eps", C.c_float)]
 
 
+RT_PATH_SURROGATE, RT_PATH_TRACER, RT_PATH_ABSENT = 0, 1, 2
+
+
+class rt_surrogate_params(C.Structure):
+    _fields_ = [("z0", C.c_double), ("dn", C.c_double), ("verify_tol", C.c_double),
+                ("dseed", C.c_double), ("max_shots", C.c_int32), ("absent_logit", C.c_float)]
+
+
 _lib = None
 
 
@@ -223,6 +231,28 @@ def lib() -> C.CDLL:
         L.rt_mlp_adam.restype = C.c_int
         L.rt_mlp_adam.argtypes = [C.c_void_p] * 4 + [C.c_int64, C.POINTER(rt_adam), C.c_void_p,
                                                     C.c_size_t, C.c_void_p]
+        L.raytrace_solve_seeded.restype = C.c_int
+        L.raytrace_solve_seeded.argtypes = [
+            C.POINTER(rt_field), C.POINTER(rt_boundaries), C.c_double, C.POINTER(rt_step_limits),
+            C.POINTER(rt_pairs), C.c_void_p, C.c_void_p, C.POINTER(rt_surrogate_params),
+            C.POINTER(rt_solve_outputs), C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
+            C.POINTER(rt_tuning)]
+        L.rt_surrogate_features.restype = C.c_int
+        L.rt_surrogate_features.argtypes = [C.POINTER(rt_pairs), C.c_double, C.c_double,
+                                            C.c_void_p, C.c_void_p]
+        L.rt_surrogate_targets.restype = C.c_int
+        L.rt_surrogate_targets.argtypes = [C.POINTER(rt_solve_outputs), C.c_int64, C.c_void_p,
+                                           C.c_void_p, C.c_void_p]
+        L.rt_surrogate_workspace_bytes.restype = C.c_int
+        L.rt_surrogate_workspace_bytes.argtypes = [C.POINTER(rt_field), C.c_int64,
+                                                   C.POINTER(rt_solve_params),
+                                                   C.POINTER(C.c_size_t)]
+        L.raytrace_solve_surrogate.restype = C.c_int
+        L.raytrace_solve_surrogate.argtypes = [
+            C.POINTER(rt_field), C.POINTER(rt_boundaries), C.c_double, C.POINTER(rt_step_limits),
+            C.POINTER(rt_pairs), C.POINTER(rt_solve_params), C.POINTER(rt_surrogate_params),
+            C.c_void_p, C.POINTER(rt_solve_outputs), C.c_void_p, C.c_void_p, C.c_void_p,
+            C.c_size_t, C.c_void_p, C.POINTER(rt_tuning)]
         _lib = L
     return _lib
 
@@ -631,3 +661,107 @@ class DeviceMLP:
     def train_step(self, x, t, m, lr):
         self.gradients(x, t, m)
         self.adam(lr)
+
+
+# --- surrogate-seeded solves ----------------------------------------------------
+def surrogate_params(z0=75.0, dn=0.43, verify_tol=0.01, dseed=1e-4, max_shots=8,
+                     absent_logit=-2.0):
+    return rt_surrogate_params(z0, dn, verify_tol, dseed, max_shots, absent_logit)
+
+
+def raytrace_solve_seeded(field, boundaries, tol, limits, pairs, seed, seed_try, sp, outputs,
+                          verify, workspace, workspace_bytes, stream, tuning=None) -> int:
+    return int(lib().raytrace_solve_seeded(
+        C.byref(field), C.byref(boundaries), float(tol), C.byref(limits), C.byref(pairs),
+        C.c_void_p(seed), C.c_void_p(seed_try), C.byref(sp), C.byref(outputs),
+        C.c_void_p(verify), C.c_void_p(workspace), C.c_size_t(workspace_bytes),
+        C.c_void_p(stream), C.byref(tuning) if tuning is not None else None))
+
+
+def rt_surrogate_features(pairs, z0, dn, x, stream) -> int:
+    return int(lib().rt_surrogate_features(C.byref(pairs), float(z0), float(dn), C.c_void_p(x),
+                                           C.c_void_p(stream)))
+
+
+def rt_surrogate_targets(solved, n, targets, mask, stream) -> int:
+    return int(lib().rt_surrogate_targets(C.byref(solved), C.c_int64(n), C.c_void_p(targets),
+                                          C.c_void_p(mask), C.c_void_p(stream)))
+
+
+def rt_surrogate_workspace_bytes(field, n_pairs, fallback) -> int:
+    n = C.c_size_t(0)
+    st = lib().rt_surrogate_workspace_bytes(C.byref(field), C.c_int64(n_pairs), C.byref(fallback),
+                                            C.byref(n))
+    if st != RT_OK:
+        raise RTError(st, rt_last_error())
+    return int(n.value)
+
+
+def raytrace_solve_surrogate(field, boundaries, tol, limits, pairs, fallback, sp, mlp_params,
+                             outputs, path, fallback_pairs, workspace, workspace_bytes, stream,
+                             tuning=None) -> int:
+    return int(lib().raytrace_solve_surrogate(
+        C.byref(field), C.byref(boundaries), float(tol), C.byref(limits), C.byref(pairs),
+        C.byref(fallback), C.byref(sp), C.c_void_p(mlp_params), C.byref(outputs),
+        C.c_void_p(path), C.c_void_p(fallback_pairs), C.c_void_p(workspace),
+        C.c_size_t(workspace_bytes), C.c_void_p(stream),
+        C.byref(tuning) if tuning is not None else None))
+
+
+def solve_seeded(scene: W.Scene, zs, zr, dist, seed, seed_try, sp=None, tuning=None):
+    """Seeded secant on the GPU (seed, seed_try shaped [n, 2]); returns
+    (results shaped (n, 2) incl. 'verify', stats)."""
+    import torch
+    ds = DeviceSolve(scene, zs, zr, dist)
+    n = ds.n
+    sd = torch.as_tensor(np.ascontiguousarray(np.asarray(seed, np.float64).reshape(2 * n)),
+                         device=ds.device)
+    tr = torch.as_tensor(np.ascontiguousarray(np.asarray(seed_try, np.int32).reshape(2 * n)),
+                         device=ds.device)
+    verify = torch.full((max(1, 2 * n),), -1, dtype=torch.int32, device=ds.device)
+    ws = torch.empty(4096, dtype=torch.uint8, device=ds.device)
+    sp = sp if sp is not None else surrogate_params()
+    st = raytrace_solve_seeded(ds.desc.field, ds.desc.bnd, ds.desc.tol, ds.desc.limits, ds.pairs,
+                               sd.data_ptr(), tr.data_ptr(), sp, ds.out, verify.data_ptr(),
+                               ws.data_ptr(), 4096, torch.cuda.current_stream().cuda_stream,
+                               tuning)
+    if st != RT_OK:
+        raise RTError(st, rt_last_error())
+    res, stats = ds.collect()
+    res["verify"] = verify[:2 * n].cpu().numpy().reshape(n, 2)
+    return res, stats
+
+
+class DeviceSurrogateSolve:
+    """Device-resident pairs, outputs and workspace for raytrace_solve_surrogate."""
+
+    def __init__(self, scene: W.Scene, zs, zr, dist, sp, fallback=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.base = DeviceSolve(scene, zs, zr, dist, fallback, device=device)
+        self.sp = sp
+        dev = self.base.device
+        n = self.base.n
+        self.path = torch.zeros(max(1, 2 * n), dtype=torch.int32, device=dev)
+        self.fallback_pairs = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.ws_bytes = rt_surrogate_workspace_bytes(self.base.desc.field, n, self.base.params)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+
+    def launch(self, mlp_params, stream=None, tuning=None):
+        b = self.base
+        if stream is None:
+            stream = self.torch.cuda.current_stream(b.device)
+        st = raytrace_solve_surrogate(b.desc.field, b.desc.bnd, b.desc.tol, b.desc.limits,
+                                      b.pairs, b.params, self.sp, mlp_params.data_ptr(), b.out,
+                                      self.path.data_ptr(), self.fallback_pairs.data_ptr(),
+                                      self.workspace.data_ptr(), self.ws_bytes,
+                                      stream.cuda_stream, tuning)
+        if st != RT_OK:
+            raise RTError(st, rt_last_error())
+
+    def collect(self):
+        res, stats = self.base.collect()
+        n = self.base.n
+        res["path"] = self.path[:2 * n].cpu().numpy().reshape(n, 2)
+        stats["fallback_pairs"] = int(self.fallback_pairs.cpu().numpy()[0])
+        return res, stats

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libradiotrace.so")
-SOURCES = ["rt_kernels.hip", "rt_solve.hip", "rt_mlp.hip", "rt_host.cpp"]
+SOURCES = ["rt_kernels.hip", "rt_solve.hip", "rt_mlp.hip", "rt_surrogate.hip", "rt_host.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -5,8 +5,10 @@
 #include <cstdio>
 #include <cstring>
 
+#include "radiotrace_mlp.h"
 #include "radiotrace_solve.h"
 #include "rt_params.hpp"
+#include "rt_solve_internal.hpp"
 
 namespace rt {
 
@@ -102,6 +104,17 @@ rt_status validate(const rt_field* field, const rt_boundaries* bnd, const rt_sou
   if (L->model != RT_MODEL_PAPER && L->model != RT_MODEL_EXACT)
     FAIL(RT_ERR_INVALID_ARG, "unknown model %d", L->model);
   if (L->max_steps_per_ray < 1) FAIL(RT_ERR_INVALID_ARG, "max_steps_per_ray must be >= 1");
+  return RT_OK;
+}
+
+rt_status check_surrogate_params(const rt_surrogate_params* sp) {
+  if (!sp) FAIL(RT_ERR_INVALID_ARG, "null surrogate params");
+  if (!(sp->verify_tol > 0.0) || !std::isfinite(sp->verify_tol))
+    FAIL(RT_ERR_INVALID_ARG, "verify_tol must be > 0");
+  if (!(sp->dseed > 0.0) || !(sp->dseed < 0.5)) FAIL(RT_ERR_INVALID_ARG, "need 0 < dseed < 0.5");
+  if (sp->max_shots < 2 || sp->max_shots > 64) FAIL(RT_ERR_INVALID_ARG, "max_shots must be 2..64");
+  if (!std::isfinite(sp->z0) || !std::isfinite(sp->dn) || std::isnan(sp->absent_logit))
+    FAIL(RT_ERR_INVALID_ARG, "non-finite profile features or logit threshold");
   return RT_OK;
 }
 

@@ -26,7 +26,9 @@
 #include <cstring>
 
 #include "radiotrace_solve.h"
+#include "radiotrace_mlp.h"
 #include "rt_device.hpp"
+#include "rt_solve_internal.hpp"
 
 namespace rt {
 
@@ -50,7 +52,7 @@ enum : int {
 };
 static_assert(sizeof(rt_solve_stats) == 8 * V_COUNT, "rt_solve_stats layout");
 
-enum : int { PH_LIST = 0, PH_SCAN = 1, PH_REFINE = 2 };
+enum : int { PH_LIST = 0, PH_SCAN = 1, PH_REFINE = 2, PH_SEEDED = 3 };
 
 struct KSolve {
   const double *zs, *zr, *dist;  // per pair (scan, refine, select) or per shot (list)
@@ -68,6 +70,16 @@ struct KSolve {
   rt_shot_outputs lo;
   rt_solve_outputs so;
   unsigned long long* stats;
+  // pair count read on the device (a compacted list whose length is known
+  // only there); NULL = n
+  const int64_t* n_dev;
+  // seeded phase: per entry [2 n] the first angle and whether to try it;
+  // verify[2 n] receives 1 (verified solution) or 0 (not verified)
+  const double* seed;
+  const int32_t* seed_try;
+  int32_t* verify;
+  double verify_tol, dseed;
+  int32_t max_shots;
 };
 
 // A pair can be shot if its values are finite, the distance is positive and
@@ -250,12 +262,22 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
   __shared__ double s_amp[4][256];
   // refinement state of each lane: bracket [ra, rb] with misses, the angle
   // being shot, and (iterations << 2 | last side + 1)
-  __shared__ double s_ra[PHASE == PH_REFINE ? 256 : 1], s_rGa[PHASE == PH_REFINE ? 256 : 1];
-  __shared__ double s_rb[PHASE == PH_REFINE ? 256 : 1], s_rGb[PHASE == PH_REFINE ? 256 : 1];
-  __shared__ double s_rc[PHASE == PH_REFINE ? 256 : 1];
-  __shared__ double s_rma[PHASE == PH_REFINE ? 256 : 1], s_rmb[PHASE == PH_REFINE ? 256 : 1];
-  __shared__ int32_t s_rm[PHASE == PH_REFINE ? 256 : 1];
+  // (the seeded phase keeps its previous angle and miss in s_ra, s_rGa and
+  // the shots taken in s_rm)
+  constexpr int kR = (PHASE == PH_REFINE || PHASE == PH_SEEDED) ? 256 : 1;
+  __shared__ double s_ra[kR], s_rGa[kR];
+  __shared__ double s_rb[kR], s_rGb[kR];
+  __shared__ double s_rc[kR];
+  __shared__ double s_rma[kR], s_rmb[kR];
+  __shared__ int32_t s_rm[kR];
   __syncthreads();
+  int64_t n_pairs = V.n, n_tasks = V.n_tasks;
+  if (V.n_dev) {
+    n_pairs = *V.n_dev;
+    n_tasks = PHASE == PH_SCAN     ? 2 * n_pairs * V.n_scan
+              : PHASE == PH_REFINE ? 2 * n_pairs * V.max_brackets
+                                   : 2 * n_pairs;
+  }
 
   Ray R;
   R.slot = -1;  // task index, -1 = idle
@@ -302,6 +324,51 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
       } else if constexpr (PHASE == PH_SCAN) {
         V.scan_miss[t] = fin.miss;
         R.slot = -1;
+      } else if constexpr (PHASE == PH_SEEDED) {
+        // seeded secant: the seed, the seed + dseed, then secant steps; the
+        // entry is solved once a shot meets the receiver plane within
+        // verify_tol
+        const int shots = s_rm[tid] + 1;
+        const double c = s_rc[tid];
+        const bool recv = fin.status == RT_SHOT_RECEIVER;
+        const bool success = recv && fabs(fin.miss) <= V.verify_tol;
+        bool done = success || !recv || shots >= V.max_shots;
+        double cn = 0.0;
+        if (!done) {
+          if (shots == 1) {
+            cn = c + V.dseed < kPi ? c + V.dseed : c - V.dseed;
+          } else {
+            const double cp = s_ra[tid], mp = s_rGa[tid];
+            cn = c - fin.miss * (c - cp) / (fin.miss - mp);
+          }
+          if (!(cn > 0.0 && cn < kPi)) done = true;  // also a non-finite step
+        }
+        if (done) {
+          const rt_solve_outputs& O = V.so;
+          O.found[t] = success ? 1 : 0;
+          O.shots[t] = shots;
+          O.theta[t] = success ? c : 0.0;
+          O.miss[t] = success ? fin.miss : 0.0;
+          O.t[t] = success ? R.y[6] : 0.0;
+          O.s[t] = success ? R.s : 0.0;
+          O.as_re[t] = success ? s_amp[0][tid] : 0.0;
+          O.as_im[t] = success ? s_amp[1][tid] : 0.0;
+          O.ap_re[t] = success ? s_amp[2][tid] : 0.0;
+          O.ap_im[t] = success ? s_amp[3][tid] : 0.0;
+          V.verify[t] = success ? 1 : 0;
+          if (success) C.bump(V_FOUND);
+          R.slot = -1;
+        } else {
+          s_ra[tid] = c;
+          s_rGa[tid] = fin.miss;
+          s_rc[tid] = cn;
+          s_rm[tid] = shots;
+          double a4[4];
+          start_shot<MODEL>(P, R, S, V.zs[S.pair], V.zr[S.pair], cn, a4);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) s_amp[i][tid] = a4[i];
+          mode = 0;
+        }
       } else {
         int meta = s_rm[tid];
         int last = (meta & 3) - 1;
@@ -369,9 +436,9 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
           base = __hip_atomic_fetch_add(&V.tickets[PHASE], (uint64_t)nidle, __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
         base = __shfl(base, 0);
-        if (base + nidle >= (uint64_t)V.n_tasks) exhausted = true;
+        if (base + nidle >= (uint64_t)n_tasks) exhausted = true;
         const uint64_t task = base + (uint64_t)__popcll(idle & lanemask_lt());
-        if (lane_idle && task < (uint64_t)V.n_tasks) {
+        if (lane_idle && task < (uint64_t)n_tasks) {
           const int64_t t = (int64_t)task;
           double zs = 0.0, zr = 0.0, theta = 0.0;
           bool go = false;
@@ -403,8 +470,29 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
             theta = ((double)k + 0.5) * V.dtheta;
             go = pair_ok(P, zs, zr, S.D);
             if (!go) V.scan_miss[t] = 0.0;  // no sign change: no bracket
+          } else if constexpr (PHASE == PH_SEEDED) {
+            S.pair = (int32_t)(t >> 1);
+            S.fam = (int32_t)(t & 1);
+            S.D = V.dist[S.pair];
+            zs = V.zs[S.pair];
+            zr = V.zr[S.pair];
+            if (V.seed_try[t]) {
+              theta = V.seed[t];
+              go = pair_ok(P, zs, zr, S.D) && theta > 0.0 && theta < kPi;
+              if (go) {
+                s_rc[tid] = theta;
+                s_rm[tid] = 0;
+              } else {
+                const rt_solve_outputs& O = V.so;
+                O.found[t] = 0;
+                O.shots[t] = 0;
+                O.theta[t] = O.miss[t] = O.t[t] = O.s[t] = 0.0;
+                O.as_re[t] = O.as_im[t] = O.ap_re[t] = O.ap_im[t] = 0.0;
+                V.verify[t] = 0;
+              }
+            }
           } else {
-            const int64_t n2 = 2 * V.n;
+            const int64_t n2 = 2 * n_pairs;
             const int b = (int)(t / n2);
             const int64_t pf = t - (int64_t)b * n2;
             S.pair = (int32_t)(pf >> 1);
@@ -620,17 +708,18 @@ shot_kernel(KParams P, KSolve V) {
 __global__ void solve_reset_kernel(KSolve V) {
   const int i = threadIdx.x;
   if (i < V_COUNT) V.stats[i] = 0;
-  if (i < 3) V.tickets[i] = 0;
+  if (i < 4) V.tickets[i] = 0;
 }
 
 // The admissible refined root with the smallest travel time, per (pair,
 // family).
 __global__ void select_kernel(KParams P, KSolve V) {
   const int64_t pf = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (pf >= 2 * V.n) return;
+  const int64_t n = V.n_dev ? *V.n_dev : V.n;
+  if (pf >= 2 * n) return;
   const rt_solve_outputs& O = V.so;
   const int32_t pair = (int32_t)(pf >> 1);
-  const int64_t n2 = 2 * V.n;
+  const int64_t n2 = 2 * n;
   int best = -1, nb = 0, last_k = -1, refine_shots = 0;
   double best_t = 0.0;
   const bool ok = pair_ok(P, V.zs[pair], V.zr[pair], V.dist[pair]);
@@ -783,6 +872,23 @@ rt_status device_cus(int& n_cu) {
   return RT_OK;
 }
 
+rt_status check_pairs_outputs(const rt_pairs* pairs, const rt_solve_outputs* out) {
+  if (pairs->n < 0 || pairs->n > ((int64_t)1 << 28)) {
+    set_last_error("pair count must be 0..2^28");
+    return RT_ERR_INVALID_ARG;
+  }
+  if (pairs->n > 0 && (!pairs->zs || !pairs->zr || !pairs->dist)) {
+    set_last_error("null pair array");
+    return RT_ERR_INVALID_ARG;
+  }
+  if (pairs->n > 0 && (!out->found || !out->shots || !out->theta || !out->miss || !out->t ||
+                       !out->s || !out->as_re || !out->as_im || !out->ap_re || !out->ap_im)) {
+    set_last_error("null output array");
+    return RT_ERR_INVALID_ARG;
+  }
+  return RT_OK;
+}
+
 rt_status tuning_of(const rt_tuning* tuning, int& block, int& refill) {
   block = tuning && tuning->block_size ? tuning->block_size : 256;
   if (block < 64 || block > 256 || block % 64) {
@@ -809,51 +915,30 @@ rt_status tuning_of(const rt_tuning* tuning, int& block, int& refill) {
     }                                                                         \
   } while (0)
 
-extern "C" rt_status raytrace_solve(const rt_field* field, const rt_boundaries* bnd, double tol,
-                                    const rt_step_limits* L, const rt_pairs* pairs,
-                                    const rt_solve_params* prm, rt_solve_outputs* out,
-                                    void* workspace, size_t workspace_bytes, void* stream,
-                                    const rt_tuning* tuning) {
-  using namespace rt;
-  rt_status st = rt_solve_validate(field, bnd, tol, L, prm);
-  if (st != RT_OK) return st;
-  if (!prm || !pairs || !out || !out->stats || !workspace) {
-    set_last_error("null params, pairs, outputs, stats or workspace");
-    return RT_ERR_INVALID_ARG;
-  }
-  if (pairs->n < 0 || pairs->n > ((int64_t)1 << 28)) {
-    set_last_error("pair count must be 0..2^28");
-    return RT_ERR_INVALID_ARG;
-  }
-  if (pairs->n > 0 && (!pairs->zs || !pairs->zr || !pairs->dist)) {
-    set_last_error("null pair array");
-    return RT_ERR_INVALID_ARG;
-  }
-  if (pairs->n > 0 && (!out->found || !out->shots || !out->theta || !out->miss || !out->t ||
-                       !out->s || !out->as_re || !out->as_im || !out->ap_re || !out->ap_im)) {
-    set_last_error("null output array");
-    return RT_ERR_INVALID_ARG;
-  }
-  size_t need = 0;
-  st = rt_solve_workspace_bytes(field, pairs->n, prm, &need);
-  if (st != RT_OK) return st;
-  if (workspace_bytes < need) {
-    set_last_error("workspace of %zu bytes < %zu needed", workspace_bytes, need);
-    return RT_ERR_INVALID_ARG;
-  }
+namespace rt {
+
+// Enqueue a solve of up to n_cap pairs (the number read on the device from
+// *n_dev when n_dev is not NULL); arguments already validated.
+rt_status solve_enqueue(const rt_field* field, const rt_boundaries* bnd, double tol,
+                        const rt_step_limits* L, const rt_pairs* pairs, int64_t n_cap,
+                        const int64_t* n_dev, const rt_solve_params* prm,
+                        const rt_solve_outputs* out, void* workspace, void* stream,
+                        const rt_tuning* tuning) {
+  rt_status st;
   int block = 0, refill = 0, n_cu = 0;
   if ((st = tuning_of(tuning, block, refill)) != RT_OK) return st;
   KParams P;
   if ((st = pack_params(field, bnd, tol, L, P)) != RT_OK) return st;
   if ((st = device_cus(n_cu)) != RT_OK) return st;
 
-  const int64_t n = pairs->n, K = prm->n_scan, B = prm->max_brackets;
+  const int64_t n = n_cap, K = prm->n_scan, B = prm->max_brackets;
   KSolve V;
   memset(&V, 0, sizeof V);
   V.zs = pairs->zs;
   V.zr = pairs->zr;
   V.dist = pairs->dist;
   V.n = n;
+  V.n_dev = n_dev;
   V.n_scan = prm->n_scan;
   V.max_iter = prm->max_iter;
   V.max_brackets = prm->max_brackets;
@@ -898,6 +983,99 @@ extern "C" rt_status raytrace_solve(const rt_field* field, const rt_boundaries* 
                      V);
   HIP_TRY(hipGetLastError());
   return RT_OK;
+}
+
+// Enqueue the seeded secant of every entry [2 n] with seed_try set; results
+// into out (found = verified), verify[2 n] = 1 / 0 for the tried entries.
+// The workspace needs 4 KiB.
+rt_status seeded_enqueue(const rt_field* field, const rt_boundaries* bnd, double tol,
+                         const rt_step_limits* L, const rt_pairs* pairs, const double* seed,
+                         const int32_t* seed_try, const rt_surrogate_params* sp,
+                         const rt_solve_outputs* out, int32_t* verify, void* workspace,
+                         void* stream, const rt_tuning* tuning) {
+  rt_status st;
+  int block = 0, refill = 0, n_cu = 0;
+  if ((st = tuning_of(tuning, block, refill)) != RT_OK) return st;
+  KParams P;
+  if ((st = pack_params(field, bnd, tol, L, P)) != RT_OK) return st;
+  if ((st = device_cus(n_cu)) != RT_OK) return st;
+  KSolve V;
+  memset(&V, 0, sizeof V);
+  V.zs = pairs->zs;
+  V.zr = pairs->zr;
+  V.dist = pairs->dist;
+  V.n = pairs->n;
+  V.n_tasks = 2 * pairs->n;
+  V.refill = refill;
+  V.tickets = static_cast<uint64_t*>(workspace);
+  V.stats = reinterpret_cast<unsigned long long*>(out->stats);
+  V.so = *out;
+  V.seed = seed;
+  V.seed_try = seed_try;
+  V.verify = verify;
+  V.verify_tol = sp->verify_tol;
+  V.dseed = sp->dseed;
+  V.max_shots = sp->max_shots;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(solve_reset_kernel, dim3(1), dim3(64), 0, s, V);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_shots<PH_SEEDED>(P, V, n_cu, block, s));
+  return RT_OK;
+}
+
+}  // namespace rt
+
+extern "C" rt_status raytrace_solve(const rt_field* field, const rt_boundaries* bnd, double tol,
+                                    const rt_step_limits* L, const rt_pairs* pairs,
+                                    const rt_solve_params* prm, rt_solve_outputs* out,
+                                    void* workspace, size_t workspace_bytes, void* stream,
+                                    const rt_tuning* tuning) {
+  using namespace rt;
+  rt_status st = rt_solve_validate(field, bnd, tol, L, prm);
+  if (st != RT_OK) return st;
+  if (!prm || !pairs || !out || !out->stats || !workspace) {
+    set_last_error("null params, pairs, outputs, stats or workspace");
+    return RT_ERR_INVALID_ARG;
+  }
+  if ((st = check_pairs_outputs(pairs, out)) != RT_OK) return st;
+  size_t need = 0;
+  st = rt_solve_workspace_bytes(field, pairs->n, prm, &need);
+  if (st != RT_OK) return st;
+  if (workspace_bytes < need) {
+    set_last_error("workspace of %zu bytes < %zu needed", workspace_bytes, need);
+    return RT_ERR_INVALID_ARG;
+  }
+  return solve_enqueue(field, bnd, tol, L, pairs, pairs->n, nullptr, prm, out, workspace,
+                       stream, tuning);
+}
+
+extern "C" rt_status raytrace_solve_seeded(const rt_field* field, const rt_boundaries* bnd,
+                                           double tol, const rt_step_limits* L,
+                                           const rt_pairs* pairs, const double* seed,
+                                           const int32_t* seed_try,
+                                           const rt_surrogate_params* sp, rt_solve_outputs* out,
+                                           int32_t* verify, void* workspace,
+                                           size_t workspace_bytes, void* stream,
+                                           const rt_tuning* tuning) {
+  using namespace rt;
+  rt_status st = rt_solve_validate(field, bnd, tol, L, nullptr);
+  if (st != RT_OK) return st;
+  if (!pairs || !out || !out->stats || !workspace || !sp) {
+    set_last_error("null pairs, params, outputs, stats or workspace");
+    return RT_ERR_INVALID_ARG;
+  }
+  if ((st = check_pairs_outputs(pairs, out)) != RT_OK) return st;
+  if ((st = check_surrogate_params(sp)) != RT_OK) return st;
+  if (pairs->n > 0 && (!seed || !seed_try || !verify)) {
+    set_last_error("null seed, seed_try or verify array");
+    return RT_ERR_INVALID_ARG;
+  }
+  if (workspace_bytes < 4096) {
+    set_last_error("workspace of %zu bytes < 4096 needed", workspace_bytes);
+    return RT_ERR_INVALID_ARG;
+  }
+  return seeded_enqueue(field, bnd, tol, L, pairs, seed, seed_try, sp, out, verify, workspace,
+                        stream, tuning);
 }
 
 extern "C" rt_status raytrace_shoot(const rt_field* field, const rt_boundaries* bnd, double tol,

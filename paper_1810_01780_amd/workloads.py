@@ -318,3 +318,38 @@ def mlp_init_params(seed: int = 0) -> np.ndarray:
         parts.append((rng.standard_normal(n_in * n_out) * np.sqrt(2.0 / n_in)).astype(np.float32))
         parts.append(np.zeros(n_out, np.float32))
     return np.concatenate(parts)
+
+
+def two_layer_medium(z0: float = FIRN["z0"], dn: float = FIRN["dn"], model: int = MODEL_PAPER,
+                     tol: float = 1e-6) -> Scene:
+    """The two-layer firn medium of the solve workloads with the firn
+    profile a - dn exp(-z/z0) (a = 1.78) scaled by (z0, dn): firn down to the
+    150 m plane, the same profile + 0.01 below, Fresnel surface and layer."""
+    regions = [air_region(),
+               Region(a=FIRN["a"], dn=dn, z0=z0, z_top=0.0, z_bot=150.0),
+               Region(a=FIRN["a"] + 0.01, dn=dn, z0=z0, z_top=150.0, z_bot=np.inf)]
+    planes = [surface_plane(ice=1, air=0),
+              Plane(point=(0.0, 0.0, 150.0), normal=(0.0, 0.0, 1.0),
+                    region_pos=2, region_neg=1)]
+    return Scene(name="twolayer-medium", regions=regions, planes=planes,
+                 sources=np.zeros((1, 3)), ray_src=np.zeros(1, np.int32),
+                 dirs=np.array([[1.0, 0.0, 0.0]]),
+                 limits=Limits(tol=tol, h_min=1e-3, h_max=10.0, s_max=5000.0,
+                               max_generations=1, model=model))
+
+
+def surrogate_training_set(n_profiles: int, pairs_per_profile: int, seed: int = 0):
+    """Seeded training pairs for the solve surrogate: per profile, the scale
+    depth z0 ~ U(40, 120) m and the contrast dn ~ U(0.35, 0.5), then pairs
+    as in solve_pairs (source 50-2000 m, receiver 0-200 m, distance
+    10 m - 3 km).  Returns a list of (z0, dn, zs, zr, dist)."""
+    rng = np.random.default_rng(np.random.SeedSequence([MASTER_SEED, 5, seed]))
+    out = []
+    for _ in range(n_profiles):
+        z0 = rng.uniform(40.0, 120.0)
+        dn = rng.uniform(0.35, 0.5)
+        zs = rng.uniform(50.0, 2000.0, pairs_per_profile)
+        zr = rng.uniform(0.0, 200.0, pairs_per_profile)
+        dist = rng.uniform(10.0, 3000.0, pairs_per_profile)
+        out.append((z0, dn, zs, zr, dist))
+    return out

@@ -1,0 +1,136 @@
+"""GPU tests of the surrogate-seeded solves.
+
+* The seeded secant on the GPU against the oracle's seeded secant from the
+  same seeds (shots are single traces: same bars as any shot).
+* End to end: the network trained on the GPU from the tracer's solves, then
+  raytrace_solve_surrogate on pairs of the two-layer workload, judged by the
+  tracer and the oracle: every entry the surrogate path reports is a
+  verified solution (|miss| <= verify_tol, confirmed by an oracle shot at its
+  angle), fallback entries equal the tracer's own solve bit for bit,
+  entries declared absent are rarely solvable, first-arrival times agree
+  with the tracer's within 0.1 ns, and the surrogate path is faster than the
+  tracer alone on the same GPU.
+"""
+import math
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_1810_01780_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+C0 = 299792458.0
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_01780_amd import binding
+    binding.lib()
+    return binding
+
+
+def _announce(name):
+    print(f"\n[gpu-case] {name}", flush=True)
+    sys.stdout.flush()
+
+
+def test_seeded_matches_oracle(gpu, oracle_lib):
+    sp_ = W.solve_pairs(128)
+    _announce("seeded-vs-oracle: 128 pairs")
+    o = oracle_lib.solve(sp_.scene, sp_.zs, sp_.zr, sp_.dist)
+    rng = np.random.default_rng(3)
+    seed = np.where(o["found"] == 1, o["theta"] + rng.normal(0, 2e-3, o["theta"].shape),
+                    rng.uniform(0.1, math.pi - 0.1, o["theta"].shape))
+    tr = np.ones_like(o["found"])
+    sp = gpu.surrogate_params(verify_tol=0.01, dseed=1e-4, max_shots=6, absent_logit=-2.0)
+    g, gst = gpu.solve_seeded(sp_.scene, sp_.zs, sp_.zr, sp_.dist, seed, tr, sp)
+    r = oracle_lib.solve_seeded(sp_.scene, sp_.zs, sp_.zr, sp_.dist, seed, tr,
+                                verify_tol=0.01, dseed=1e-4, max_shots=6)
+    same = (g["verify"] == r["verify"]) & (g["shots"] == r["shots"])
+    both = (g["verify"] == 1) & (r["verify"] == 1)
+    print(f"[gpu-case] seeded: verified gpu {int((g['verify'] == 1).sum())} oracle "
+          f"{int((r['verify'] == 1).sum())}, same decisions {same.mean():.4f}", flush=True)
+    assert same.mean() >= 0.99
+    assert np.all(np.abs(g["theta"][both] - r["theta"][both]) <= 1e-9)
+    assert np.all(np.abs(g["t"][both] - r["t"][both]) <= 1e-9 * r["t"][both])
+    assert np.all(np.abs(g["miss"][g["verify"] == 1]) <= 0.01)
+    # the seeds are within a few mrad of the roots: most verify in <= 4 shots
+    assert (g["verify"] == 1).sum() >= 0.9 * (o["found"] == 1).sum()
+
+
+@pytest.fixture(scope="module")
+def trained(gpu):
+    from paper_1810_01780_amd import surrogate
+    _announce("surrogate training: 64 profiles x 8192 pairs, 3000 steps")
+    log = lambda m: print(f"[gpu-case] {m}", flush=True)
+    net, losses = surrogate.default_model(seed=0, n_profiles=64, pairs_per_profile=8192,
+                                          steps=3000, log=log)
+    assert losses[-1][1] < 0.2 * losses[0][1]
+    return net
+
+
+def test_surrogate_solve_end_to_end(gpu, oracle_lib, trained):
+    import torch
+    n = 65536
+    sp_ = W.solve_pairs(n)
+    _announce(f"surrogate-solve: {n} pairs")
+    sp = gpu.surrogate_params(z0=75.0, dn=0.43, verify_tol=0.01, max_shots=8, absent_logit=-2.0)
+    # tracer alone
+    ref = gpu.DeviceSolve(sp_.scene, sp_.zs, sp_.zr, sp_.dist)
+    ref.launch()
+    rres, rst = ref.collect()
+    # surrogate path
+    ds = gpu.DeviceSurrogateSolve(sp_.scene, sp_.zs, sp_.zr, sp_.dist, sp)
+    ds.launch(trained.params)
+    res, st = ds.collect()
+    path = res["path"]
+    sur, fb, ab = path == gpu.RT_PATH_SURROGATE, path == gpu.RT_PATH_TRACER, path == \
+        gpu.RT_PATH_ABSENT
+    # surrogate entries: verified solutions
+    ok = sur & (res["found"] == 1)
+    assert np.array_equal(ok, sur), "an entry on the surrogate path is not a solution"
+    assert np.all(np.abs(res["miss"][sur]) <= 0.01)
+    idx = np.argwhere(sur)
+    pick = idx[np.random.default_rng(0).choice(len(idx), min(512, len(idx)), replace=False)]
+    rs = oracle_lib.shoot(sp_.scene, sp_.zs[pick[:, 0]], sp_.zr[pick[:, 0]],
+                          sp_.dist[pick[:, 0]], res["theta"][pick[:, 0], pick[:, 1]],
+                          pick[:, 1].astype(np.int32))
+    assert np.all(rs["status"] == 0) and np.all(np.abs(rs["miss"]) <= 0.01 + 1e-9)
+    # fallback entries: the tracer's own results
+    for f in ("found", "theta", "t", "s", "miss", "as_re", "shots"):
+        assert np.array_equal(res[f][fb], rres[f][fb]), f
+    # absent entries: rarely solvable
+    false_absent = int((ab & (rres["found"] == 1)).sum())
+    # first arrivals: travel time within 0.1 ns of the tracer's
+    both = sur & (rres["found"] == 1)
+    dt = np.abs(res["t"][both] - rres["t"][both])
+    late = int((dt > 0.1e-9).sum())
+    summ = dict(entries=2 * n, surrogate=int(sur.sum()), fallback_pairs=st["fallback_pairs"],
+                absent=int(ab.sum()), false_absent=false_absent, tracer_found=int(rres["found"].sum()),
+                surrogate_found=int(res["found"].sum()), other_arrival=late,
+                shots=st["shots"], tracer_shots=rst["shots"])
+    print(f"[gpu-case] surrogate-solve: {summ}", flush=True)
+    assert false_absent <= 0.001 * 2 * n
+    assert late <= 0.01 * both.sum()
+    assert res["found"].sum() >= 0.98 * rres["found"].sum()
+    # speed on the same GPU: best of 3 each
+    def timed(fn):
+        best = 1e9
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+    t_tr = timed(lambda: ref.launch())
+    t_su = timed(lambda: ds.launch(trained.params))
+    print(f"[gpu-case] surrogate-solve: tracer {t_tr * 1e3:.2f} ms, surrogate "
+          f"{t_su * 1e3:.2f} ms, gain {t_tr / t_su:.2f}x", flush=True)
+    assert t_su < t_tr / 1.5

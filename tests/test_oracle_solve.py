@@ -210,3 +210,27 @@ def test_slope_bound_only_drops_jumps(oracle_lib):
         assert np.array_equal(on[k][f], off[k][f]), k
     # both take the same scan shots; the refinement shots drop
     assert (on["shots"] - 64).sum() < 0.5 * (off["shots"] - 64).sum()
+
+
+def test_seeded_secant(oracle_lib):
+    """Seeded secant: from a seed near the straight-line angle it verifies
+    within verify_tol and lands on that angle; a seed whose shot touches the
+    surface (direct family) fails at once; untried entries stay -1."""
+    n = 1.5
+    sc = two_media(W.Region(a=n, z_top=0.0))
+    zs = np.array([300.0, 900.0, 300.0])
+    zr = np.array([50.0, 120.0, 50.0])
+    D = np.array([400.0, 2500.0, 400.0])
+    th = np.arctan2(D, zs - zr)
+    seed = np.stack([th + np.array([3e-3, -5e-3, 0.0]), np.full(3, 1.0)], axis=1)
+    seed[2, 0] = 0.05  # steep upward: reaches the surface first
+    tr = np.array([[1, 0], [1, 0], [1, 0]])
+    r = oracle_lib.solve_seeded(sc, zs, zr, D, seed, tr, verify_tol=1e-3, max_shots=6)
+    assert r["verify"].tolist() == [[1, -1], [1, -1], [0, -1]]
+    assert np.all(r["shots"][:2, 0] <= 5) and r["shots"][2, 0] == 1
+    L = np.hypot(D, zs - zr)
+    for i in range(2):
+        assert abs(r["miss"][i, 0]) <= 1e-3
+        # the miss of a straight line is D cot(theta) - (zs - zr) shifted: angle error ~ miss / L
+        assert r["theta"][i, 0] == pytest.approx(th[i], abs=2e-3 / L[i])
+        assert r["t"][i, 0] * C0 == pytest.approx(n * L[i], abs=n * 2e-3)
