@@ -44,7 +44,7 @@ class Region(C.Structure):
 class Plane(C.Structure):
     _fields_ = [("point", C.c_double * 3), ("normal", C.c_double * 3),
                 ("region_pos", C.c_int32), ("region_neg", C.c_int32),
-                ("kind", C.c_int32)]
+                ("kind", C.c_int32), ("shape", C.c_int32), ("param", C.c_double)]
 
 
 class Problem(C.Structure):
@@ -128,7 +128,7 @@ class _Prepared:
         pls = (Plane * max(1, len(scene.planes)))()
         for i, p in enumerate(scene.planes):
             pls[i] = Plane((C.c_double * 3)(*p.point), (C.c_double * 3)(*p.normal),
-                           p.region_pos, p.region_neg, p.kind)
+                           p.region_pos, p.region_neg, p.kind, p.shape, p.param)
         src = np.ascontiguousarray(scene.sources, dtype=np.float64)
         dirs = np.ascontiguousarray(scene.dirs, dtype=np.float64)
         rsrc = np.ascontiguousarray(scene.ray_src, dtype=np.int32)

@@ -37,10 +37,18 @@ typedef struct {
   int32_t use_grid;
 } orc_region;
 
+/* Boundary surfaces (shape): plane through point with normal; sphere with
+ * centre point and radius param (g = |r - c| - R, region_pos outside);
+ * paraboloid z = z_v + param ((x - x_v)^2 + (y - y_v)^2) with vertex point
+ * (g = z - z_v - param rho^2, region_pos below, i.e. at larger depth). */
+enum { ORC_SHAPE_PLANE = 0, ORC_SHAPE_SPHERE = 1, ORC_SHAPE_PARABOLOID = 2 };
+
 typedef struct {
   double point[3], normal[3];      /* normal need not be unit length */
   int32_t region_pos, region_neg;  /* region on the +normal / -normal side */
   int32_t kind;
+  int32_t shape;
+  double param;
 } orc_plane;
 
 typedef struct {

@@ -81,8 +81,9 @@ typedef struct {
 enum { KIND_FRESNEL = 0, KIND_ABSORB = 1, KIND_BOX = 2, KIND_TIME = 3 };
 
 typedef struct {
-  double nrm[3], d;
-  int32_t kind, reg_pos, reg_neg;
+  double nrm[3], d;     /* plane: unit normal and offset */
+  double pt[3], param;  /* sphere: centre, radius; paraboloid: vertex, curvature */
+  int32_t kind, reg_pos, reg_neg, shape;
 } bplane_t;
 
 typedef struct {
@@ -99,9 +100,14 @@ static void build_scene(const orc_problem* P, scene_t* S) {
     double len = sqrt(q->normal[0] * q->normal[0] + q->normal[1] * q->normal[1] +
                       q->normal[2] * q->normal[2]);
     bplane_t* b = &S->pl[m++];
-    for (int i = 0; i < 3; ++i) b->nrm[i] = q->normal[i] / len;
-    b->d = q->point[0] * b->nrm[0] + q->point[1] * b->nrm[1] +
-           q->point[2] * b->nrm[2];
+    memset(b, 0, sizeof *b);
+    b->shape = q->shape;
+    for (int i = 0; i < 3; ++i) b->pt[i] = q->point[i];
+    b->param = q->param;
+    if (q->shape == ORC_SHAPE_PLANE) {
+      for (int i = 0; i < 3; ++i) b->nrm[i] = q->normal[i] / len;
+      b->d = q->point[0] * b->nrm[0] + q->point[1] * b->nrm[1] + q->point[2] * b->nrm[2];
+    }
     b->kind = q->kind == ORC_PLANE_ABSORB ? KIND_ABSORB : KIND_FRESNEL;
     b->reg_pos = q->region_pos;
     b->reg_neg = q->region_neg;
@@ -131,7 +137,52 @@ static void build_scene(const orc_problem* P, scene_t* S) {
 static double bnd_g(const scene_t* S, int k, const double y[7]) {
   const bplane_t* b = &S->pl[k];
   if (b->kind == KIND_TIME) return (S->P->t_max - y[6]) * C0;
+  if (b->shape == ORC_SHAPE_SPHERE) {
+    const double dx = y[0] - b->pt[0], dy = y[1] - b->pt[1], dz = y[2] - b->pt[2];
+    return sqrt(dx * dx + dy * dy + dz * dz) - b->param;
+  }
+  if (b->shape == ORC_SHAPE_PARABOLOID) {
+    const double dx = y[0] - b->pt[0], dy = y[1] - b->pt[1];
+    return y[2] - b->pt[2] - b->param * (dx * dx + dy * dy);
+  }
   return y[0] * b->nrm[0] + y[1] * b->nrm[1] + y[2] * b->nrm[2] - b->d;
+}
+
+/* Unit normal of boundary k at y, pointing to the g > 0 side (grad g). */
+static void bnd_normal(const scene_t* S, int k, const double y[7], double n[3]) {
+  const bplane_t* b = &S->pl[k];
+  if (b->shape == ORC_SHAPE_SPHERE) {
+    for (int i = 0; i < 3; ++i) n[i] = y[i] - b->pt[i];
+  } else if (b->shape == ORC_SHAPE_PARABOLOID) {
+    n[0] = -2.0 * b->param * (y[0] - b->pt[0]);
+    n[1] = -2.0 * b->param * (y[1] - b->pt[1]);
+    n[2] = 1.0;
+  } else {
+    for (int i = 0; i < 3; ++i) n[i] = b->nrm[i];
+    return;
+  }
+  const double l = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  for (int i = 0; i < 3; ++i) n[i] /= l;
+}
+
+/* Move a located point onto boundary k: along the normal for a plane,
+ * radially for a sphere, vertically for a paraboloid (whose g is a depth
+ * difference). */
+static void bnd_snap(const scene_t* S, int k, double y[7]) {
+  const bplane_t* b = &S->pl[k];
+  if (b->kind == KIND_TIME) return;
+  if (b->shape == ORC_SHAPE_SPHERE) {
+    const double dx = y[0] - b->pt[0], dy = y[1] - b->pt[1], dz = y[2] - b->pt[2];
+    const double f = b->param / sqrt(dx * dx + dy * dy + dz * dz);
+    y[0] = b->pt[0] + f * dx;
+    y[1] = b->pt[1] + f * dy;
+    y[2] = b->pt[2] + f * dz;
+  } else if (b->shape == ORC_SHAPE_PARABOLOID) {
+    y[2] -= bnd_g(S, k, y);
+  } else {
+    const double g = bnd_g(S, k, y);
+    for (int i = 0; i < 3; ++i) y[i] -= g * b->nrm[i];
+  }
 }
 
 static double side_sign(const ray_t* r, int k) {
@@ -542,11 +593,7 @@ static void trace_tree(worker_t* W, const ray_t* root) {
         }
       }
       const bplane_t* b = &S->pl[k];
-      if (b->kind != KIND_TIME) {
-        /* snap onto the plane */
-        double g = bnd_g(S, k, ystar);
-        for (int i = 0; i < 3; ++i) ystar[i] -= g * b->nrm[i];
-      }
+      bnd_snap(S, k, ystar);
       {
         double u[3];
         unit_direction(ystar, u);
@@ -575,7 +622,9 @@ static void trace_tree(worker_t* W, const ray_t* root) {
       r.n_ev++;
       W->st.events++;
       double sgn = side_sign(&r, k);
-      double nin[3] = {sgn * b->nrm[0], sgn * b->nrm[1], sgn * b->nrm[2]};
+      double nb[3];
+      bnd_normal(S, k, r.y, nb);
+      double nin[3] = {sgn * nb[0], sgn * nb[1], sgn * nb[2]};
       double u[3];
       unit_direction(r.y, u);
       double ci = -(u[0] * nin[0] + u[1] * nin[1] + u[2] * nin[2]);
@@ -859,10 +908,7 @@ static shot_t shoot(worker_t* W, const scene_t* S, double zs, double zr, double 
       }
     }
     const bplane_t* b = &S->pl[k];
-    if (b->kind != KIND_TIME) {
-      double g = bnd_g(S, k, ystar);
-      for (int i = 0; i < 3; ++i) ystar[i] -= g * b->nrm[i];
-    }
+    bnd_snap(S, k, ystar);
     {
       double u[3];
       unit_direction(ystar, u);
@@ -945,6 +991,14 @@ static shot_t shoot(worker_t* W, const scene_t* S, double zs, double zr, double 
   out.n_rej = r.n_rej;
   out.miss = SHOT_MISS_LOW;
   return out;
+}
+
+/* Shots follow planes only (the surface mirror and the receiver plane
+ * assume them). */
+static int planes_only(const orc_problem* P) {
+  for (int k = 0; k < P->n_planes; ++k)
+    if (P->planes[k].shape != ORC_SHAPE_PLANE) return 0;
+  return 1;
 }
 
 static int miss_sign(double m) { return m < 0.0 ? -1 : 1; }
@@ -1124,7 +1178,8 @@ static void* run_shoot(void* arg) {
 int orc_shoot(const orc_problem* P, const double* zs, const double* zr, const double* dist,
               const double* theta, const int32_t* family, int64_t n, orc_shot_out* out,
               int n_threads) {
-  if (P->n_planes < 1 || P->n_planes > 16 || P->has_box || P->t_max > 0.0) return -2;
+  if (P->n_planes < 1 || P->n_planes > 16 || P->has_box || P->t_max > 0.0 || !planes_only(P))
+    return -2;
   scene_t S;
   build_scene(P, &S);
   if (n_threads < 1) n_threads = 1;
@@ -1230,7 +1285,8 @@ int orc_solve_seeded(const orc_problem* P, const double* zs, const double* zr,
                      const double* dist, int64_t n_pairs, const double* seed,
                      const int32_t* try_, const orc_seed_spec* spec, orc_solve_out* out,
                      int32_t* verify, int n_threads) {
-  if (P->n_planes < 1 || P->n_planes > 16 || P->has_box || P->t_max > 0.0) return -2;
+  if (P->n_planes < 1 || P->n_planes > 16 || P->has_box || P->t_max > 0.0 || !planes_only(P))
+    return -2;
   scene_t S;
   build_scene(P, &S);
   if (n_threads < 1) n_threads = 1;
@@ -1263,7 +1319,8 @@ int orc_solve_seeded(const orc_problem* P, const double* zs, const double* zr,
 
 int orc_solve(const orc_problem* P, const orc_solve_spec* sp, const int64_t* pairs,
               int64_t n_pairs, orc_solve_out* out, int n_threads) {
-  if (P->n_planes < 1 || P->n_planes > 16 || P->has_box || P->t_max > 0.0) return -2;
+  if (P->n_planes < 1 || P->n_planes > 16 || P->has_box || P->t_max > 0.0 || !planes_only(P))
+    return -2;
   scene_t S;
   build_scene(P, &S);
   if (n_threads < 1) n_threads = 1;

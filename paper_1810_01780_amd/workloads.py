@@ -35,6 +35,7 @@ MODEL_EXACT = 1   # full eikonal (paper §2, eq. 1)
 # plane kinds
 PLANE_FRESNEL = 0  # reflect + refracted secondary, Fresnel amplitudes
 PLANE_ABSORB = 1   # terminate the ray on contact
+SHAPE_PLANE, SHAPE_SPHERE, SHAPE_PARABOLOID = 0, 1, 2  # boundary surface shapes
 
 
 @dataclasses.dataclass
@@ -50,11 +51,16 @@ class Region:
 
 @dataclasses.dataclass
 class Plane:
+    """A boundary surface: a plane (point, normal), a sphere (centre = point,
+    radius = param; region_pos outside) or a paraboloid z = z_v + param
+    ((x - x_v)^2 + (y - y_v)^2) with vertex = point (region_pos below)."""
     point: Sequence[float]
     normal: Sequence[float]
     region_pos: int       # region on the side the normal points to
     region_neg: int
     kind: int = PLANE_FRESNEL
+    shape: int = 0        # SHAPE_PLANE, SHAPE_SPHERE, SHAPE_PARABOLOID
+    param: float = 0.0
 
 
 @dataclasses.dataclass
