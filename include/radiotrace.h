@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define RT_ABI_VERSION 1
+#define RT_ABI_VERSION 2
 #define RT_MAX_REGIONS 8
 #define RT_MAX_PLANES 16
 #define RT_MAX_GENERATIONS 4 /* ray keys hold three 8-bit event ordinals */
@@ -57,6 +57,7 @@ typedef enum {
 
 enum { RT_MODEL_PAPER = 0, RT_MODEL_EXACT = 1 };
 enum { RT_PLANE_FRESNEL = 0, RT_PLANE_ABSORB = 1 };
+enum { RT_SHAPE_PLANE = 0, RT_SHAPE_SPHERE = 1, RT_SHAPE_PARABOLOID = 2 };
 
 /* Per-record status (out->status). */
 enum {
@@ -103,15 +104,25 @@ typedef struct {
   rt_grid grid;             /* used when any region has use_grid */
 } rt_field;
 
-/* A planar boundary.  The normal need not be unit length.  region_pos is the
- * medium on the side the normal points to, region_neg the other one; a ray
- * refracted through the plane continues in the other medium.  Stage
- * evaluations of a step always use the ray's own medium, extended smoothly
- * across the plane; the crossing itself is found by the event search. */
+/* A boundary surface (section 2: boundaries are defined explicitly; curved
+ * boundaries are among the supported shapes).  region_pos is the medium on
+ * the side its normal points to, region_neg the other one; a ray refracted
+ * through it continues in the other medium.  Stage evaluations of a step
+ * always use the ray's own medium, extended smoothly across the surface;
+ * the crossing itself is found by the event search, and the reflection and
+ * refraction use the local normal at the crossing.
+ *   RT_SHAPE_PLANE       through point with normal (any length > 0)
+ *   RT_SHAPE_SPHERE      centre point, radius param > 0; region_pos outside
+ *   RT_SHAPE_PARABOLOID  z = point[2] + param ((x - point[0])^2 +
+ *                        (y - point[1])^2), param != 0; region_pos below it
+ *                        (larger depth); normal unused for curved shapes.
+ * A zero-initialised shape/param gives a plane. */
 typedef struct {
   double point[3], normal[3];
   int32_t region_pos, region_neg;
-  int32_t kind; /* RT_PLANE_FRESNEL or RT_PLANE_ABSORB */
+  int32_t kind;  /* RT_PLANE_FRESNEL or RT_PLANE_ABSORB */
+  int32_t shape; /* RT_SHAPE_* */
+  double param;  /* sphere radius or paraboloid curvature (1/m) */
 } rt_plane;
 
 typedef struct {

@@ -27,6 +27,7 @@ RT_ST_QUEUED, RT_ST_EMPTY = -1, 0
 (RT_ST_PATH, RT_ST_BOX, RT_ST_TIME, RT_ST_AMP, RT_ST_ABSORB, RT_ST_STEPCAP,
  RT_ST_NONFINITE, RT_ST_INVALID) = range(1, 9)
 RT_MAX_REGIONS, RT_MAX_PLANES, RT_MAX_GENERATIONS = 8, 16, 4
+RT_SHAPE_PLANE, RT_SHAPE_SPHERE, RT_SHAPE_PARABOLOID = 0, 1, 2
 
 
 class rt_region(C.Structure):
@@ -45,7 +46,8 @@ class rt_field(C.Structure):
 
 class rt_plane(C.Structure):
     _fields_ = [("point", C.c_double * 3), ("normal", C.c_double * 3),
-                ("region_pos", C.c_int32), ("region_neg", C.c_int32), ("kind", C.c_int32)]
+                ("region_pos", C.c_int32), ("region_neg", C.c_int32), ("kind", C.c_int32),
+                ("shape", C.c_int32), ("param", C.c_double)]
 
 
 class rt_boundaries(C.Structure):
@@ -310,7 +312,7 @@ class HostDescriptors:
         pls = (rt_plane * max(1, len(scene.planes)))()
         for i, p in enumerate(scene.planes):
             pls[i] = rt_plane((C.c_double * 3)(*p.point), (C.c_double * 3)(*p.normal),
-                              p.region_pos, p.region_neg, p.kind)
+                              p.region_pos, p.region_neg, p.kind, p.shape, p.param)
         self._keep = [regs, pls]
         self.field = rt_field(len(scene.regions), C.cast(regs, C.POINTER(rt_region)), rt_grid())
         if scene.grid is not None:

@@ -366,11 +366,68 @@ __device__ __forceinline__ double clamp_h(const KParams& P, double h) {
   return fmin(fmax(h, P.h_min), P.h_max);
 }
 
+// Value of a boundary surface's function g at y (positive on its
+// region_pos side): a plane's signed distance, a sphere's distance from its
+// centre minus the radius, a paraboloid's depth difference.
+__device__ __forceinline__ double bnd_value(const KBnd& B, const double* y) {
+  if (B.shape == SH_SPHERE) {
+    const double dx = y[0] - B.nrm[0], dy = y[1] - B.nrm[1], dz = y[2] - B.nrm[2];
+    return sqrt(fma(dx, dx, fma(dy, dy, dz * dz))) - B.d;
+  }
+  if (B.shape == SH_PARABOLOID) {
+    const double dx = y[0] - B.nrm[0], dy = y[1] - B.nrm[1];
+    return y[2] - B.nrm[2] - B.d * fma(dx, dx, dy * dy);
+  }
+  return fma(y[2], B.nrm[2], fma(y[1], B.nrm[1], y[0] * B.nrm[0])) - B.d;
+}
+
+// Unit normal of a boundary at y, pointing to its g > 0 side.
+__device__ __forceinline__ void bnd_normal(const KBnd& B, const double* y, double n[3]) {
+  if (B.shape == SH_PLANE) {
+    n[0] = B.nrm[0];
+    n[1] = B.nrm[1];
+    n[2] = B.nrm[2];
+    return;
+  }
+  if (B.shape == SH_SPHERE) {
+    n[0] = y[0] - B.nrm[0];
+    n[1] = y[1] - B.nrm[1];
+    n[2] = y[2] - B.nrm[2];
+  } else {
+    n[0] = -2.0 * B.d * (y[0] - B.nrm[0]);
+    n[1] = -2.0 * B.d * (y[1] - B.nrm[1]);
+    n[2] = 1.0;
+  }
+  const double il = rsqrt_nr(fma(n[0], n[0], fma(n[1], n[1], n[2] * n[2])));
+  n[0] *= il;
+  n[1] *= il;
+  n[2] *= il;
+}
+
+// Put a located point onto the boundary: along the normal (plane),
+// radially (sphere), vertically (paraboloid, whose g is a depth difference).
+__device__ __forceinline__ void bnd_snap(const KBnd& B, double* y) {
+  if (B.shape == SH_SPHERE) {
+    const double dx = y[0] - B.nrm[0], dy = y[1] - B.nrm[1], dz = y[2] - B.nrm[2];
+    const double f = B.d * rsqrt_nr(fma(dx, dx, fma(dy, dy, dz * dz)));
+    y[0] = fma(f, dx, B.nrm[0]);
+    y[1] = fma(f, dy, B.nrm[1]);
+    y[2] = fma(f, dz, B.nrm[2]);
+  } else if (B.shape == SH_PARABOLOID) {
+    y[2] -= bnd_value(B, y);
+  } else {
+    const double g = bnd_value(B, y);
+    y[0] -= g * B.nrm[0];
+    y[1] -= g * B.nrm[1];
+    y[2] -= g * B.nrm[2];
+  }
+}
+
 // Boundary function with the ray's side sign applied: > 0 before crossing.
 __device__ __forceinline__ double bnd_G(const KParams& P, const KBnd& B, int k, uint32_t side,
                                         const double y[7]) {
   if (B.kind == B_TIME) return (P.t_max - y[6]) * 299792458.0;
-  double g = fma(y[2], B.nrm[2], fma(y[1], B.nrm[1], y[0] * B.nrm[0])) - B.d;
+  const double g = bnd_value(B, y);
   return ((side >> k) & 1u) ? g : -g;
 }
 

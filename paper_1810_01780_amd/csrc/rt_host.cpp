@@ -71,7 +71,15 @@ rt_status validate(const rt_field* field, const rt_boundaries* bnd, const rt_sou
       FAIL(RT_ERR_INVALID_ARG, "plane %d: non-finite point or normal", k);
     const double l2 = p.normal[0] * p.normal[0] + p.normal[1] * p.normal[1] +
                       p.normal[2] * p.normal[2];
-    if (!(l2 > 0.0)) FAIL(RT_ERR_INVALID_ARG, "plane %d: zero normal", k);
+    if (p.shape == RT_SHAPE_PLANE && !(l2 > 0.0))
+      FAIL(RT_ERR_INVALID_ARG, "plane %d: zero normal", k);
+    if (p.shape != RT_SHAPE_PLANE && p.shape != RT_SHAPE_SPHERE &&
+        p.shape != RT_SHAPE_PARABOLOID)
+      FAIL(RT_ERR_INVALID_ARG, "plane %d: unknown shape %d", k, p.shape);
+    if (p.shape == RT_SHAPE_SPHERE && !(p.param > 0.0 && std::isfinite(p.param)))
+      FAIL(RT_ERR_INVALID_ARG, "plane %d: sphere radius must be > 0", k);
+    if (p.shape == RT_SHAPE_PARABOLOID && !(p.param != 0.0 && std::isfinite(p.param)))
+      FAIL(RT_ERR_INVALID_ARG, "plane %d: paraboloid curvature must be finite and non-zero", k);
     if (p.kind != RT_PLANE_FRESNEL && p.kind != RT_PLANE_ABSORB)
       FAIL(RT_ERR_INVALID_ARG, "plane %d: unknown kind %d", k, p.kind);
     if (p.region_pos < 0 || p.region_pos >= field->n_regions || p.region_neg < 0 ||
@@ -206,6 +214,11 @@ rt_status rt_solve_validate(const rt_field* field, const rt_boundaries* bnd, dou
     rt::set_last_error("solves need planes[0] = the surface, of kind RT_PLANE_FRESNEL");
     return RT_ERR_INVALID_ARG;
   }
+  for (int k = 0; k < bnd->n_planes; ++k)
+    if (bnd->planes[k].shape != RT_SHAPE_PLANE) {
+      rt::set_last_error("solves follow planar boundaries only (plane %d is curved)", k);
+      return RT_ERR_UNSUPPORTED;
+    }
   if (prm) {
     if (prm->n_scan < 2 || prm->n_scan > 4096 || prm->max_iter < 1 || prm->max_iter > 1000 ||
         prm->max_brackets < 1 || prm->max_brackets > 16) {

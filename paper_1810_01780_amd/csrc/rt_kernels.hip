@@ -114,13 +114,7 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
                                                   double ys[7], double h_next, const Counters& C,
                                                   const WaveQueue& WQ) {
   const KBnd& B = s_bnd[k];
-  if (B.kind != B_TIME) {
-    // snap onto the plane
-    double g = fma(ys[2], B.nrm[2], fma(ys[1], B.nrm[1], ys[0] * B.nrm[0])) - B.d;
-    ys[0] -= g * B.nrm[0];
-    ys[1] -= g * B.nrm[1];
-    ys[2] -= g * B.nrm[2];
-  }
+  if (B.kind != B_TIME) bnd_snap(B, ys);  // onto the boundary
 #pragma unroll
   for (int i = 0; i < 7; ++i) R.y[i] = ys[i];
   set_direction<MODEL, FIELD>(P, R, ys[3], ys[4], ys[5]);
@@ -134,7 +128,9 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
   C.bump(S_EVENTS);
 
   const double sg = ((R.side >> k) & 1u) ? 1.0 : -1.0;
-  const double nin[3] = {sg * B.nrm[0], sg * B.nrm[1], sg * B.nrm[2]};
+  double nb[3];
+  bnd_normal(B, R.y, nb);
+  const double nin[3] = {sg * nb[0], sg * nb[1], sg * nb[2]};
   const double il = rsqrt_nr(fma(R.y[3], R.y[3], fma(R.y[4], R.y[4], R.y[5] * R.y[5])));
   const double u[3] = {R.y[3] * il, R.y[4] * il, R.y[5] * il};
   double ci = -fma(u[2], nin[2], fma(u[1], nin[1], u[0] * nin[0]));
@@ -659,7 +655,7 @@ __global__ void init_kernel(KParams P, const double* __restrict__ src_xyz, int32
   for (int k = 0; k < P.n_bnd; ++k) {
     const KBnd& B = P.bnd[k];
     if (B.kind == B_TIME) continue;
-    const double g = r[0] * B.nrm[0] + r[1] * B.nrm[1] + r[2] * B.nrm[2] - B.d;
+    const double g = bnd_value(B, r);
     if (B.kind == B_BOX) ok = ok && g > 0.0;
     else ok = ok && fabs(g) > 1e-9;
     if (g > 0.0) side |= 1u << k;
@@ -814,10 +810,16 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   for (int i = 0; i < bnd->n_planes; ++i) {
     const rt_plane& p = bnd->planes[i];
     KBnd& b = P.bnd[nb++];
-    const double len = sqrt(p.normal[0] * p.normal[0] + p.normal[1] * p.normal[1] +
-                            p.normal[2] * p.normal[2]);
-    for (int a = 0; a < 3; ++a) b.nrm[a] = p.normal[a] / len;
-    b.d = p.point[0] * b.nrm[0] + p.point[1] * b.nrm[1] + p.point[2] * b.nrm[2];
+    b.shape = p.shape;
+    if (p.shape == RT_SHAPE_PLANE) {
+      const double len = sqrt(p.normal[0] * p.normal[0] + p.normal[1] * p.normal[1] +
+                              p.normal[2] * p.normal[2]);
+      for (int a = 0; a < 3; ++a) b.nrm[a] = p.normal[a] / len;
+      b.d = p.point[0] * b.nrm[0] + p.point[1] * b.nrm[1] + p.point[2] * b.nrm[2];
+    } else {  // centre or vertex, radius or curvature
+      for (int a = 0; a < 3; ++a) b.nrm[a] = p.point[a];
+      b.d = p.param;
+    }
     b.kind = p.kind == RT_PLANE_ABSORB ? B_ABSORB : B_FRESNEL;
     b.reg_pos = p.region_pos;
     b.reg_neg = p.region_neg;

@@ -18,11 +18,16 @@ struct KRegion {
   int32_t use_grid, pad;
 };
 
-// g(r) = r . nrm - d  (unit normal); positive on the +normal side
+// Boundary surface, positive g on the region_pos side:
+//   plane       g = r . nrm - d (unit normal)
+//   sphere      g = |r - nrm| - d (centre nrm, radius d)
+//   paraboloid  g = z - nrm[2] - d ((x - nrm[0])^2 + (y - nrm[1])^2)
+//               (vertex nrm, curvature d)
+enum ShapeKind : int32_t { SH_PLANE = 0, SH_SPHERE = 1, SH_PARABOLOID = 2 };
 struct KBnd {
   double nrm[3];
   double d;
-  int32_t kind, reg_pos, reg_neg, pad;
+  int32_t kind, reg_pos, reg_neg, shape;
 };
 
 struct Pool {

@@ -359,3 +359,33 @@ def surrogate_training_set(n_profiles: int, pairs_per_profile: int, seed: int = 
         dist = rng.uniform(10.0, 3000.0, pairs_per_profile)
         out.append((z0, dn, zs, zr, dist))
     return out
+
+
+def curved(n_sources: int = 4, rays_per_source: int = 256, model: int = MODEL_PAPER,
+           generations: int = 3, s_max: float = 1500.0, tol: float = 1e-6,
+           bed_kind: int = PLANE_ABSORB) -> Scene:
+    """Curved boundaries in firn: an air-filled spherical void (radius 25 m,
+    centre at 150 m depth) with Fresnel walls, a paraboloidal bed
+    z = 400 m - 0.0005 rho^2 (absorbing, or a Fresnel interface to rock of
+    n = 2.5 below it), the flat Fresnel surface; isotropic rays from
+    sources 40 m off the axis at 180 and 220 m depth; amplitude cut 1e-3
+    (bounds the bounces inside the void)."""
+    rng = _rng(4)
+    offs = np.array([[40.0, 0.0, 180.0], [-40.0, 0.0, 180.0], [0.0, 40.0, 220.0],
+                     [0.0, -40.0, 220.0]])[:n_sources]
+    dirs = isotropic(rng, n_sources * rays_per_source)
+    ray_src = np.repeat(np.arange(n_sources, dtype=np.int32), rays_per_source)
+    regions = [air_region(),
+               Region(**FIRN, z_top=0.0, z_bot=np.inf),
+               Region(a=1.0, z_top=np.inf, z_bot=np.inf),       # inside the void
+               Region(a=2.5, z_top=np.inf, z_bot=np.inf)]       # rock below the bed
+    below = 3 if bed_kind == PLANE_FRESNEL else 1
+    planes = [surface_plane(ice=1, air=0),
+              Plane(point=(0.0, 0.0, 150.0), normal=(0.0, 0.0, 1.0), region_pos=1,
+                    region_neg=2, shape=SHAPE_SPHERE, param=25.0),
+              Plane(point=(0.0, 0.0, 400.0), normal=(0.0, 0.0, 1.0), region_pos=below,
+                    region_neg=1, kind=bed_kind, shape=SHAPE_PARABOLOID, param=-5e-4)]
+    return Scene(name="curved", regions=regions, planes=planes, sources=offs,
+                 ray_src=ray_src, dirs=dirs,
+                 limits=Limits(tol=tol, h_min=1e-3, h_max=10.0, s_max=s_max, amp_min=1e-3,
+                               max_generations=generations, model=model))

@@ -29,13 +29,13 @@ def test_library_exports_every_declared_symbol():
                           "raytrace_launch", "rt_collect", "rt_last_error"}
     for n in names:
         assert hasattr(lib, n), n
-    assert B.rt_abi_version() == 1
+    assert B.rt_abi_version() == 2
 
 
 def test_struct_layouts_match_header():
     # sizes follow from the header's field lists on x86-64
     assert C.sizeof(B.rt_region) == 56
-    assert C.sizeof(B.rt_plane) == 64
+    assert C.sizeof(B.rt_plane) == 72
     assert C.sizeof(B.rt_step_limits) == 64
     assert C.sizeof(B.rt_stats) == 8 * len(B.STAT_FIELDS)
     assert C.sizeof(B.rt_outputs) == 8 * (len(B.RECORD_FIELDS) + 2)
@@ -229,3 +229,22 @@ def test_solve_and_shoot_validate_before_touching_the_device():
     bad = B.solve_params(max_iter=0)
     st = B.raytrace_solve(d.field, d.bnd, d.tol, d.limits, pairs, bad, out, 0, 0, 0)
     assert st == B.RT_ERR_INVALID_ARG
+
+
+def test_validate_curved_boundaries():
+    d = _descs(W.curved(n_sources=1, rays_per_source=4))
+    assert _validate(d) == B.RT_OK
+    d.bnd.planes[1].param = 0.0           # sphere of radius 0
+    assert _validate(d) == B.RT_ERR_INVALID_ARG and "radius" in B.rt_last_error()
+    d = _descs(W.curved(n_sources=1, rays_per_source=4))
+    d.bnd.planes[2].param = float("inf")  # paraboloid curvature
+    assert _validate(d) == B.RT_ERR_INVALID_ARG
+    d = _descs(W.curved(n_sources=1, rays_per_source=4))
+    d.bnd.planes[1].shape = 7
+    assert _validate(d) == B.RT_ERR_INVALID_ARG and "shape" in B.rt_last_error()
+    # solves follow planes only
+    s = _solve_descs()
+    s.bnd.planes[1].shape = B.RT_SHAPE_SPHERE if hasattr(B, "RT_SHAPE_SPHERE") else 1
+    s.bnd.planes[1].param = 10.0
+    assert B.rt_solve_validate(s.field, s.bnd, s.tol, s.limits, B.solve_params()) == \
+        B.RT_ERR_UNSUPPORTED

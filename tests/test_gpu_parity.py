@@ -69,6 +69,24 @@ def test_two_layer_reduced(gpu, oracle_lib, model):
     assert abs(gst["accepted"] - rst["accepted"]) <= 1e-4 * rst["accepted"]
 
 
+@pytest.mark.parametrize("bed", [W.PLANE_ABSORB, W.PLANE_FRESNEL])
+@pytest.mark.parametrize("model", [W.MODEL_PAPER, W.MODEL_EXACT])
+def test_curved_boundaries(gpu, oracle_lib, model, bed):
+    """A spherical air void with Fresnel walls and a paraboloidal bed
+    (absorbing, or Fresnel to rock) in firn, 1,024 isotropic rays, three
+    generations."""
+    sc = W.curved(model=model, bed_kind=bed)
+    got, gst, ref, rst, s = run_pair(gpu, oracle_lib, sc, f"curved-m{model}-bed{bed}")
+    for f in ("spawned", "events", "records"):
+        assert gst[f] == rst[f], f
+    assert (got["region"] == 2).sum() > 0     # some rays end inside the void
+    assert (got["status"] == 4).sum() > 0     # amplitude cut inside the void
+    if bed == W.PLANE_ABSORB:
+        assert (got["status"] == 5).sum() > 0
+    else:
+        assert (got["region"] == 3).sum() > 0
+
+
 def test_paper_example_time_and_amplitude_cuts(gpu, oracle_lib):
     """Fig. 1 setting: 10 m top layer, 5 us travel-time limit, A/A0 < 0.05 cut."""
     sc = W.paper_example()
