@@ -38,7 +38,12 @@ def build(force: bool = True) -> str:
 class Region(C.Structure):
     _fields_ = [("a", C.c_double), ("b", C.c_double), ("dn", C.c_double),
                 ("z0", C.c_double), ("z_top", C.c_double), ("z_bot", C.c_double),
-                ("use_grid", C.c_int32)]
+                ("use_grid", C.c_int32), ("axis", C.c_double * 3)]
+
+
+class Anomaly(C.Structure):
+    _fields_ = [("centre", C.c_double * 3), ("amplitude", C.c_double),
+                ("sigma", C.c_double), ("region", C.c_int32)]
 
 
 class Plane(C.Structure):
@@ -61,7 +66,8 @@ class Problem(C.Structure):
                 ("tol", C.c_double), ("h_min", C.c_double), ("h_max", C.c_double),
                 ("h_init", C.c_double), ("s_max", C.c_double), ("t_max", C.c_double),
                 ("amp_min", C.c_double), ("max_gen", C.c_int32),
-                ("model", C.c_int32), ("max_steps", C.c_int64)]
+                ("model", C.c_int32), ("max_steps", C.c_int64),
+                ("n_anomalies", C.c_int32), ("anomalies", C.POINTER(Anomaly))]
 
 
 F64_FIELDS = ["x", "y", "z", "ux", "uy", "uz", "s", "t",
@@ -124,7 +130,11 @@ class _Prepared:
         self.keep = []
         regs = (Region * max(1, len(scene.regions)))()
         for i, r in enumerate(scene.regions):
-            regs[i] = Region(r.a, r.b, r.dn, r.z0, r.z_top, r.z_bot, int(r.use_grid))
+            regs[i] = Region(r.a, r.b, r.dn, r.z0, r.z_top, r.z_bot, int(r.use_grid),
+                             (C.c_double * 3)(*r.axis))
+        anoms = (Anomaly * max(1, len(scene.anomalies)))()
+        for i, q in enumerate(scene.anomalies):
+            anoms[i] = Anomaly((C.c_double * 3)(*q.centre), q.amplitude, q.sigma, q.region)
         pls = (Plane * max(1, len(scene.planes)))()
         for i, p in enumerate(scene.planes):
             pls[i] = Plane((C.c_double * 3)(*p.point), (C.c_double * 3)(*p.normal),
@@ -132,10 +142,12 @@ class _Prepared:
         src = np.ascontiguousarray(scene.sources, dtype=np.float64)
         dirs = np.ascontiguousarray(scene.dirs, dtype=np.float64)
         rsrc = np.ascontiguousarray(scene.ray_src, dtype=np.int32)
-        self.keep += [regs, pls, src, dirs, rsrc]
+        self.keep += [regs, pls, anoms, src, dirs, rsrc]
         P = Problem()
         P.n_regions = len(scene.regions)
         P.regions = C.cast(regs, C.POINTER(Region))
+        P.n_anomalies = len(scene.anomalies)
+        P.anomalies = C.cast(anoms, C.POINTER(Anomaly))
         P.n_planes = len(scene.planes)
         P.planes = C.cast(pls, C.POINTER(Plane))
         if scene.box_lo is not None:

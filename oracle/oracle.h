@@ -10,6 +10,9 @@
  * shares no code, header or constant with the GPU library.
  *
  * Coordinates: z is depth (positive downward), the surface is z = 0.
+ * Besides stratified media n(z) it evaluates non-stratified analytic media
+ * (a stratification axis other than depth, Gaussian index anomalies) and
+ * gridded data, which section 2 names among the supported fields.
  */
 #ifndef RT_ORACLE_H
 #define RT_ORACLE_H
@@ -31,11 +34,22 @@ enum {
   ORC_ST_NONFINITE = 7  /* NaN or Inf in the state */
 };
 
-/* n(z) = a + b z - dn exp(-z/z0), or the grid when use_grid != 0 */
+/* n = a + b zeta - dn exp(-zeta/z0) with zeta = k . r, k the unit vector
+ * along axis (axis all zero: k = (0, 0, 1), i.e. zeta = depth z); or the grid
+ * when use_grid != 0.  Gaussian anomalies of the region are added to either.
+ * [z_top, z_bot) picks the region a primary ray starts in. */
 typedef struct {
   double a, b, dn, z0, z_top, z_bot;
   int32_t use_grid;
+  double axis[3];
 } orc_region;
+
+/* amplitude exp(-|r - centre|^2 / (2 sigma^2)) added to n inside region */
+typedef struct {
+  double centre[3];
+  double amplitude, sigma;
+  int32_t region;
+} orc_anomaly;
 
 /* Boundary surfaces (shape): plane through point with normal; sphere with
  * centre point and radius param (g = |r - c| - R, region_pos outside);
@@ -69,6 +83,8 @@ typedef struct {
   double tol, h_min, h_max, h_init, s_max, t_max, amp_min;
   int32_t max_gen, model;
   int64_t max_steps;
+  int32_t n_anomalies;
+  const orc_anomaly* anomalies;
 } orc_problem;
 
 typedef struct {

@@ -251,14 +251,35 @@ void orc_field(const orc_problem* P, int32_t reg, const double r[3], double* n,
   const orc_region* R = &P->regions[reg];
   if (R->use_grid) {
     grid_eval(P, r, n, g);
-    return;
+  } else {
+    /* n = a + b zeta - dn exp(-zeta/z0) along the unit stratification axis k
+     * (depth when no axis is given): grad n = (b + dn/z0 exp(-zeta/z0)) k */
+    double k[3] = {0.0, 0.0, 1.0};
+    double len = sqrt(R->axis[0] * R->axis[0] + R->axis[1] * R->axis[1] +
+                      R->axis[2] * R->axis[2]);
+    if (len > 0.0)
+      for (int a = 0; a < 3; ++a) k[a] = R->axis[a] / len;
+    double zeta = k[0] * r[0] + k[1] * r[1] + k[2] * r[2];
+    double e = R->dn != 0.0 ? exp(-zeta / R->z0) : 0.0;
+    *n = R->a + R->b * zeta - R->dn * e;
+    double gs = R->b + R->dn / R->z0 * e;
+    for (int a = 0; a < 3; ++a) g[a] = gs * k[a];
   }
-  /* n(z) = a + b z - dn exp(-z/z0); z is depth */
-  double e = R->dn != 0.0 ? exp(-r[2] / R->z0) : 0.0;
-  *n = R->a + R->b * r[2] - R->dn * e;
-  g[0] = 0.0;
-  g[1] = 0.0;
-  g[2] = R->b + R->dn / R->z0 * e;
+  /* Gaussian anomalies A exp(-q / (2 sigma^2)), q = |r - c|^2:
+   * grad = -A exp(...) (r - c) / sigma^2 */
+  for (int j = 0; j < P->n_anomalies; ++j) {
+    const orc_anomaly* A = &P->anomalies[j];
+    if (A->region != reg) continue;
+    double d[3], q = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      d[a] = r[a] - A->centre[a];
+      q += d[a] * d[a];
+    }
+    double s2 = A->sigma * A->sigma;
+    double v = A->amplitude * exp(-q / (2.0 * s2));
+    *n += v;
+    for (int a = 0; a < 3; ++a) g[a] -= v * d[a] / s2;
+  }
 }
 
 /* ------------------------------------------------------------------------ */

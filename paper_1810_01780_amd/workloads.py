@@ -47,6 +47,19 @@ class Region:
     z_top: float = -np.inf   # launch-region lookup: z_top <= z < z_bot
     z_bot: float = np.inf
     use_grid: bool = False
+    # stratification axis: n = a + b zeta - dn exp(-zeta / z0), zeta = k . r
+    # with k = axis / |axis|; all zero means depth, zeta = z
+    axis: Sequence[float] = (0.0, 0.0, 0.0)
+
+
+@dataclasses.dataclass
+class Anomaly:
+    """Gaussian index anomaly: amplitude exp(-|r - centre|^2 / (2 sigma^2))
+    added to the refractive index of one region."""
+    centre: Sequence[float]
+    amplitude: float
+    sigma: float
+    region: int
 
 
 @dataclasses.dataclass
@@ -96,6 +109,7 @@ class Scene:
     box_lo: Optional[Sequence[float]] = None
     box_hi: Optional[Sequence[float]] = None
     grid: Optional[Grid] = None
+    anomalies: List[Anomaly] = dataclasses.field(default_factory=list)
 
     @property
     def n_rays(self) -> int:
