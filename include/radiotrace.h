@@ -42,9 +42,10 @@
 extern "C" {
 #endif
 
-#define RT_ABI_VERSION 2
+#define RT_ABI_VERSION 3
 #define RT_MAX_REGIONS 8
 #define RT_MAX_PLANES 16
+#define RT_MAX_ANOMALIES 8
 #define RT_MAX_GENERATIONS 4 /* ray keys hold three 8-bit event ordinals */
 
 typedef enum {
@@ -75,15 +76,30 @@ enum {
                           or outside the box; not traced */
 };
 
-/* One stratified medium.  Analytic: n(z) = a + b*z - dn*exp(-z/z0), which
- * covers the paper's firn profile n0 - dn*exp(-depth/z0) (section 2) and
- * linear and constant media.  use_grid != 0: n comes from rt_field.grid.
- * [z_top, z_bot) is used only to pick the region a primary ray starts in. */
+/* One medium.  Analytic: n = a + b*zeta - dn*exp(-zeta/z0) with
+ * zeta = k . r, k = axis/|axis| the stratification direction; an all-zero
+ * axis means depth, zeta = z.  This covers the paper's firn profile
+ * n0 - dn*exp(-depth/z0) (section 2), linear and constant media, and layers
+ * stratified along any direction (section 2 lists analytic fields beyond
+ * depth profiles).  use_grid != 0: n comes from rt_field.grid (axis
+ * unused).  Gaussian anomalies (rt_field.anomalies) naming the region add
+ * to either.  [z_top, z_bot) is used only to pick the region a primary ray
+ * starts in, by its depth z. */
 typedef struct {
   double a, b, dn, z0;
   double z_top, z_bot;
   int32_t use_grid;
+  double axis[3];
 } rt_region;
+
+/* Gaussian refractive-index anomaly amplitude * exp(-|r - centre|^2 /
+ * (2 sigma^2)), added to the index of one region (a lens where amplitude >
+ * 0, a low-index pocket where it is < 0).  sigma > 0. */
+typedef struct {
+  double centre[3];
+  double amplitude, sigma;
+  int32_t region;
+} rt_anomaly;
 
 /* Gridded refractive index (section 2 mentions gridded data): FP32 values
  * n[k][j][i] at origin + (i, j, k) * spacing, x fastest.  n is trilinearly
@@ -98,10 +114,16 @@ typedef struct {
   double origin[3], spacing[3];
 } rt_grid;
 
+/* Fields that are not stratified in depth (a grid, an axis other than
+ * +z, anomalies) run on the general 3-D gradient kernel; depth-stratified
+ * fields on the kernel specialised for them.  Solves take depth-stratified
+ * fields only. */
 typedef struct {
-  int32_t n_regions;        /* 1..RT_MAX_REGIONS */
-  const rt_region* regions; /* host */
-  rt_grid grid;             /* used when any region has use_grid */
+  int32_t n_regions;          /* 1..RT_MAX_REGIONS */
+  const rt_region* regions;   /* host */
+  rt_grid grid;               /* used when any region has use_grid */
+  int32_t n_anomalies;        /* 0..RT_MAX_ANOMALIES */
+  const rt_anomaly* anomalies; /* host; may be NULL when n_anomalies == 0 */
 } rt_field;
 
 /* A boundary surface (section 2: boundaries are defined explicitly; curved

@@ -26,13 +26,19 @@ RT_OK, RT_ERR_INVALID_ARG, RT_ERR_CAPACITY, RT_ERR_DEVICE, RT_ERR_UNSUPPORTED = 
 RT_ST_QUEUED, RT_ST_EMPTY = -1, 0
 (RT_ST_PATH, RT_ST_BOX, RT_ST_TIME, RT_ST_AMP, RT_ST_ABSORB, RT_ST_STEPCAP,
  RT_ST_NONFINITE, RT_ST_INVALID) = range(1, 9)
-RT_MAX_REGIONS, RT_MAX_PLANES, RT_MAX_GENERATIONS = 8, 16, 4
+RT_MAX_REGIONS, RT_MAX_PLANES, RT_MAX_GENERATIONS, RT_MAX_ANOMALIES = 8, 16, 4, 8
 RT_SHAPE_PLANE, RT_SHAPE_SPHERE, RT_SHAPE_PARABOLOID = 0, 1, 2
 
 
 class rt_region(C.Structure):
     _fields_ = [("a", C.c_double), ("b", C.c_double), ("dn", C.c_double), ("z0", C.c_double),
-                ("z_top", C.c_double), ("z_bot", C.c_double), ("use_grid", C.c_int32)]
+                ("z_top", C.c_double), ("z_bot", C.c_double), ("use_grid", C.c_int32),
+                ("axis", C.c_double * 3)]
+
+
+class rt_anomaly(C.Structure):
+    _fields_ = [("centre", C.c_double * 3), ("amplitude", C.c_double), ("sigma", C.c_double),
+                ("region", C.c_int32)]
 
 
 class rt_grid(C.Structure):
@@ -41,7 +47,8 @@ class rt_grid(C.Structure):
 
 
 class rt_field(C.Structure):
-    _fields_ = [("n_regions", C.c_int32), ("regions", C.POINTER(rt_region)), ("grid", rt_grid)]
+    _fields_ = [("n_regions", C.c_int32), ("regions", C.POINTER(rt_region)), ("grid", rt_grid),
+                ("n_anomalies", C.c_int32), ("anomalies", C.POINTER(rt_anomaly))]
 
 
 class rt_plane(C.Structure):
@@ -308,13 +315,18 @@ class HostDescriptors:
         self.scene = scene
         regs = (rt_region * max(1, len(scene.regions)))()
         for i, r in enumerate(scene.regions):
-            regs[i] = rt_region(r.a, r.b, r.dn, r.z0, r.z_top, r.z_bot, int(r.use_grid))
+            regs[i] = rt_region(r.a, r.b, r.dn, r.z0, r.z_top, r.z_bot, int(r.use_grid),
+                                (C.c_double * 3)(*r.axis))
+        anoms = (rt_anomaly * max(1, len(scene.anomalies)))()
+        for i, q in enumerate(scene.anomalies):
+            anoms[i] = rt_anomaly((C.c_double * 3)(*q.centre), q.amplitude, q.sigma, q.region)
         pls = (rt_plane * max(1, len(scene.planes)))()
         for i, p in enumerate(scene.planes):
             pls[i] = rt_plane((C.c_double * 3)(*p.point), (C.c_double * 3)(*p.normal),
                               p.region_pos, p.region_neg, p.kind, p.shape, p.param)
-        self._keep = [regs, pls]
-        self.field = rt_field(len(scene.regions), C.cast(regs, C.POINTER(rt_region)), rt_grid())
+        self._keep = [regs, pls, anoms]
+        self.field = rt_field(len(scene.regions), C.cast(regs, C.POINTER(rt_region)), rt_grid(),
+                              len(scene.anomalies), C.cast(anoms, C.POINTER(rt_anomaly)))
         if scene.grid is not None:
             nz, ny, nx = scene.grid.n.shape
             self.field.grid.nx, self.field.grid.ny, self.field.grid.nz = nx, ny, nz

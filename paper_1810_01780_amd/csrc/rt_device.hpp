@@ -105,7 +105,7 @@ __device__ __forceinline__ double exp_small(double x) {
 // Medium of one ray, kept in registers: n(z) = a + b z - dn exp(-z/z0).
 struct Medium {
   double a, b, dn, inv_z0, dn_inv_z0;
-  int use_grid;
+  int use_grid, reg;
 };
 
 // Media and boundary tables indexed per lane (by a ray's medium or by the
@@ -117,7 +117,7 @@ __shared__ KBnd s_bnd[kMaxBnd];
 __device__ __forceinline__ Medium medium_of(const KParams& P, int r) {
   (void)P;
   const KRegion& R = s_reg[r];
-  return Medium{R.a, R.b, R.dn, R.inv_z0, R.dn_inv_z0, R.use_grid};
+  return Medium{R.a, R.b, R.dn, R.inv_z0, R.dn_inv_z0, R.use_grid, r};
 }
 
 __device__ __forceinline__ void strat_field(const Medium& M, double z, double& n, double& gz) {
@@ -268,19 +268,34 @@ __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], 
   }
 }
 
-// General 3-D gradient (gridded media, or analytic media inside the grid
-// kernel).
+// General 3-D gradient: gridded media, or analytic media stratified along
+// their axis (ax, from LDS), plus the Gaussian anomalies of the medium's
+// region (uniform loop over the kernel arguments).
 template <int MODEL>
 __device__ __forceinline__ void field3(const KParams& P, const Medium& M, double x, double y,
                                        double z, double& n, double g[3]) {
   if (M.use_grid) {
     grid_field(P, x, y, z, n, g);
   } else {
-    double gz;
-    strat_field(M, z, n, gz);
-    g[0] = 0.0;
-    g[1] = 0.0;
-    g[2] = gz;
+    const double* ax = s_reg[M.reg].ax;
+    const double zeta = fma(ax[0], x, fma(ax[1], y, ax[2] * z));
+    double gs;
+    strat_field(M, zeta, n, gs);
+    g[0] = gs * ax[0];
+    g[1] = gs * ax[1];
+    g[2] = gs * ax[2];
+  }
+  for (int j = 0; j < P.n_anom; ++j) {
+    const KAnom& A = P.anom[j];
+    if (A.region != M.reg) continue;
+    const double dx = x - A.c[0], dy = y - A.c[1], dz = z - A.c[2];
+    const double q = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double v = A.amp * exp(-q * A.k);
+    const double f = -2.0 * A.k * v;  // grad = -2 k v (r - c)
+    n += v;
+    g[0] = fma(f, dx, g[0]);
+    g[1] = fma(f, dy, g[1]);
+    g[2] = fma(f, dz, g[2]);
   }
 }
 

@@ -31,6 +31,17 @@ static bool finite3(const double* v) {
   return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
 }
 
+bool field_is_general(const rt_field* f) {
+  if (f->n_anomalies > 0) return true;
+  for (int i = 0; i < f->n_regions; ++i) {
+    const rt_region& r = f->regions[i];
+    if (r.use_grid) return true;
+    // an axis along +z (any length) or all zero is depth
+    if (r.axis[0] != 0.0 || r.axis[1] != 0.0 || r.axis[2] < 0.0) return true;
+  }
+  return false;
+}
+
 #define FAIL(code, ...)            \
   do {                             \
     set_last_error(__VA_ARGS__);   \
@@ -50,6 +61,20 @@ rt_status validate(const rt_field* field, const rt_boundaries* bnd, const rt_sou
       FAIL(RT_ERR_INVALID_ARG, "region %d: z0 must be finite and non-zero when dn != 0", i);
     if (std::isnan(r.z_top) || std::isnan(r.z_bot) || !(r.z_top <= r.z_bot))
       FAIL(RT_ERR_INVALID_ARG, "region %d: need z_top <= z_bot", i);
+    if (!finite3(r.axis)) FAIL(RT_ERR_INVALID_ARG, "region %d: non-finite axis", i);
+  }
+  if (field->n_anomalies < 0 || field->n_anomalies > RT_MAX_ANOMALIES ||
+      (field->n_anomalies > 0 && !field->anomalies))
+    FAIL(RT_ERR_INVALID_ARG, "n_anomalies must be 0..%d with an anomaly array",
+         RT_MAX_ANOMALIES);
+  for (int j = 0; j < field->n_anomalies; ++j) {
+    const rt_anomaly& q = field->anomalies[j];
+    if (!finite3(q.centre) || !std::isfinite(q.amplitude))
+      FAIL(RT_ERR_INVALID_ARG, "anomaly %d: non-finite centre or amplitude", j);
+    if (!(q.sigma > 0.0) || !std::isfinite(q.sigma) || !std::isfinite(1.0 / (q.sigma * q.sigma)))
+      FAIL(RT_ERR_INVALID_ARG, "anomaly %d: sigma must be > 0 (and not tiny)", j);
+    if (q.region < 0 || q.region >= field->n_regions)
+      FAIL(RT_ERR_INVALID_ARG, "anomaly %d: region index out of range", j);
   }
   if (field_uses_grid(field)) {
     const rt_grid& g = field->grid;
@@ -198,8 +223,9 @@ rt_status rt_solve_validate(const rt_field* field, const rt_boundaries* bnd, dou
   const rt_directions no_dirs = {nullptr, nullptr, 0};
   rt_status st = rt::validate(field, bnd, &no_src, &no_dirs, tol, &lim);
   if (st != RT_OK) return st;
-  if (rt::field_uses_grid(field)) {
-    rt::set_last_error("solves support stratified (analytic) fields only");
+  if (rt::field_is_general(field)) {
+    rt::set_last_error("solves support depth-stratified analytic fields only "
+                       "(no grid, axis, or anomalies)");
     return RT_ERR_UNSUPPORTED;
   }
   if (L->t_max != 0.0) {

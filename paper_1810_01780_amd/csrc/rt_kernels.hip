@@ -805,6 +805,18 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
     k.z_top = r.z_top;
     k.z_bot = r.z_bot;
     k.use_grid = r.use_grid ? 1 : 0;
+    const double len = sqrt(r.axis[0] * r.axis[0] + r.axis[1] * r.axis[1] +
+                            r.axis[2] * r.axis[2]);
+    for (int a = 0; a < 3; ++a) k.ax[a] = len > 0.0 ? r.axis[a] / len : (a == 2 ? 1.0 : 0.0);
+  }
+  P.n_anom = field->n_anomalies;
+  for (int j = 0; j < field->n_anomalies; ++j) {
+    const rt_anomaly& q = field->anomalies[j];
+    KAnom& A = P.anom[j];
+    for (int a = 0; a < 3; ++a) A.c[a] = q.centre[a];
+    A.amp = q.amplitude;
+    A.k = 1.0 / (2.0 * q.sigma * q.sigma);
+    A.region = q.region;
   }
   int nb = 0;
   for (int i = 0; i < bnd->n_planes; ++i) {
@@ -859,8 +871,9 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   P.gq = reinterpret_cast<int32_t*>(static_cast<char*>(workspace) + 4096);
   const size_t gq_bytes = ((size_t)out->capacity * 4 + 4095) / 4096 * 4096;
   P.stats = out->stats;
-  const bool grid = field_uses_grid(field);
-  if (grid) {
+  const bool has_grid = field_uses_grid(field);
+  const bool grid = field_is_general(field);  // FIELD = 1 kernel
+  if (has_grid) {
     const rt_grid& g = field->grid;
     P.nodes = static_cast<char*>(workspace) + 4096 + gq_bytes;
     P.gnx = g.nx;
@@ -887,7 +900,7 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
 
   hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, P);
   HIP_TRY(hipGetLastError());
-  if (grid) {
+  if (has_grid) {
     const int64_t total = (int64_t)field->grid.nx * field->grid.ny * field->grid.nz;
     hipLaunchKernelGGL(grid_prep_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                        field->grid.n, static_cast<float4*>(const_cast<void*>(P.nodes)),

@@ -11,11 +11,20 @@ namespace rt {
 constexpr int kMaxBnd = RT_MAX_PLANES + 6 + 1;
 enum BndKind : int32_t { B_FRESNEL = 0, B_ABSORB = 1, B_BOX = 2, B_TIME = 3 };
 
-// n(z) = a + b z - dn exp(-z / z0); exp is skipped when dn == 0
+// n = a + b zeta - dn exp(-zeta / z0), zeta = ax . r (unit axis; depth in the
+// stratified kernel); exp is skipped when dn == 0
 struct KRegion {
   double a, b, dn, inv_z0, dn_inv_z0;
   double z_top, z_bot;  // launch-region lookup: z_top <= z < z_bot
   int32_t use_grid, pad;
+  double ax[3];
+};
+
+// Gaussian anomaly amp exp(-k |r - c|^2), k = 1 / (2 sigma^2), in one region
+struct KAnom {
+  double c[3];
+  double amp, k;
+  int32_t region, pad;
 };
 
 // Boundary surface, positive g on the region_pos side:
@@ -51,6 +60,8 @@ struct KParams {
   KBnd bnd[kMaxBnd];
   int32_t n_regions, n_bnd;
   int32_t model, max_gen;
+  KAnom anom[RT_MAX_ANOMALIES];
+  int32_t n_anom, pad_anom;
   // grid: float4 nodes (n, Dx, Dy, Dz) with grad n = D / (2 spacing)
   const void* nodes;
   int32_t gnx, gny, gnz, refill;
@@ -73,5 +84,7 @@ rt_status validate(const rt_field* field, const rt_boundaries* boundaries,
                    const rt_sources* sources, const rt_directions* directions,
                    double tol, const rt_step_limits* limits);
 bool field_uses_grid(const rt_field* field);
+// true unless every region is analytic along +z and there are no anomalies
+bool field_is_general(const rt_field* field);
 
 }  // namespace rt

@@ -403,3 +403,28 @@ def curved(n_sources: int = 4, rays_per_source: int = 256, model: int = MODEL_PA
                  ray_src=ray_src, dirs=dirs,
                  limits=Limits(tol=tol, h_min=1e-3, h_max=10.0, s_max=s_max, amp_min=1e-3,
                                max_generations=generations, model=model))
+
+
+def field3d(n_sources: int = 4, rays_per_source: int = 256, model: int = MODEL_PAPER,
+            generations: int = 2, s_max: float = 1500.0, tol: float = 1e-6,
+            tilt_deg: float = 8.0) -> Scene:
+    """Firn that is not stratified in depth: the profile of FIRN along an axis
+    tilted by tilt_deg from the vertical toward +x, a high-index lens
+    (+0.04, sigma 20 m, centre at 120 m depth) and a low-index pocket
+    (-0.15, sigma 8 m, at (30, 20, 60) m) in it, under the flat Fresnel
+    surface; isotropic rays from sources 40 m off the axis at 180 and 220 m
+    depth."""
+    rng = _rng(4)
+    offs = np.array([[40.0, 0.0, 180.0], [-40.0, 0.0, 180.0], [0.0, 40.0, 220.0],
+                     [0.0, -40.0, 220.0]])[:n_sources]
+    dirs = isotropic(rng, n_sources * rays_per_source)
+    ray_src = np.repeat(np.arange(n_sources, dtype=np.int32), rays_per_source)
+    t = np.radians(tilt_deg)
+    regions = [air_region(),
+               Region(**FIRN, z_top=0.0, z_bot=np.inf, axis=(np.sin(t), 0.0, np.cos(t)))]
+    anomalies = [Anomaly(centre=(0.0, 0.0, 120.0), amplitude=0.04, sigma=20.0, region=1),
+                 Anomaly(centre=(30.0, 20.0, 60.0), amplitude=-0.15, sigma=8.0, region=1)]
+    return Scene(name="field3d", regions=regions, planes=[surface_plane(ice=1, air=0)],
+                 sources=offs, ray_src=ray_src, dirs=dirs, anomalies=anomalies,
+                 limits=Limits(tol=tol, h_min=1e-3, h_max=10.0, s_max=s_max,
+                               max_generations=generations, model=model))

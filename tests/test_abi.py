@@ -29,12 +29,14 @@ def test_library_exports_every_declared_symbol():
                           "raytrace_launch", "rt_collect", "rt_last_error"}
     for n in names:
         assert hasattr(lib, n), n
-    assert B.rt_abi_version() == 2
+    assert B.rt_abi_version() == 3
 
 
 def test_struct_layouts_match_header():
     # sizes follow from the header's field lists on x86-64
-    assert C.sizeof(B.rt_region) == 56
+    assert C.sizeof(B.rt_region) == 80
+    assert C.sizeof(B.rt_anomaly) == 48
+    assert C.sizeof(B.rt_field) == 104 and B.rt_field.n_anomalies.offset == 88
     assert C.sizeof(B.rt_plane) == 72
     assert C.sizeof(B.rt_step_limits) == 64
     assert C.sizeof(B.rt_stats) == 8 * len(B.STAT_FIELDS)
@@ -248,3 +250,34 @@ def test_validate_curved_boundaries():
     s.bnd.planes[1].param = 10.0
     assert B.rt_solve_validate(s.field, s.bnd, s.tol, s.limits, B.solve_params()) == \
         B.RT_ERR_UNSUPPORTED
+
+
+def test_validate_non_stratified_fields():
+    d = _descs(W.field3d(n_sources=1, rays_per_source=4))
+    assert _validate(d) == B.RT_OK
+    d.field.anomalies[0].sigma = 0.0
+    assert _validate(d) == B.RT_ERR_INVALID_ARG and "sigma" in B.rt_last_error()
+    d = _descs(W.field3d(n_sources=1, rays_per_source=4))
+    d.field.anomalies[1].region = 5
+    assert _validate(d) == B.RT_ERR_INVALID_ARG and "region" in B.rt_last_error()
+    d = _descs(W.field3d(n_sources=1, rays_per_source=4))
+    d.field.n_anomalies = B.RT_MAX_ANOMALIES + 1
+    assert _validate(d) == B.RT_ERR_INVALID_ARG
+    d = _descs(W.field3d(n_sources=1, rays_per_source=4))
+    d.field.regions[1].axis[0] = float("nan")
+    assert _validate(d) == B.RT_ERR_INVALID_ARG and "axis" in B.rt_last_error()
+    # solves take depth-stratified fields only: an axis along +z of any length
+    # is depth, any other axis or an anomaly is not
+    s = _solve_descs()
+    p = B.solve_params()
+    s.field.regions[1].axis[2] = 3.0
+    assert B.rt_solve_validate(s.field, s.bnd, s.tol, s.limits, p) == B.RT_OK
+    s.field.regions[1].axis[0] = 0.1
+    assert B.rt_solve_validate(s.field, s.bnd, s.tol, s.limits, p) == B.RT_ERR_UNSUPPORTED
+    s = _solve_descs()
+    s.field.regions[1].axis[2] = -1.0
+    assert B.rt_solve_validate(s.field, s.bnd, s.tol, s.limits, p) == B.RT_ERR_UNSUPPORTED
+    s = _solve_descs()
+    an = (B.rt_anomaly * 1)(B.rt_anomaly((C.c_double * 3)(0.0, 0.0, 100.0), 0.01, 5.0, 1))
+    s.field.n_anomalies, s.field.anomalies = 1, C.cast(an, C.POINTER(B.rt_anomaly))
+    assert B.rt_solve_validate(s.field, s.bnd, s.tol, s.limits, p) == B.RT_ERR_UNSUPPORTED

@@ -87,6 +87,29 @@ def test_curved_boundaries(gpu, oracle_lib, model, bed):
         assert (got["region"] == 3).sum() > 0
 
 
+@pytest.mark.parametrize("model", [W.MODEL_PAPER, W.MODEL_EXACT])
+def test_non_stratified_analytic_field(gpu, oracle_lib, model):
+    """Firn stratified along a tilted axis with a lens and a low-index pocket
+    (general 3-D kernel), 1,024 isotropic rays, refracted secondaries."""
+    sc = W.field3d(model=model)
+    got, gst, ref, rst, s = run_pair(gpu, oracle_lib, sc, f"field3d-m{model}")
+    for f in ("spawned", "events", "records"):
+        assert gst[f] == rst[f], f
+    assert gst["spawned"] > 0
+
+
+def test_grid_with_anomalies(gpu, oracle_lib):
+    """Gaussian anomalies added to a gridded field (64 x 48 x 40 nodes),
+    tolerance 1e-6."""
+    import dataclasses
+    sc = W.gridded(rays_per_source=8, n_sources=32, nx=64, ny=48, nz=40, s_max=600.0, tol=1e-6)
+    sc = dataclasses.replace(sc, anomalies=[
+        W.Anomaly(centre=(0.0, 0.0, 150.0), amplitude=0.05, sigma=25.0, region=1),
+        W.Anomaly(centre=(20.0, -10.0, 80.0), amplitude=-0.1, sigma=10.0, region=1)])
+    got, gst, ref, rst, s = run_pair(gpu, oracle_lib, sc, "grid-anomalies")
+    assert gst["accepted"] == rst["accepted"] and gst["rejected"] == rst["rejected"]
+
+
 def test_paper_example_time_and_amplitude_cuts(gpu, oracle_lib):
     """Fig. 1 setting: 10 m top layer, 5 us travel-time limit, A/A0 < 0.05 cut."""
     sc = W.paper_example()
