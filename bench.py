@@ -36,6 +36,19 @@ sys.path.insert(0, ROOT)
 #   renormalise w (3 FMA-equivalent + sqrt 8 + div 8 + 3 mul)                     24
 #   boundary tests (2 planes x 6) and s += h                                      13
 FLOP_PER_TRIAL_STRAT_PAPER = 540
+# Boundary tests per trial by surface: plane 3 FMA; sphere 3 sub + 2 FMA +
+# mul + sqrt + sub; paraboloid 4 sub + FMA + 2 mul; box face as a plane;
+# travel-time limit 2.
+SURFACE_FLOP = {0: 6, 1: 17, 2: 8}
+# General 3-D kernel, paper model, analytic medium along an axis with A
+# Gaussian anomalies in the ray's region:
+#   6 stages x (zeta 5 + profile 37 + grad 3 + anomalies 49 A + dw/ds 11 + 1)
+#   stage inputs of all six components (6 x 35)                           210
+#   fifth-order outputs (7 x 9) and error vector (6 x 9)                   117
+#   error norms (2 x 13 + |w0| 13 + 4)                                      43
+#   controller 69, renormalise 24, s += h 1                                 94
+FLOP_3D_BASE = 6 * (5 + 37 + 3 + 11 + 1) + 210 + 117 + 43 + 94
+FLOP_3D_PER_ANOMALY = 6 * 49
 # Gridded media, paper model: per stage 8 float4 node loads (128 B) -> 768 B
 # of node data per trial step.
 BYTES_PER_TRIAL_GRID = 768
@@ -64,10 +77,48 @@ def make_scene(name):
         return W.gridded(), dict(workload="grid256", rays=4194304, sources=256,
                                  grid=[256, 256, 128], spacing_m=10, tol=1e-7, s_max_m=3000,
                                  model="paper")
+    if name == "curved":
+        return W.curved(rays_per_source=262144), dict(
+            workload="curved", rays=1048576, sources=4, generations=3, tol=1e-6, s_max_m=1500,
+            model="paper", surfaces="plane, sphere R 25 m, paraboloid bed")
+    if name == "field3d":
+        return W.field3d(rays_per_source=262144), dict(
+            workload="field3d", rays=1048576, sources=4, generations=2, tol=1e-6, s_max_m=1500,
+            model="paper", field="firn along an axis tilted 8 deg, 2 Gaussian anomalies")
     if name == "fan1024":
         return W.point_source_fan(), dict(workload="fan1024", rays=1024, sources=1,
                                           generations=2, tol=1e-6, s_max_m=2000, model="paper")
     raise SystemExit(f"unknown workload {name}")
+
+
+def is_general(scene):
+    """True when the scene runs on the general 3-D kernel."""
+    return bool(scene.anomalies) or any(
+        r.use_grid or r.axis[0] != 0.0 or r.axis[1] != 0.0 or r.axis[2] < 0.0
+        for r in scene.regions)
+
+
+def flop_per_trial(scene, region):
+    """Algorithmic FP64 work of one paper-model trial step of a ray in
+    region (analytic media)."""
+    bnd = sum(SURFACE_FLOP[p.shape] for p in scene.planes)
+    bnd += 36 if scene.box_lo is not None else 0
+    bnd += 2 if scene.limits.t_max > 0 else 0
+    if not is_general(scene):
+        return FLOP_PER_TRIAL_STRAT_PAPER - 12 + bnd
+    n_an = sum(1 for q in scene.anomalies if q.region == region)
+    return FLOP_3D_BASE + FLOP_3D_PER_ANOMALY * n_an + bnd
+
+
+def trial_flops(scene, rec, trials):
+    """FLOP of a launch: each record's trials at its region's rate (a record
+    stays in one region: the parent reflects, the secondary carries the
+    refraction), event-search trials at the mean rate."""
+    import numpy as np
+    per = np.array([flop_per_trial(scene, r) for r in range(len(scene.regions))], float)
+    n = rec["n_acc"].astype(np.float64) + rec["n_rej"]
+    w = float((n * per[rec["region"]]).sum())
+    return w * trials / max(1.0, float(n.sum()))
 
 
 def cpu_baseline(scene, target_s, threads, log):
@@ -308,7 +359,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="twolayer",
-                    choices=["twolayer", "grid256", "fan1024", "solve", "surrogate"])
+                    choices=["twolayer", "grid256", "curved", "field3d", "fan1024", "solve",
+                             "surrogate"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -355,7 +407,7 @@ def main():
         ds.launch(tuning=tuning(b, e))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    _, st = ds.collect()
+    rec, st = ds.collect()
     kern_ms = []
     for b, e in pairs:
         ms = ctypes.c_float()
@@ -373,7 +425,7 @@ def main():
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
     else:
-        achieved = trials * FLOP_PER_TRIAL_STRAT_PAPER / kern_s / 1e12
+        achieved = trial_flops(scene, rec, trials) / kern_s / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
                 "traffic": None}
