@@ -188,7 +188,11 @@ typedef struct {
   int64_t suppressed_gen; /* secondaries not created: generation limit */
   int64_t suppressed_amp; /* secondaries not created: amplitude cut */
   int64_t records;    /* records written (rays finished) */
-  int64_t needed;     /* records the launch needed (primaries + spawned) */
+  int64_t needed;     /* records the launch needs: primaries + spawned; when
+                         some secondaries found no slot below capacity, plus
+                         the scheduler's reserve (64 slots per wave of the
+                         launch), which a relaunch with capacity >= needed
+                         always holds */
   int64_t nonfinite;  /* rays ended RT_ST_NONFINITE */
   int64_t max_gen;    /* highest generation traced */
   int64_t invalid;    /* primary rays flagged RT_ST_INVALID */
@@ -198,7 +202,8 @@ typedef struct {
 } rt_stats;
 
 /* Caller-owned output records, one per ray (primary or secondary), in no
- * particular order; 'key' identifies a ray deterministically: bits 24..55
+ * particular order, in slots [0, records + invalid) (primaries first, in
+ * slots [0, n)); 'key' identifies a ray deterministically: bits 24..55
  * hold the primary index, bits 16..23 / 8..15 / 0..7 the parent's event
  * ordinal (1..255) at which the generation-1 / -2 / -3 ancestor was cast.
  * All arrays are device arrays of 'capacity' elements.  x,y,z: final

@@ -406,7 +406,7 @@ class DeviceScene:
         st = rt_collect(host, self.capacity)
         if check and st != RT_OK:
             raise RTError(st, rt_last_error())
-        n = min(stats["needed"], self.capacity)
+        n = min(stats["records"] + stats["invalid"], self.capacity)
         out = {}
         for f in RECORD_FIELDS:
             a = self.rec[f][:n].cpu().numpy()

@@ -38,14 +38,78 @@ enum : int {
 // (the L2s of the eight XCDs are not coherent with each other, and
 // publishing through them would mean L2 write-backs).
 constexpr uint32_t kRing = 1024;  // LDS ring entries per wave (>= any local limit)
+constexpr int64_t kChunk = 64;    // secondary record slots a wave reserves at once
 struct WaveQueue {
   int32_t* ring;   // kRing slot indices
   uint32_t* head;  // next index to take
   uint32_t* tail;  // next index to fill
 };
 
-// Reserve consecutive record slots for the calling wave's active lanes (one
-// atomic per wave); returns this lane's slot index.
+// Per-lane ray data that boundary events read and update, kept in LDS (one
+// entry per thread) instead of being re-read from the record pool: the
+// Fresnel amplitudes and the ray key.  An event then issues no global load
+// whose completion it would wait for; the pool receives the amplitudes when
+// the record is written.
+__shared__ double s_as_re[256], s_as_im[256], s_ap_re[256], s_ap_im[256];
+__shared__ uint64_t s_key[256];
+
+// Record slots of secondaries.  A wave reserves slots in chunks of P.chunk
+// consecutive indices (one atomic per chunk rather than per spawning
+// iteration: a single counter bumped by every wave is a contended address),
+// which also keeps each wave's children in cache lines of their own.  The
+// unused rest of a wave's chunk is published as finished while the wave is
+// idle, so that finished == tail still means that no ray is running; the
+// wave takes that count back before it hands out such a slot.  Slots left
+// unused at the end are filled by moving the last records into them
+// (compact_*_kernel), so the records stay dense.  Near the capacity waves
+// switch to one reservation per child.
+__shared__ unsigned long long s_cnext[4], s_cend[4];
+__shared__ uint32_t s_cphant[4], s_cmode[4];
+
+__device__ __forceinline__ uint64_t wave_slot(const KParams& P, int wv) {
+  const uint64_t m = __ballot(1);
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  const uint32_t cnt = (uint32_t)__popcll(m);
+  const uint32_t rank = (uint32_t)__popcll(m & lanemask_lt());
+  unsigned long long b1 = 0, b2 = 0, t1 = 0;
+  if ((int)__lane_id() == leader) {
+    unsigned long long nx = s_cnext[wv], en = s_cend[wv];
+    t1 = min((unsigned long long)cnt, en - nx);
+    b1 = nx;
+    nx += t1;
+    const uint32_t rest = cnt - (uint32_t)t1;
+    if (rest > 0) {
+      if (s_cmode[wv]) {  // a fresh chunk (P.chunk >= 64 covers any rest)
+        const uint64_t b = __hip_atomic_fetch_add(&P.q->tail, (uint64_t)P.chunk, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        b2 = b;
+        nx = b + rest;
+        en = b + P.chunk;
+        if (b + 2 * (uint64_t)P.chunk > P.chunk_limit) s_cmode[wv] = 0;
+      } else {
+        b2 = __hip_atomic_fetch_add(&P.q->tail, (uint64_t)rest, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+        nx = en = 0;
+      }
+    }
+    s_cnext[wv] = nx;
+    s_cend[wv] = en;
+    // slots published as finished by an idle phase are running rays now
+    const uint32_t unused = (uint32_t)(en - nx);
+    if (s_cphant[wv] > unused) {
+      __hip_atomic_fetch_add(&P.q->finished, (uint64_t)unused - s_cphant[wv], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      s_cphant[wv] = unused;
+    }
+  }
+  b1 = __shfl(b1, leader);
+  b2 = __shfl(b2, leader);
+  t1 = __shfl(t1, leader);
+  return rank < t1 ? b1 + rank : b2 + (rank - t1);
+}
+
+// Reserve consecutive entries of a counter for the calling wave's active
+// lanes (one atomic per wave); returns this lane's index.
 __device__ __forceinline__ uint64_t wave_append(uint64_t* tail) {
   const uint64_t m = __ballot(1);
   const int leader = __ffsll((unsigned long long)m) - 1;
@@ -71,6 +135,11 @@ __device__ __forceinline__ void write_record(const KParams& P, const Ray& R, int
   Q.s[i] = R.s;
   Q.t[i] = R.y[6];
   Q.h[i] = R.h;
+  const int t = (int)threadIdx.x;
+  Q.as_re[i] = s_as_re[t];
+  Q.as_im[i] = s_as_im[t];
+  Q.ap_re[i] = s_ap_re[t];
+  Q.ap_im[i] = s_ap_im[t];
   Q.n_acc[i] = R.n_acc;
   Q.n_rej[i] = R.n_rej;
   Q.n_ev[i] = R.n_ev;
@@ -96,6 +165,12 @@ __device__ __forceinline__ void load_ray(const KParams& P, int32_t slot, Ray& R,
   R.region = Q.region[slot];
   R.side = Q.side[slot];
   R.n_acc = R.n_rej = R.n_ev = 0;
+  const int t = (int)threadIdx.x;
+  s_as_re[t] = Q.as_re[slot];
+  s_as_im[t] = Q.as_im[slot];
+  s_ap_re[t] = Q.ap_re[slot];
+  s_ap_im[t] = Q.ap_im[slot];
+  s_key[t] = Q.key[slot];
   set_direction<MODEL, FIELD>(P, R, Q.ux[slot], Q.uy[slot], Q.uz[slot]);
   C.max(S_MAXGEN, (unsigned long long)R.gen);
 }
@@ -143,9 +218,9 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
   const bool tir = fresnel(n1, n2, ci, rt, ct);
 
   const Pool& Q = P.pool;
-  const int i = R.slot;
-  const double as_re = Q.as_re[i], as_im = Q.as_im[i];
-  const double ap_re = Q.ap_re[i], ap_im = Q.ap_im[i];
+  const int tl = (int)threadIdx.x;
+  const double as_re = s_as_re[tl], as_im = s_as_im[tl];
+  const double ap_re = s_ap_re[tl], ap_im = s_ap_im[tl];
   if (!tir) {
     if (R.gen + 1 < P.max_gen) {
       const double cs_re = as_re * rt[4] - as_im * rt[5];
@@ -157,13 +232,15 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
         C.bump(S_SUPP_AMP);
       } else {
         C.bump(S_SPAWNED);
-        const uint64_t c = wave_append(&P.q->tail);
+        const uint64_t c = wave_slot(P, (int)threadIdx.x / 64);
         if (c >= (uint64_t)P.capacity) {
           C.bump(S_FIN);  // no record slot: reported via stats.needed
+          __hip_atomic_fetch_add(&P.q->dropped, (uint64_t)1, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
         } else {
           const double eta = n1 / n2;
           const double f = eta * ci - ct;
-          const uint64_t key = Q.key[i];
+          const uint64_t key = s_key[tl];
           Q.x[c] = R.y[0];
           Q.y[c] = R.y[1];
           Q.z[c] = R.y[2];
@@ -218,10 +295,10 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
   const double rs_im = as_re * rt[1] + as_im * rt[0];
   const double rp_re = ap_re * rt[2] - ap_im * rt[3];
   const double rp_im = ap_re * rt[3] + ap_im * rt[2];
-  Q.as_re[i] = rs_re;
-  Q.as_im[i] = rs_im;
-  Q.ap_re[i] = rp_re;
-  Q.ap_im[i] = rp_im;
+  s_as_re[tl] = rs_re;
+  s_as_im[tl] = rs_im;
+  s_ap_re[tl] = rp_re;
+  s_ap_im[tl] = rp_im;
   const double c2 = 2.0 * ci;
   set_direction<MODEL, FIELD>(P, R, fma(c2, nin[0], u[0]), fma(c2, nin[1], u[1]),
                               fma(c2, nin[2], u[2]));
@@ -281,6 +358,10 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
   if (lane == 0) {
     s_rh[wv] = 0;
     s_rt[wv] = 0;
+    s_cnext[wv] = 0;
+    s_cend[wv] = 0;
+    s_cphant[wv] = 0;
+    s_cmode[wv] = P.chunk > 0 ? 1u : 0u;
   }
   bool prim_done = false;  // wave-uniform: no primaries left to claim
   int32_t ticket = -1;     // overflow ticket: -1 none, -2 exhausted, else entry
@@ -381,12 +462,16 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
       }
     }
     if (__ballot(R.slot >= 0) == 0) {
-      // nothing to step: publish finished counts, stop once no work can come
+      // nothing to step: publish finished counts and the unused slots of
+      // the wave's chunk, stop once no work can come
       if (lane == 0) {
         const unsigned long long f = C.c[S_FIN];
-        if (f) {
+        const uint32_t unused = (uint32_t)(s_cend[wv] - s_cnext[wv]);
+        const unsigned long long d = f + (unused - s_cphant[wv]);  // unused >= s_cphant
+        if (d) {
           C.c[S_FIN] = 0;
-          __hip_atomic_fetch_add(&P.q->finished, (uint64_t)f, __ATOMIC_RELAXED,
+          s_cphant[wv] = unused;
+          __hip_atomic_fetch_add(&P.q->finished, (uint64_t)d, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);
         }
       }
@@ -591,12 +676,66 @@ __global__ void reset_kernel(KParams P) {
     P.q->gq_head = 0;
     P.q->gq_tail = 0;
     P.q->finished = 0;
+    P.q->dropped = 0;
+    P.q->fix_a = 0;
+    P.q->fix_b = 0;
   }
 }
 
-// Records the launch needed = primaries + every secondary reserved.
+// Slot compaction after a launch with chunked reservations: the records
+// number N = records + invalid primaries; every empty slot below N (a hole
+// left by a chunk) receives a record from a slot at or above N.  The two
+// lists live in the overflow queue, which is free after the trace: holes at
+// gq[0, ...), records to move at gq[capacity/2, ...); both are at most
+// P.reserve long.
+__global__ void compact_scan_kernel(KParams P) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t tail = P.q->tail;
+  const int64_t M = tail < (uint64_t)P.capacity ? (int64_t)tail : P.capacity;
+  const int64_t N = P.stats->records + P.stats->invalid;
+  const int32_t st = s < M ? P.pool.status[s] : RT_ST_EMPTY;
+  const bool hole = s < M && s < N && st == RT_ST_EMPTY;
+  const bool mover = s < M && s >= N && st != RT_ST_EMPTY;
+  const uint64_t half = (uint64_t)P.capacity / 2;
+  if (__ballot(hole)) {
+    if (hole) {
+      const uint64_t e = wave_append(&P.q->fix_a);
+      if (e < half) P.gq[e] = (int32_t)s;
+    }
+  }
+  if (__ballot(mover)) {
+    if (mover) {
+      const uint64_t e = wave_append(&P.q->fix_b);
+      if (e < half) P.gq[half + e] = (int32_t)s;
+    }
+  }
+}
+
+__global__ void compact_move_kernel(KParams P) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t half = P.capacity / 2;
+  if (i >= (int64_t)P.q->fix_a || i >= (int64_t)P.q->fix_b || i >= half) return;
+  const int32_t d = P.gq[i], s = P.gq[half + i];
+  const Pool& Q = P.pool;
+  double* const f64[] = {Q.x, Q.y, Q.z, Q.ux, Q.uy, Q.uz, Q.s, Q.t,
+                         Q.as_re, Q.as_im, Q.ap_re, Q.ap_im, Q.h};
+#pragma unroll
+  for (int f = 0; f < 13; ++f) f64[f][d] = f64[f][s];
+  Q.key[d] = Q.key[s];
+  Q.parent[d] = Q.parent[s];
+  int32_t* const i32[] = {Q.gen, Q.status, Q.n_acc, Q.n_rej, Q.n_ev, Q.region};
+#pragma unroll
+  for (int f = 0; f < 6; ++f) i32[f][d] = i32[f][s];
+  Q.side[d] = Q.side[s];
+  Q.status[s] = RT_ST_EMPTY;
+}
+
+// Records the launch needs: primaries + every secondary cast; when some
+// found no slot, plus the slots chunks may leave unused, so that a relaunch
+// with that capacity holds them all.
 __global__ void finish_kernel(KParams P) {
-  if (threadIdx.x == 0) P.stats->needed = (int64_t)P.q->tail;
+  if (threadIdx.x == 0)
+    P.stats->needed = P.n_primary + P.stats->spawned + (P.q->dropped ? (int64_t)P.reserve : 0);
 }
 
 // FP32 grid -> float4 nodes (n, Dx, Dy, Dz): D is the central difference of
@@ -924,6 +1063,14 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   int64_t nblk = (int64_t)g_dev.n_cu * bpc;
   const int64_t by_rays = std::max<int64_t>(1, (dirs->n + block - 1) / block);
   nblk = std::max<int64_t>(1, std::min(nblk, by_rays));
+  // chunked secondary slots when the capacity leaves room for the chunks'
+  // unused rests (at most one chunk per wave) and for the compaction lists
+  const int64_t waves = nblk * (block / 64);
+  const int64_t reserve = waves * kChunk;
+  const bool chunked = L->max_generations > 1 && out->capacity >= dirs->n + 4 * reserve;
+  P.chunk = chunked ? (uint32_t)kChunk : 0u;
+  P.chunk_limit = chunked ? (uint64_t)(out->capacity - reserve) : 0;
+  P.reserve = chunked ? (uint64_t)reserve : 0;
 
   if (tuning && tuning->ev_trace_begin)
     HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(tuning->ev_trace_begin), s));
@@ -937,6 +1084,14 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   HIP_TRY(e);
   if (tuning && tuning->ev_trace_end)
     HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(tuning->ev_trace_end), s));
+  if (chunked) {
+    hipLaunchKernelGGL(compact_scan_kernel, dim3((unsigned)((out->capacity + 255) / 256)),
+                       dim3(256), 0, s, P);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(compact_move_kernel, dim3((unsigned)((reserve + 255) / 256)), dim3(256), 0,
+                       s, P);
+    HIP_TRY(hipGetLastError());
+  }
   hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, P);
   HIP_TRY(hipGetLastError());
   return RT_OK;

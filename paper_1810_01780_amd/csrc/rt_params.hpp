@@ -49,10 +49,13 @@ struct Pool {
 
 struct QueueCounters {
   uint64_t head;      // next primary to hand out
-  uint64_t tail;      // record slots reserved so far (primaries + spawned)
+  uint64_t tail;      // record slots reserved so far (primaries, secondaries, chunks)
   uint64_t gq_head;   // next overflow-queue ticket
   uint64_t gq_tail;   // overflow-queue entries reserved
-  uint64_t finished;  // rays finished (added lazily, per wave)
+  uint64_t finished;  // rays finished plus reserved slots idle waves will not use
+  uint64_t dropped;   // secondaries that found no slot below capacity
+  uint64_t fix_a;     // slot compaction: holes below the record count
+  uint64_t fix_b;     // slot compaction: records at or above it
 };
 
 struct KParams {
@@ -66,6 +69,9 @@ struct KParams {
   const void* nodes;
   int32_t gnx, gny, gnz, refill;
   uint32_t local_limit;  // children a wave keeps before publishing globally
+  uint32_t chunk;        // secondary slots a wave reserves at once (0: one per child)
+  uint64_t chunk_limit;  // waves stop taking chunks once they reach this slot
+  uint64_t reserve;      // slots chunks can leave unused (waves x chunk)
   double gorg[3], ginv[3], gmax[3], ghalf[3];
   // limits
   double tol, inv_tol, h_min, h_max, h_init, s_max, t_max, amp_min;

@@ -196,6 +196,33 @@ def test_capacity_overflow_reported(gpu):
     assert st2["records"] == st["needed"]
 
 
+def test_chunked_slots_dense_and_overflow(gpu):
+    """Secondary record slots are reserved in chunks of 64 per wave when the
+    capacity leaves room for them (1,024 rays: 16 waves, reserve 1,024
+    slots): the records stay dense; a capacity short of the records needed
+    is reported, with a needed count that a relaunch then holds."""
+    sc = W.two_layer(rays_per_source=16)
+    _announce("chunked-slots", sc)
+    big, bst = gpu.trace(sc, capacity=16384)
+    n_rec = bst["records"] + bst["invalid"]
+    assert n_rec == sc.n_rays + bst["spawned"] == bst["needed"]
+    assert len(big["status"]) == n_rec and np.all(big["status"] != gpu.RT_ST_EMPTY)
+    assert len(np.unique(big["key"])) == n_rec
+    short = sc.n_rays + 4 * 1024 + 64   # chunked, and below the records needed
+    assert short < n_rec
+    got, st = gpu.trace(sc, capacity=short, check=False)
+    assert st["needed"] > short and st["records"] + st["invalid"] <= short
+    assert np.all(got["status"] != gpu.RT_ST_EMPTY)
+    with pytest.raises(gpu.RTError) as e:
+        gpu.trace(sc, capacity=short)
+    assert e.value.status == gpu.RT_ERR_CAPACITY
+    again, st2 = gpu.trace(sc, capacity=st["needed"])
+    assert st2["records"] + st2["invalid"] == n_rec
+    a, b = sort_by_key(big), sort_by_key(again)
+    for f in ("key", "x", "z", "s", "t", "as_re", "ap_im", "n_acc", "status", "parent"):
+        assert np.array_equal(a[f], b[f]), f
+
+
 @pytest.mark.parametrize("block,refill", [(64, 1), (128, 64), (256, 16), (192, 33)])
 def test_schedule_independence(gpu, block, refill):
     """Results do not depend on block size or refill threshold."""
