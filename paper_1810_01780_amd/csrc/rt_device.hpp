@@ -127,6 +127,14 @@ __device__ __forceinline__ void strat_field(const Medium& M, double z, double& n
   gz = fma(M.dn_inv_z0, e, M.b);
 }
 
+// Same at the step's start z, where E = exp(-z/z0) is known.
+__device__ __forceinline__ void strat_field_at(const Medium& M, double z, double E, double& n,
+                                               double& gz) {
+  const double e = M.dn != 0.0 ? E : 0.0;
+  n = fma(M.b, z, M.a) - M.dn * e;
+  gz = fma(M.dn_inv_z0, e, M.b);
+}
+
 // Same at a stage point z = z0 + dz of a step starting at z0, where
 // E0 = exp(-z0/z0_medium): exp(-z/z0) = E0 exp(-dz/z0), and the second factor
 // is a short polynomial because a step moves at most a fraction of z0.
@@ -215,7 +223,8 @@ __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], 
       if (st == 4) { dz = stage_inc<4>(h, kz); ws = stage_in<4>(y[5], h, kw); }
       if (st == 5) { dz = stage_inc<5>(h, kz); ws = stage_in<5>(y[5], h, kw); }
       double n, gz;
-      strat_field_rel(M, y[2], dz, E0, n, gz);
+      if (st == 0) strat_field_at(M, y[2], E0, n, gz);
+      else strat_field_rel(M, y[2], dz, E0, n, gz);
       kz[st] = ws;
       kw[st] = gz * rcp_nr(n);
       if (st == 0) tsum = kB1 * n;
@@ -246,7 +255,8 @@ __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], 
       if (st == 4) { dz = stage_inc<4>(h, kz); ps = stage_in<4>(y[5], h, kp); }
       if (st == 5) { dz = stage_inc<5>(h, kz); ps = stage_in<5>(y[5], h, kp); }
       double n, gz;
-      strat_field_rel(M, y[2], dz, E0, n, gz);
+      if (st == 0) strat_field_at(M, y[2], E0, n, gz);
+      else strat_field_rel(M, y[2], dz, E0, n, gz);
       const double ip = rsqrt_nr(fma(ps, ps, pxy2));
       kx[st] = px * ip;
       ky[st] = py * ip;
