@@ -53,6 +53,31 @@ FLOP_3D_PER_ANOMALY = 6 * 49
 # of node data per trial step.
 BYTES_PER_TRIAL_GRID = 768
 
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, per dispatch), each divided by what the same
+# counter reads per byte of a plain 1 GiB device copy (--workload copy).
+# Valid only for the kernel sources with the listed SHA-256 digest; after a
+# change to them the traffic is reported as null until measured again.
+TRAFFIC = {}  # workload -> (fetch bytes, write bytes, digest)
+TRACE_SOURCES = ("rt_kernels.hip", "rt_device.hpp", "rt_params.hpp")
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRACE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1810_01780_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    t = TRAFFIC.get(workload)
+    if t is None or t[2] != kernel_digest():
+        return None
+    return t[0] + t[1]
+
+
 PEAK_FP64_VECTOR_TFLOPS = 78.6   # MI355X: 256 CU x 128 FLOP/clk x 2.4 GHz
 PEAK_HBM_GBS = 8000.0            # MI355X HBM3E
 
@@ -353,6 +378,30 @@ def bench_surrogate(args, log):
     print(json.dumps(out), flush=True)
 
 
+def bench_copy(args, log):
+    """A plain device-to-device copy of 1 GiB per step: the calibration of the
+    HBM byte counters (reads 2^30 bytes, writes 2^30 bytes)."""
+    import torch
+    n = 1 << 27
+    x = torch.rand(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    log(f"copy: {dt * 1e3:.3f} ms per GiB copied")
+    out = {"metric": "device copy bandwidth (read + write)", "value": 2 * n * 8 / dt / 1e9,
+           "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "copy", "bytes_read": n * 8, "bytes_written": n * 8}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -360,7 +409,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="twolayer",
                     choices=["twolayer", "grid256", "curved", "field3d", "fan1024", "solve",
-                             "surrogate"])
+                             "surrogate", "copy"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -370,8 +419,8 @@ def main():
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this tracer runs on one GPU; a multi-GPU run is not part of this "
-              "build (rays shard trivially by root index; see the design notes)", file=sys.stderr)
+        print("bench.py: one GPU per process; rays shard across GPUs by root index, which "
+              "is left to the caller, so only --gpus 1 is measured", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -379,6 +428,8 @@ def main():
 
     assert torch.cuda.is_available(), "no GPU"
     torch.cuda.set_device(0)
+    if args.workload == "copy":
+        return bench_copy(args, log)
     if args.workload == "solve":
         return bench_solve(args, log)
     if args.workload == "surrogate":
@@ -423,12 +474,12 @@ def main():
     if args.workload == "grid256":
         achieved = trials * BYTES_PER_TRIAL_GRID / kern_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+                "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(args.workload)}
     else:
         achieved = trial_flops(scene, rec, trials) / kern_s / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
-                "traffic": None}
+                "traffic": measured_traffic(args.workload)}
     roof["kernel"] = "trace_kernel"
     roof["kernel_ms"] = kern_s * 1e3
 

@@ -1,0 +1,52 @@
+"""Host-side logic of bench.py (no GPU): the FLOP model per trial step, the
+traffic figure's validity rule, and the one-GPU contract."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+from paper_1810_01780_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_flop_model_per_trial():
+    # stratified kernel, two planes: the 540 FLOP breakdown
+    sc = W.two_layer(rays_per_source=1)
+    assert not bench.is_general(sc)
+    assert [bench.flop_per_trial(sc, r) for r in range(3)] == [540, 540, 540]
+    # a sphere and a paraboloid instead of a plane change the boundary term
+    cv = W.curved(rays_per_source=1)
+    assert bench.flop_per_trial(cv, 1) == 540 - 12 + 6 + 17 + 8
+    # general kernel: 812 + 294 per anomaly of the ray's region + boundaries
+    f3 = W.field3d(rays_per_source=1)
+    assert bench.is_general(f3)
+    assert bench.flop_per_trial(f3, 0) == 806 + 6
+    assert bench.flop_per_trial(f3, 1) == 806 + 2 * 294 + 6
+
+
+def test_trial_flops_weights_records_by_region():
+    import numpy as np
+    sc = W.field3d(rays_per_source=1)
+    rec = {"n_acc": np.array([10, 20]), "n_rej": np.array([0, 5]), "region": np.array([0, 1])}
+    want = 10 * bench.flop_per_trial(sc, 0) + 25 * bench.flop_per_trial(sc, 1)
+    assert bench.trial_flops(sc, rec, 35) == pytest.approx(want)
+    # event-search trials (beyond the records' own counts) at the mean rate
+    assert bench.trial_flops(sc, rec, 70) == pytest.approx(2 * want)
+
+
+def test_traffic_only_for_the_measured_sources(monkeypatch):
+    d = bench.kernel_digest()
+    monkeypatch.setattr(bench, "TRAFFIC", {"twolayer": (100.0, 50.0, d),
+                                           "grid256": (1.0, 2.0, "0" * 64)})
+    assert bench.measured_traffic("twolayer") == 150.0
+    assert bench.measured_traffic("grid256") is None   # sources changed since
+    assert bench.measured_traffic("curved") is None    # never measured
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
