@@ -58,7 +58,10 @@ BYTES_PER_TRIAL_GRID = 768
 # counter reads per byte of a plain 1 GiB device copy (--workload copy).
 # Valid only for the kernel sources with the listed SHA-256 digest; after a
 # change to them the traffic is reported as null until measured again.
-TRAFFIC = {}  # workload -> (fetch bytes, write bytes, digest)
+TRAFFIC = {  # workload -> (fetch bytes, write bytes, digest)
+    "twolayer": (1.2032e+09, 5.2546e+09,
+                 "e4b9a8d6428f0c6183006eb57f15a1ff49f1fc03428bf7e3b0a47f6c32d357b5"),
+}
 TRACE_SOURCES = ("rt_kernels.hip", "rt_device.hpp", "rt_params.hpp")
 
 
