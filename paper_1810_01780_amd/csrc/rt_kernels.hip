@@ -52,6 +52,10 @@ struct WaveQueue {
 // the record is written.
 __shared__ double s_as_re[256], s_as_im[256], s_ap_re[256], s_ap_im[256];
 __shared__ uint64_t s_key[256];
+// Accepted and rejected steps of the rays each lane has finished: the
+// launch totals are the sums of the records' step counts, so the step loop
+// keeps no counters of its own.
+__shared__ unsigned long long s_nacc[256], s_nrej[256];
 
 // Record slots of secondaries.  A wave reserves slots in chunks of P.chunk
 // consecutive indices (one atomic per chunk rather than per spawning
@@ -136,6 +140,8 @@ __device__ __forceinline__ void write_record(const KParams& P, const Ray& R, int
   Q.t[i] = R.y[6];
   Q.h[i] = R.h;
   const int t = (int)threadIdx.x;
+  s_nacc[t] += (unsigned long long)R.n_acc;
+  s_nrej[t] += (unsigned long long)R.n_rej;
   Q.as_re[i] = s_as_re[t];
   Q.as_im[i] = s_as_im[t];
   Q.ap_re[i] = s_ap_re[t];
@@ -327,6 +333,8 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
   __shared__ int32_t s_k[256], s_meta[256];
   __syncthreads();
 
+  s_nacc[tid] = 0;
+  s_nrej[tid] = 0;
   Ray R;
   R.slot = -1;
   R.s = R.h = 0.0;
@@ -517,11 +525,9 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
         fin = RT_ST_NONFINITE;
       } else if (!accept) {
         R.n_rej++;
-        C.bump(S_REJ);
         R.h = hn;
       } else {
         R.n_acc++;
-        C.bump(S_ACC);
         if (err > 1.0) C.bump(S_FORCED);
         if constexpr (MODEL == RT_MODEL_PAPER) {
           const double il = rsqrt_nr(fma(y5[3], y5[3], fma(y5[4], y5[4], y5[5] * y5[5])));
@@ -642,6 +648,18 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
   }
 
   // ---- per-wave statistics into the launch's rt_stats ----
+  {
+    unsigned long long a = s_nacc[tid], r = s_nrej[tid];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o);
+      r += __shfl_xor(r, o);
+    }
+    if (lane == 0) {
+      C.c[S_ACC] += a;
+      C.c[S_REJ] += r;
+    }
+  }
   if (lane == 0) {
     unsigned long long* s64 = reinterpret_cast<unsigned long long*>(P.stats);
     for (int i = 0; i < S_FIN; ++i) {
