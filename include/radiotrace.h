@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define RT_ABI_VERSION 3
+#define RT_ABI_VERSION 4
 #define RT_MAX_REGIONS 8
 #define RT_MAX_PLANES 16
 #define RT_MAX_ANOMALIES 8
@@ -53,7 +53,9 @@ typedef enum {
   RT_ERR_INVALID_ARG = 1, /* bad descriptor, or rays flagged RT_ST_INVALID */
   RT_ERR_CAPACITY = 2,    /* more records than out->capacity; see stats.needed */
   RT_ERR_DEVICE = 3,      /* a HIP call failed; message in rt_last_error() */
-  RT_ERR_UNSUPPORTED = 4  /* e.g. more than RT_MAX_GENERATIONS generations */
+  RT_ERR_UNSUPPORTED = 4, /* e.g. more than RT_MAX_GENERATIONS generations */
+  RT_INTERRUPTED = 5      /* the launch reached max_steps_per_launch; relaunch
+                             with resume = 1 to continue */
 } rt_status;
 
 enum { RT_MODEL_PAPER = 0, RT_MODEL_EXACT = 1 };
@@ -62,6 +64,8 @@ enum { RT_SHAPE_PLANE = 0, RT_SHAPE_SPHERE = 1, RT_SHAPE_PARABOLOID = 2 };
 
 /* Per-record status (out->status). */
 enum {
+  RT_ST_PARKED = -2,   /* internal: a ray stopped mid-flight by an
+                          interrupted launch, resumed by the next one */
   RT_ST_QUEUED = -1,   /* internal: slot holds a ray waiting to be traced */
   RT_ST_EMPTY = 0,     /* internal: slot not written */
   RT_ST_PATH = 1,      /* reached the path-length limit s_max */
@@ -175,6 +179,16 @@ typedef struct {
   int32_t max_generations; /* 1 = primaries only ... 4 */
   int32_t model;           /* RT_MODEL_PAPER or RT_MODEL_EXACT */
   int64_t max_steps_per_ray; /* accepted + rejected trials per ray, >= 1 */
+  int64_t max_steps_per_launch; /* 0 = off; else the launch stops after about
+                                   this many trial steps (the waves check
+                                   every 64 iterations), parks the rays in
+                                   flight in their record slots and reports
+                                   RT_INTERRUPTED */
+  int32_t resume; /* 1: continue an interrupted launch: same descriptors,
+                     outputs and workspace, none of them changed since; the
+                     records and statistics then accumulate as if the launches
+                     were one.  Results equal those of an uninterrupted launch
+                     bit for bit. */
 } rt_step_limits;
 
 /* Launch statistics, accumulated on the device into out->stats. */
@@ -199,6 +213,7 @@ typedef struct {
   int64_t refills;    /* wave refill operations of the scheduler */
   int64_t sched_errors; /* scheduler waits that timed out (must stay 0) */
   int64_t spilled;    /* secondaries handed to other waves (global queue) */
+  int64_t interrupted; /* 1: this launch stopped at max_steps_per_launch */
 } rt_stats;
 
 /* Caller-owned output records, one per ray (primary or secondary), in no
@@ -279,8 +294,11 @@ rt_status raytrace_launch(const rt_field* field,
  * the scheduler reported an error, RT_ERR_INVALID_ARG when input rays were
  * invalid, RT_ERR_CAPACITY when stats.needed exceeds
  * capacity (records of the slots below capacity are still valid; relaunch
- * with a capacity of at least stats.needed), else RT_OK.  Rays that ended
- * RT_ST_NONFINITE are per-ray results and do not fail the launch. */
+ * with a capacity of at least stats.needed), RT_INTERRUPTED when the launch
+ * stopped at its step budget (the slots then hold finished records, parked
+ * and queued rays and unused slots; continue with resume = 1), else RT_OK.
+ * Rays that ended RT_ST_NONFINITE are per-ray results and do not fail the
+ * launch. */
 rt_status rt_collect(const rt_stats* host_stats, int64_t capacity);
 
 /* Message for the last non-OK status returned on the calling thread. */

@@ -22,8 +22,9 @@ from . import workloads as W
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libradiotrace.so")
 
-RT_OK, RT_ERR_INVALID_ARG, RT_ERR_CAPACITY, RT_ERR_DEVICE, RT_ERR_UNSUPPORTED = range(5)
-RT_ST_QUEUED, RT_ST_EMPTY = -1, 0
+RT_OK, RT_ERR_INVALID_ARG, RT_ERR_CAPACITY, RT_ERR_DEVICE, RT_ERR_UNSUPPORTED, \
+    RT_INTERRUPTED = range(6)
+RT_ST_PARKED, RT_ST_QUEUED, RT_ST_EMPTY = -2, -1, 0
 (RT_ST_PATH, RT_ST_BOX, RT_ST_TIME, RT_ST_AMP, RT_ST_ABSORB, RT_ST_STEPCAP,
  RT_ST_NONFINITE, RT_ST_INVALID) = range(1, 9)
 RT_MAX_REGIONS, RT_MAX_PLANES, RT_MAX_GENERATIONS, RT_MAX_ANOMALIES = 8, 16, 4, 8
@@ -74,12 +75,13 @@ class rt_step_limits(C.Structure):
     _fields_ = [("h_min", C.c_double), ("h_max", C.c_double), ("h_init", C.c_double),
                 ("s_max", C.c_double), ("t_max", C.c_double), ("amp_min", C.c_double),
                 ("max_generations", C.c_int32), ("model", C.c_int32),
-                ("max_steps_per_ray", C.c_int64)]
+                ("max_steps_per_ray", C.c_int64), ("max_steps_per_launch", C.c_int64),
+                ("resume", C.c_int32)]
 
 
 STAT_FIELDS = ["accepted", "rejected", "relocation", "forced", "events", "spawned",
                "suppressed_gen", "suppressed_amp", "records", "needed", "nonfinite",
-               "max_gen", "invalid", "refills", "sched_errors", "spilled"]
+               "max_gen", "invalid", "refills", "sched_errors", "spilled", "interrupted"]
 
 
 class rt_stats(C.Structure):
@@ -340,7 +342,7 @@ class HostDescriptors:
         lim = scene.limits
         self.limits = rt_step_limits(lim.h_min, lim.h_max, lim.h_init, lim.s_max, lim.t_max,
                                      lim.amp_min, lim.max_generations, lim.model,
-                                     lim.max_steps_per_ray)
+                                     lim.max_steps_per_ray, lim.max_steps_per_launch, 0)
         self.tol = lim.tol
         self.sources = rt_sources(None, int(scene.sources.shape[0]))
         self.dirs = rt_directions(None, None, int(scene.n_rays))
@@ -382,14 +384,20 @@ class DeviceScene:
         self.ws_bytes = rt_workspace_bytes(self.desc.field, self.capacity)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
 
-    def launch(self, stream=None, tuning: Optional[rt_tuning] = None) -> None:
-        """Enqueue one full trace on the stream (torch's current stream by default)."""
+    def launch(self, stream=None, tuning: Optional[rt_tuning] = None, resume: bool = False) -> None:
+        """Enqueue one trace on the stream (torch's current stream by default);
+        resume=True continues a launch that stopped at its step budget."""
         torch = self.torch
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
-        st = raytrace_launch(self.desc.field, self.desc.bnd, self.desc.sources, self.desc.dirs,
-                             self.desc.tol, self.desc.limits, self.out, self.workspace.data_ptr(),
-                             self.ws_bytes, stream.cuda_stream, tuning)
+        self.desc.limits.resume = 1 if resume else 0
+        try:
+            st = raytrace_launch(self.desc.field, self.desc.bnd, self.desc.sources,
+                                 self.desc.dirs, self.desc.tol, self.desc.limits, self.out,
+                                 self.workspace.data_ptr(), self.ws_bytes, stream.cuda_stream,
+                                 tuning)
+        finally:
+            self.desc.limits.resume = 0
         if st != RT_OK:
             raise RTError(st, rt_last_error())
 

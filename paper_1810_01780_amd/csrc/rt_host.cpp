@@ -137,6 +137,9 @@ rt_status validate(const rt_field* field, const rt_boundaries* bnd, const rt_sou
   if (L->model != RT_MODEL_PAPER && L->model != RT_MODEL_EXACT)
     FAIL(RT_ERR_INVALID_ARG, "unknown model %d", L->model);
   if (L->max_steps_per_ray < 1) FAIL(RT_ERR_INVALID_ARG, "max_steps_per_ray must be >= 1");
+  if (L->max_steps_per_launch < 0)
+    FAIL(RT_ERR_INVALID_ARG, "max_steps_per_launch must be >= 0 (0 = no limit)");
+  if (L->resume != 0 && L->resume != 1) FAIL(RT_ERR_INVALID_ARG, "resume must be 0 or 1");
   return RT_OK;
 }
 
@@ -204,6 +207,10 @@ rt_status rt_collect(const rt_stats* s, int64_t capacity) {
                        (long long)s->needed);
     return RT_ERR_CAPACITY;
   }
+  if (s->interrupted) {
+    rt::set_last_error("step budget reached; relaunch with resume = 1 to continue");
+    return RT_INTERRUPTED;
+  }
   return RT_OK;
 }
 
@@ -215,6 +222,10 @@ rt_status rt_solve_validate(const rt_field* field, const rt_boundaries* bnd, dou
   }
   // shots have no sources, directions, path limit, amplitude cut or
   // secondaries: check the rest as for a trace
+  if (L->max_steps_per_launch != 0 || L->resume != 0) {
+    rt::set_last_error("solves take no step budget per launch and no resume");
+    return RT_ERR_INVALID_ARG;
+  }
   rt_step_limits lim = *L;
   lim.s_max = 1.0;
   lim.amp_min = 0.0;

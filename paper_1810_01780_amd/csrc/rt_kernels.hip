@@ -170,15 +170,54 @@ __device__ __forceinline__ void load_ray(const KParams& P, int32_t slot, Ray& R,
   R.gen = Q.gen[slot];
   R.region = Q.region[slot];
   R.side = Q.side[slot];
-  R.n_acc = R.n_rej = R.n_ev = 0;
+  R.n_acc = Q.n_acc[slot];
+  R.n_rej = Q.n_rej[slot];
+  R.n_ev = Q.n_ev[slot];
   const int t = (int)threadIdx.x;
   s_as_re[t] = Q.as_re[slot];
   s_as_im[t] = Q.as_im[slot];
   s_ap_re[t] = Q.ap_re[slot];
   s_ap_im[t] = Q.ap_im[slot];
   s_key[t] = Q.key[slot];
-  set_direction<MODEL, FIELD>(P, R, Q.ux[slot], Q.uy[slot], Q.uz[slot]);
+  if (Q.status[slot] == RT_ST_PARKED) {  // the exact direction state it had
+    R.y[3] = Q.ux[slot];
+    R.y[4] = Q.uy[slot];
+    R.y[5] = Q.uz[slot];
+  } else {
+    set_direction<MODEL, FIELD>(P, R, Q.ux[slot], Q.uy[slot], Q.uz[slot]);
+  }
   C.max(S_MAXGEN, (unsigned long long)R.gen);
+}
+
+// Park a ray in flight when the launch's step budget is reached: its whole
+// state goes into its record slot (the direction state as it is, not
+// normalised) with status RT_ST_PARKED, and a resumed launch continues it
+// bit for bit.  A ray that was locating a crossing redoes that step: its
+// state is still the step's start, and the accepted step is uncounted.
+__device__ __forceinline__ void park_ray(const KParams& P, Ray& R, int mode) {
+  const Pool& Q = P.pool;
+  const int i = R.slot;
+  const int t = (int)threadIdx.x;
+  if (mode == 1) R.n_acc--;
+  Q.x[i] = R.y[0];
+  Q.y[i] = R.y[1];
+  Q.z[i] = R.y[2];
+  Q.ux[i] = R.y[3];
+  Q.uy[i] = R.y[4];
+  Q.uz[i] = R.y[5];
+  Q.s[i] = R.s;
+  Q.t[i] = R.y[6];
+  Q.h[i] = R.h;
+  Q.as_re[i] = s_as_re[t];
+  Q.as_im[i] = s_as_im[t];
+  Q.ap_re[i] = s_ap_re[t];
+  Q.ap_im[i] = s_ap_im[t];
+  Q.n_acc[i] = R.n_acc;
+  Q.n_rej[i] = R.n_rej;
+  Q.n_ev[i] = R.n_ev;
+  Q.region[i] = R.region;
+  Q.side[i] = R.side;
+  Q.status[i] = RT_ST_PARKED;
 }
 
 // Checks made before every normal trial step; returns a final status or 0.
@@ -313,6 +352,21 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
   return 0;
 }
 
+// Publish a wave's finished rays and the unused rest of its slot chunk
+// (lane 0; the chunk count replaces what was published before).
+__device__ __forceinline__ void publish_idle(const KParams& P, const Counters& C, int wv) {
+  if ((int)__lane_id() != 0) return;
+  const unsigned long long f = C.c[S_FIN];
+  const uint32_t unused = (uint32_t)(s_cend[wv] - s_cnext[wv]);
+  const unsigned long long d = f + (unused - s_cphant[wv]);  // unused >= s_cphant
+  if (d) {
+    C.c[S_FIN] = 0;
+    s_cphant[wv] = unused;
+    __hip_atomic_fetch_add(&P.q->finished, (uint64_t)d, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Persistent trace kernel.
 template <int MODEL, int FIELD>
@@ -372,6 +426,15 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
     s_cmode[wv] = P.chunk > 0 ? 1u : 0u;
   }
   bool prim_done = false;  // wave-uniform: no primaries left to claim
+  // Step budget of the launch, per wave in LDS (no registers in the loop):
+  // trial steps not yet added to q->steps, iterations, and the stop flag.
+  __shared__ unsigned long long s_bsteps[4];
+  __shared__ uint32_t s_biter[4], s_bstop[4];
+  if (lane == 0) {
+    s_bsteps[wv] = 0;
+    s_biter[wv] = 0;
+    s_bstop[wv] = 0;
+  }
   int32_t ticket = -1;     // overflow ticket: -1 none, -2 exhausted, else entry
   uint32_t sleeps = 0;
   const Pool& Q = P.pool;
@@ -387,6 +450,8 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
         R.slot = -1;
       }
     }
+    // ---- step budget reached: leave (the rays in flight are parked below) ----
+    if (P.budget > 0 && s_bstop[wv]) break;
     // ---- refill idle lanes ----
     const bool lane_idle = R.slot < 0 && ticket == -1;
     const uint64_t idle = __ballot(lane_idle);
@@ -471,17 +536,13 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
     }
     if (__ballot(R.slot >= 0) == 0) {
       // nothing to step: publish finished counts and the unused slots of
-      // the wave's chunk, stop once no work can come
-      if (lane == 0) {
-        const unsigned long long f = C.c[S_FIN];
-        const uint32_t unused = (uint32_t)(s_cend[wv] - s_cnext[wv]);
-        const unsigned long long d = f + (unused - s_cphant[wv]);  // unused >= s_cphant
-        if (d) {
-          C.c[S_FIN] = 0;
-          s_cphant[wv] = unused;
-          __hip_atomic_fetch_add(&P.q->finished, (uint64_t)d, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT);
-        }
+      // the wave's chunk, stop once no work can come or the budget is spent
+      publish_idle(P, C, wv);
+      if (P.budget > 0) {
+        unsigned long long stop = 0;
+        if (lane == 0)
+          stop = __hip_atomic_load(&P.q->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__shfl(stop, 0)) break;
       }
       if (*WQ.head == *WQ.tail && prim_done) {
         if (__ballot(ticket == -2) == ~0ull) break;  // no work can reach this wave
@@ -501,6 +562,24 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
         __builtin_amdgcn_s_sleep(4);
       }
       continue;
+    }
+    if (P.budget > 0) {
+      const uint32_t busy = (uint32_t)__popcll(__ballot(R.slot >= 0));
+      if (lane == 0) {
+        s_bsteps[wv] += busy;
+        if ((++s_biter[wv] & 63u) == 0) {
+          const unsigned long long w = s_bsteps[wv];
+          const unsigned long long tot =
+              __hip_atomic_fetch_add(&P.q->steps, (uint64_t)w, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT) + w;
+          s_bsteps[wv] = 0;
+          if (tot >= (unsigned long long)P.budget) {
+            s_bstop[wv] = 1;
+            __hip_atomic_store(&P.q->stop, (uint64_t)1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+      }
     }
     if (R.slot < 0) continue;
 
@@ -647,6 +726,11 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
     }
   }
 
+  // A wave that stopped at the step budget parks its rays; it (and any
+  // other) publishes its finished count and unused chunk slots.
+  if (R.slot >= 0) park_ray(P, R, mode);
+  publish_idle(P, C, wv);
+
   // ---- per-wave statistics into the launch's rt_stats ----
   {
     unsigned long long a = s_nacc[tid], r = s_nrej[tid];
@@ -683,6 +767,12 @@ __global__ void __launch_bounds__(256) trace_grid_kernel(KParams P) {
   trace_body<MODEL, 1>(P);
 }
 
+// Record slots in use: [0, min(tail, capacity)).
+__device__ __forceinline__ int64_t used_slots(const KParams& P) {
+  const uint64_t tail = P.q->tail;
+  return tail < (uint64_t)P.capacity ? (int64_t)tail : P.capacity;
+}
+
 // Queue counters and statistics to their launch values.
 __global__ void reset_kernel(KParams P) {
   const int i = threadIdx.x;
@@ -697,20 +787,77 @@ __global__ void reset_kernel(KParams P) {
     P.q->dropped = 0;
     P.q->fix_a = 0;
     P.q->fix_b = 0;
+    P.q->steps = 0;
+    P.q->stop = 0;
+    P.q->holes = 0;
   }
 }
 
-// Slot compaction after a launch with chunked reservations: the records
-// number N = records + invalid primaries; every empty slot below N (a hole
-// left by a chunk) receives a record from a slot at or above N.  The two
-// lists live in the overflow queue, which is free after the trace: holes at
-// gq[0, ...), records to move at gq[capacity/2, ...); both are at most
-// P.reserve long.
-__global__ void compact_scan_kernel(KParams P) {
+// Resuming an interrupted launch: the queue counters and statistics carry
+// on; the overflow queue is rebuilt from the slots that hold rays still to
+// trace (parked rays, and queued secondaries or primaries already handed
+// out), so that no ray waits on a ticket or a ring that ended with the
+// interrupted launch.  Fresh primaries stay with q->head.
+__global__ void resume_reset_kernel(KParams P) {
+  if (threadIdx.x == 0) {
+    P.q->gq_head = 0;
+    P.q->gq_tail = 0;
+    P.q->fix_a = 0;
+    P.q->fix_b = 0;
+    P.q->holes = 0;
+    P.q->steps = 0;
+    P.q->stop = 0;
+    P.stats->interrupted = 0;
+  }
+}
+
+__global__ void resume_clear_kernel(KParams P) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t tail = P.q->tail;
-  const int64_t M = tail < (uint64_t)P.capacity ? (int64_t)tail : P.capacity;
-  const int64_t N = P.stats->records + P.stats->invalid;
+  if (s < P.capacity) P.gq[s] = -1;
+}
+
+__global__ void resume_queue_kernel(KParams P) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t M = used_slots(P);
+  const uint64_t head = P.q->head;
+  bool pending = false;
+  if (s < M) {  // after resume_fix_kernel: M = the occupied slots
+    const int32_t st = P.pool.status[s];
+    pending = st == RT_ST_PARKED ||
+              (st == RT_ST_QUEUED && (s >= P.n_primary || (uint64_t)s < head));
+  }
+  if (__ballot(pending)) {
+    if (pending) {
+      const uint64_t e = wave_append(&P.q->gq_tail);
+      if (e < (uint64_t)P.capacity) P.gq[e] = (int32_t)s;
+    }
+  }
+}
+
+// Slot compaction after a launch with chunked reservations, and before a
+// resumed one: with M = min(tail, capacity) and H the empty slots among the
+// secondaries in [n_primary, M) (holes left by chunks), every empty slot
+// below N = M - H receives a record (finished, parked or queued) from a slot
+// at or above N, so the occupied slots become [0, N).  The two lists live in
+// the overflow queue, which is free at these points: holes at gq[0, ...),
+// records to move at gq[capacity/2, ...); both hold at most
+// min(N, capacity - N) <= capacity/2 entries.  Nothing refers to a slot
+// index across these kernels (queued rays are found again by their status).
+__global__ void compact_count_kernel(KParams P) {
+  if (P.q->stop) return;  // interrupted: compacted when resumed
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool hole = s >= P.n_primary && s < used_slots(P) && P.pool.status[s] == RT_ST_EMPTY;
+  const uint64_t m = __ballot(hole);
+  if (m && (int)__lane_id() == __ffsll((unsigned long long)m) - 1)
+    __hip_atomic_fetch_add(&P.q->holes, (uint64_t)__popcll(m), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void compact_scan_kernel(KParams P) {
+  if (P.q->stop) return;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t M = used_slots(P);
+  const int64_t N = M - (int64_t)P.q->holes;
   const int32_t st = s < M ? P.pool.status[s] : RT_ST_EMPTY;
   const bool hole = s < M && s < N && st == RT_ST_EMPTY;
   const bool mover = s < M && s >= N && st != RT_ST_EMPTY;
@@ -730,30 +877,48 @@ __global__ void compact_scan_kernel(KParams P) {
 }
 
 __global__ void compact_move_kernel(KParams P) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (P.q->stop) return;
   const int64_t half = P.capacity / 2;
-  if (i >= (int64_t)P.q->fix_a || i >= (int64_t)P.q->fix_b || i >= half) return;
-  const int32_t d = P.gq[i], s = P.gq[half + i];
+  const int64_t n = min(min((int64_t)P.q->fix_a, (int64_t)P.q->fix_b), half);
   const Pool& Q = P.pool;
-  double* const f64[] = {Q.x, Q.y, Q.z, Q.ux, Q.uy, Q.uz, Q.s, Q.t,
-                         Q.as_re, Q.as_im, Q.ap_re, Q.ap_im, Q.h};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t d = P.gq[i], s = P.gq[half + i];
+    double* const f64[] = {Q.x, Q.y, Q.z, Q.ux, Q.uy, Q.uz, Q.s, Q.t,
+                           Q.as_re, Q.as_im, Q.ap_re, Q.ap_im, Q.h};
 #pragma unroll
-  for (int f = 0; f < 13; ++f) f64[f][d] = f64[f][s];
-  Q.key[d] = Q.key[s];
-  Q.parent[d] = Q.parent[s];
-  int32_t* const i32[] = {Q.gen, Q.status, Q.n_acc, Q.n_rej, Q.n_ev, Q.region};
+    for (int f = 0; f < 13; ++f) f64[f][d] = f64[f][s];
+    Q.key[d] = Q.key[s];
+    Q.parent[d] = Q.parent[s];
+    int32_t* const i32[] = {Q.gen, Q.status, Q.n_acc, Q.n_rej, Q.n_ev, Q.region};
 #pragma unroll
-  for (int f = 0; f < 6; ++f) i32[f][d] = i32[f][s];
-  Q.side[d] = Q.side[s];
-  Q.status[s] = RT_ST_EMPTY;
+    for (int f = 0; f < 6; ++f) i32[f][d] = i32[f][s];
+    Q.side[d] = Q.side[s];
+    Q.status[s] = RT_ST_EMPTY;
+  }
+}
+
+// After compacting for a resumed launch: the holes were counted as finished
+// when their waves published them; both counts drop by the hole count.
+__global__ void resume_fix_kernel(KParams P) {
+  if (threadIdx.x == 0) {
+    const uint64_t h = P.q->holes;
+    P.q->tail -= h;
+    P.q->finished -= h;
+    P.q->holes = 0;
+    P.q->fix_a = 0;
+    P.q->fix_b = 0;
+  }
 }
 
 // Records the launch needs: primaries + every secondary cast; when some
 // found no slot, plus the slots chunks may leave unused, so that a relaunch
 // with that capacity holds them all.
 __global__ void finish_kernel(KParams P) {
-  if (threadIdx.x == 0)
+  if (threadIdx.x == 0) {
     P.stats->needed = P.n_primary + P.stats->spawned + (P.q->dropped ? (int64_t)P.reserve : 0);
+    P.stats->interrupted = P.q->stop ? 1 : 0;
+  }
 }
 
 // FP32 grid -> float4 nodes (n, Dx, Dy, Dz): D is the central difference of
@@ -880,6 +1045,13 @@ hipError_t launch_trace(const KParams& P, int grid, int block, hipStream_t s) {
     hipLaunchKernelGGL((trace_grid_kernel<MODEL>), dim3(grid), dim3(block), 0, s, P);
   else
     hipLaunchKernelGGL((trace_strat_kernel<MODEL>), dim3(grid), dim3(block), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_compaction(const KParams& P, unsigned cap_blocks, hipStream_t s) {
+  hipLaunchKernelGGL(compact_count_kernel, dim3(cap_blocks), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(compact_scan_kernel, dim3(cap_blocks), dim3(256), 0, s, P);
+  hipLaunchKernelGGL(compact_move_kernel, dim3(std::min(cap_blocks, 1024u)), dim3(256), 0, s, P);
   return hipGetLastError();
 }
 
@@ -1018,6 +1190,7 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   P.t_max = L->t_max;
   P.amp_min = L->amp_min;
   P.max_steps = L->max_steps_per_ray;
+  P.budget = L->max_steps_per_launch;
   P.pool = Pool{out->x,     out->y,     out->z,     out->ux,    out->uy,    out->uz,
                 out->s,     out->t,     out->as_re, out->as_im, out->ap_re, out->ap_im,
                 out->h,     out->key,   out->parent, out->gen,  out->status, out->n_acc,
@@ -1055,8 +1228,23 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
     g_dev.n_cu = ncu;
   }
 
-  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, P);
-  HIP_TRY(hipGetLastError());
+  const unsigned cap_blocks = (unsigned)((out->capacity + 255) / 256);
+  if (L->resume) {
+    hipLaunchKernelGGL(resume_reset_kernel, dim3(1), dim3(64), 0, s, P);
+    HIP_TRY(hipGetLastError());
+    if (out->capacity > 0) {
+      HIP_TRY(launch_compaction(P, cap_blocks, s));
+      hipLaunchKernelGGL(resume_fix_kernel, dim3(1), dim3(64), 0, s, P);
+      HIP_TRY(hipGetLastError());
+      hipLaunchKernelGGL(resume_clear_kernel, dim3(cap_blocks), dim3(256), 0, s, P);
+      HIP_TRY(hipGetLastError());
+      hipLaunchKernelGGL(resume_queue_kernel, dim3(cap_blocks), dim3(256), 0, s, P);
+      HIP_TRY(hipGetLastError());
+    }
+  } else {
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, P);
+    HIP_TRY(hipGetLastError());
+  }
   if (has_grid) {
     const int64_t total = (int64_t)field->grid.nx * field->grid.ny * field->grid.nz;
     hipLaunchKernelGGL(grid_prep_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
@@ -1064,7 +1252,7 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
                        field->grid.nx, field->grid.ny, field->grid.nz);
     HIP_TRY(hipGetLastError());
   }
-  if (out->capacity > 0) {
+  if (out->capacity > 0 && !L->resume) {
     hipLaunchKernelGGL(init_kernel, dim3((unsigned)((out->capacity + 255) / 256)), dim3(256), 0,
                        s, P, src->xyz, src->n, dirs->xyz, dirs->src, P.h_init);
     HIP_TRY(hipGetLastError());
@@ -1102,14 +1290,7 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   HIP_TRY(e);
   if (tuning && tuning->ev_trace_end)
     HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(tuning->ev_trace_end), s));
-  if (chunked) {
-    hipLaunchKernelGGL(compact_scan_kernel, dim3((unsigned)((out->capacity + 255) / 256)),
-                       dim3(256), 0, s, P);
-    HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(compact_move_kernel, dim3((unsigned)((reserve + 255) / 256)), dim3(256), 0,
-                       s, P);
-    HIP_TRY(hipGetLastError());
-  }
+  if (chunked && out->capacity > 0) HIP_TRY(launch_compaction(P, cap_blocks, s));
   hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, P);
   HIP_TRY(hipGetLastError());
   return RT_OK;

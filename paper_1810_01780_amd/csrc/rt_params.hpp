@@ -56,6 +56,9 @@ struct QueueCounters {
   uint64_t dropped;   // secondaries that found no slot below capacity
   uint64_t fix_a;     // slot compaction: holes below the record count
   uint64_t fix_b;     // slot compaction: records at or above it
+  uint64_t steps;     // trial steps of this launch (added every 64 wave iterations)
+  uint64_t stop;      // 1 once the step budget is reached
+  uint64_t holes;     // slot compaction: empty slots among the secondaries
 };
 
 struct KParams {
@@ -76,6 +79,7 @@ struct KParams {
   // limits
   double tol, inv_tol, h_min, h_max, h_init, s_max, t_max, amp_min;
   int64_t max_steps;
+  int64_t budget;  // trial steps per launch, 0 = no limit
   // record pool (= caller's outputs)
   Pool pool;
   int64_t capacity, n_primary;

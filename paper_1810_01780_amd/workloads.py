@@ -95,6 +95,7 @@ class Limits:
     max_generations: int = 1
     model: int = MODEL_PAPER
     max_steps_per_ray: int = 1_000_000
+    max_steps_per_launch: int = 0    # GPU launches only: 0 = no step budget
 
 
 @dataclasses.dataclass

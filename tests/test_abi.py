@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
                           "raytrace_launch", "rt_collect", "rt_last_error"}
     for n in names:
         assert hasattr(lib, n), n
-    assert B.rt_abi_version() == 3
+    assert B.rt_abi_version() == 4
 
 
 def test_struct_layouts_match_header():
@@ -38,7 +38,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(B.rt_anomaly) == 48
     assert C.sizeof(B.rt_field) == 104 and B.rt_field.n_anomalies.offset == 88
     assert C.sizeof(B.rt_plane) == 72
-    assert C.sizeof(B.rt_step_limits) == 64
+    assert C.sizeof(B.rt_step_limits) == 80
     assert C.sizeof(B.rt_stats) == 8 * len(B.STAT_FIELDS)
     assert C.sizeof(B.rt_outputs) == 8 * (len(B.RECORD_FIELDS) + 2)
 
@@ -281,3 +281,28 @@ def test_validate_non_stratified_fields():
     an = (B.rt_anomaly * 1)(B.rt_anomaly((C.c_double * 3)(0.0, 0.0, 100.0), 0.01, 5.0, 1))
     s.field.n_anomalies, s.field.anomalies = 1, C.cast(an, C.POINTER(B.rt_anomaly))
     assert B.rt_solve_validate(s.field, s.bnd, s.tol, s.limits, p) == B.RT_ERR_UNSUPPORTED
+
+
+def test_validate_step_budget_and_resume():
+    d = _descs()
+    d.limits.max_steps_per_launch = 1000
+    d.limits.resume = 1
+    assert _validate(d) == B.RT_OK
+    d.limits.max_steps_per_launch = -1
+    assert _validate(d) == B.RT_ERR_INVALID_ARG and "max_steps_per_launch" in B.rt_last_error()
+    d = _descs()
+    d.limits.resume = 2
+    assert _validate(d) == B.RT_ERR_INVALID_ARG and "resume" in B.rt_last_error()
+    # solves take neither
+    s = _solve_descs()
+    s.limits.max_steps_per_launch = 10
+    assert B.rt_solve_validate(s.field, s.bnd, s.tol, s.limits, B.solve_params()) == \
+        B.RT_ERR_INVALID_ARG
+
+
+def test_collect_reports_interruption():
+    s = B.rt_stats()
+    s.interrupted = 1
+    assert B.rt_collect(s, 10) == B.RT_INTERRUPTED and "resume" in B.rt_last_error()
+    s.needed = 11   # slots short takes precedence: resuming cannot fix it
+    assert B.rt_collect(s, 10) == B.RT_ERR_CAPACITY

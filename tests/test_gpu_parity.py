@@ -223,6 +223,43 @@ def test_chunked_slots_dense_and_overflow(gpu):
         assert np.array_equal(a[f], b[f]), f
 
 
+@pytest.mark.parametrize("model", [W.MODEL_PAPER, W.MODEL_EXACT])
+def test_interrupt_and_resume(gpu, oracle_lib, model):
+    """A step budget per launch stops the trace, parks the rays in flight in
+    their slots and returns RT_INTERRUPTED; relaunches with resume = 1
+    continue it.  After several interruptions the records and the step,
+    event and record counts equal those of one uninterrupted launch bit for
+    bit, and the oracle's within the standard bars."""
+    import dataclasses
+    sc = W.two_layer(rays_per_source=16, model=model)
+    _announce(f"interrupt-resume-m{model}", sc)
+    base, bst = gpu.trace(sc)
+    total = bst["accepted"] + bst["rejected"] + bst["relocation"]
+    lim = dataclasses.replace(sc.limits, max_steps_per_launch=total // 6)
+    ds = gpu.DeviceScene(dataclasses.replace(sc, limits=lim))
+    ds.launch()
+    rec, st = ds.collect(check=False)
+    n_int = 0
+    while st["interrupted"]:
+        assert st["sched_errors"] == 0
+        assert gpu.rt_collect(gpu.rt_stats(*[st[f] for f in gpu.STAT_FIELDS]),
+                              ds.capacity) == gpu.RT_INTERRUPTED
+        n_int += 1
+        assert n_int < 50
+        ds.launch(resume=True)
+        rec, st = ds.collect(check=False)
+    print(f"[gpu-case] interrupt-resume-m{model}: {n_int} interruptions", flush=True)
+    assert n_int >= 3
+    rec, st = ds.collect(check=True)
+    for f in ("accepted", "rejected", "events", "spawned", "records", "needed", "max_gen"):
+        assert st[f] == bst[f], f
+    a, b = sort_by_key(base), sort_by_key(rec)
+    for f in a:
+        assert np.array_equal(a[f], b[f]), f
+    ref, rst = oracle_lib.trace(sc)
+    compare(rec, ref, sc.limits.tol, label=f"interrupt-resume-m{model}")
+
+
 @pytest.mark.parametrize("block,refill", [(64, 1), (128, 64), (256, 16), (192, 33)])
 def test_schedule_independence(gpu, block, refill):
     """Results do not depend on block size or refill threshold."""
