@@ -304,3 +304,40 @@ def test_two_layer_full_size_sampled(gpu, oracle_lib):
     summ = compare(sub, ref, sc.limits.tol, label="twolayer-full-sample")
     print(f"[gpu-case] twolayer-full: {summ}; stats {gst}", flush=True)
     assert gst["records"] == gst["needed"] and gst["sched_errors"] == 0
+
+
+def _sampled(gpu, oracle_lib, sc, name, n_roots=512, conditioned=False):
+    """Full-size launch in the benchmark's configuration; the whole ray trees
+    of n_roots evenly spaced primaries are compared with the oracle."""
+    _announce(name, sc)
+    got, gst = gpu.trace(sc)
+    roots = np.arange(0, sc.n_rays, max(1, sc.n_rays // n_roots), dtype=np.int64)
+    ref, rst = oracle_lib.trace(sc, roots=roots)
+    sel = np.isin((got["key"] >> np.uint64(24)).astype(np.int64), roots)
+    sub = {f: a[sel] for f, a in got.items()}
+    if conditioned:
+        ref2, _ = oracle_lib.trace(perturbed(sc), roots=roots)
+        summ = compare_conditioned(sub, ref, ref2, sc.limits.tol, label=name)
+    else:
+        summ = compare(sub, ref, sc.limits.tol, label=name)
+    print(f"[gpu-case] {name}: {summ}; stats {gst}", flush=True)
+    assert gst["records"] + gst["invalid"] == gst["needed"] and gst["sched_errors"] == 0
+    return summ
+
+
+def test_curved_full_size_sampled(gpu, oracle_lib):
+    """The curved-boundary bench workload (1,048,576 rays, three
+    generations)."""
+    _sampled(gpu, oracle_lib, W.curved(rays_per_source=262144), "curved-full")
+
+
+def test_field3d_full_size_sampled(gpu, oracle_lib):
+    """The non-stratified bench workload (1,048,576 rays, general kernel)."""
+    _sampled(gpu, oracle_lib, W.field3d(rays_per_source=262144), "field3d-full")
+
+
+def test_gridded_full_size_sampled(gpu, oracle_lib):
+    """The gridded bench workload (4,194,304 rays at tol 1e-7), judged
+    against the oracle's own sensitivity like the reduced gridded case."""
+    summ = _sampled(gpu, oracle_lib, W.gridded(), "grid256-full", n_roots=256, conditioned=True)
+    assert summ["well_conditioned"] > 0.5 * 256
