@@ -755,15 +755,25 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
 }
 
 // Persistent trace kernels.  The stratified variants are held to three
-// waves per SIMD (168 VGPRs): latency of the FP64 dependency chains is hidden
-// by occupancy, and they fit without spilling.
+// waves per SIMD (168 VGPRs), where they fit with few spills.  The general
+// 3-D gradient body runs in two instances: for analytic media, arithmetic
+// bound, with the registers it wants (two waves per SIMD); for gridded
+// media, held to three waves per SIMD although ~120 VGPRs then spill to
+// scratch: its node gathers mostly miss L2 (about a third hit), and the
+// extra wave hides more of that latency (1.28x faster on the 256^3 grid
+// than two waves without spills; the analytic case is 1.34x slower so).
 template <int MODEL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 trace_strat_kernel(KParams P) {
   trace_body<MODEL, 0>(P);
 }
 template <int MODEL>
-__global__ void __launch_bounds__(256) trace_grid_kernel(KParams P) {
+__global__ void __launch_bounds__(256) trace_general_kernel(KParams P) {
+  trace_body<MODEL, 1>(P);
+}
+template <int MODEL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+trace_grid_kernel(KParams P) {
   trace_body<MODEL, 1>(P);
 }
 
@@ -1018,10 +1028,12 @@ struct DeviceInfo {
 };
 thread_local DeviceInfo g_dev;
 
-template <int MODEL, int FIELD>
+// Kernel instances: 0 stratified, 1 general analytic, 2 gridded.
+template <int MODEL, int KIND>
 void* trace_kernel_ptr() {
-  return FIELD ? reinterpret_cast<void*>(&trace_grid_kernel<MODEL>)
-               : reinterpret_cast<void*>(&trace_strat_kernel<MODEL>);
+  if constexpr (KIND == 2) return reinterpret_cast<void*>(&trace_grid_kernel<MODEL>);
+  if constexpr (KIND == 1) return reinterpret_cast<void*>(&trace_general_kernel<MODEL>);
+  return reinterpret_cast<void*>(&trace_strat_kernel<MODEL>);
 }
 
 template <int MODEL, int FIELD>
@@ -1039,13 +1051,29 @@ int max_blocks_per_cu(int block) {
   return c;
 }
 
-template <int MODEL, int FIELD>
+template <int MODEL, int KIND>
 hipError_t launch_trace(const KParams& P, int grid, int block, hipStream_t s) {
-  if constexpr (FIELD == 1)
+  if constexpr (KIND == 2)
     hipLaunchKernelGGL((trace_grid_kernel<MODEL>), dim3(grid), dim3(block), 0, s, P);
+  else if constexpr (KIND == 1)
+    hipLaunchKernelGGL((trace_general_kernel<MODEL>), dim3(grid), dim3(block), 0, s, P);
   else
     hipLaunchKernelGGL((trace_strat_kernel<MODEL>), dim3(grid), dim3(block), 0, s, P);
   return hipGetLastError();
+}
+
+template <int MODEL>
+int blocks_per_cu(int kind, int block) {
+  if (kind == 2) return max_blocks_per_cu<MODEL, 2>(block);
+  if (kind == 1) return max_blocks_per_cu<MODEL, 1>(block);
+  return max_blocks_per_cu<MODEL, 0>(block);
+}
+
+template <int MODEL>
+hipError_t launch_kind(int kind, const KParams& P, int grid, int block, hipStream_t s) {
+  if (kind == 2) return launch_trace<MODEL, 2>(P, grid, block, s);
+  if (kind == 1) return launch_trace<MODEL, 1>(P, grid, block, s);
+  return launch_trace<MODEL, 0>(P, grid, block, s);
 }
 
 hipError_t launch_compaction(const KParams& P, unsigned cap_blocks, hipStream_t s) {
@@ -1202,7 +1230,7 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   const size_t gq_bytes = ((size_t)out->capacity * 4 + 4095) / 4096 * 4096;
   P.stats = out->stats;
   const bool has_grid = field_uses_grid(field);
-  const bool grid = field_is_general(field);  // FIELD = 1 kernel
+  const int kind = has_grid ? 2 : field_is_general(field) ? 1 : 0;
   if (has_grid) {
     const rt_grid& g = field->grid;
     P.nodes = static_cast<char*>(workspace) + 4096 + gq_bytes;
@@ -1262,9 +1290,9 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   // small launches
   int bpc = 0;
   if (L->model == RT_MODEL_PAPER)
-    bpc = grid ? max_blocks_per_cu<RT_MODEL_PAPER, 1>(block) : max_blocks_per_cu<RT_MODEL_PAPER, 0>(block);
+    bpc = blocks_per_cu<RT_MODEL_PAPER>(kind, block);
   else
-    bpc = grid ? max_blocks_per_cu<RT_MODEL_EXACT, 1>(block) : max_blocks_per_cu<RT_MODEL_EXACT, 0>(block);
+    bpc = blocks_per_cu<RT_MODEL_EXACT>(kind, block);
   if (tuning && tuning->blocks_per_cu > 0) bpc = std::min(bpc, (int)tuning->blocks_per_cu);
   int64_t nblk = (int64_t)g_dev.n_cu * bpc;
   const int64_t by_rays = std::max<int64_t>(1, (dirs->n + block - 1) / block);
@@ -1282,11 +1310,9 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
     HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(tuning->ev_trace_begin), s));
   hipError_t e;
   if (L->model == RT_MODEL_PAPER)
-    e = grid ? launch_trace<RT_MODEL_PAPER, 1>(P, (int)nblk, block, s)
-             : launch_trace<RT_MODEL_PAPER, 0>(P, (int)nblk, block, s);
+    e = launch_kind<RT_MODEL_PAPER>(kind, P, (int)nblk, block, s);
   else
-    e = grid ? launch_trace<RT_MODEL_EXACT, 1>(P, (int)nblk, block, s)
-             : launch_trace<RT_MODEL_EXACT, 0>(P, (int)nblk, block, s);
+    e = launch_kind<RT_MODEL_EXACT>(kind, P, (int)nblk, block, s);
   HIP_TRY(e);
   if (tuning && tuning->ev_trace_end)
     HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(tuning->ev_trace_end), s));
