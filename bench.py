@@ -40,14 +40,15 @@ FLOP_PER_TRIAL_STRAT_PAPER = 540
 # mul + sqrt + sub; paraboloid 4 sub + FMA + 2 mul; box face as a plane;
 # travel-time limit 2.
 SURFACE_FLOP = {0: 6, 1: 17, 2: 8}
-# General 3-D kernel, paper model, analytic medium along an axis with A
-# Gaussian anomalies in the ray's region:
+# General 3-D kernel, paper model (Nystrom form of the Cash-Karp step),
+# analytic medium along an axis with A Gaussian anomalies in the ray's region:
 #   6 stages x (zeta 5 + profile 37 + grad 3 + anomalies 49 A + dw/ds 11 + 1)
-#   stage inputs of all six components (6 x 35)                           210
-#   fifth-order outputs (7 x 9) and error vector (6 x 9)                   117
+#   stage positions: 3 components x sum over stages 2..6 of (2 s + 3)       135
+#   outputs: r (3 x 14), w (3 x 9), tau 2                                    71
+#   error: position (3 x 11) and direction (3 x 9) vectors                   60
 #   error norms (2 x 13 + |w0| 13 + 4)                                      43
 #   controller 69, renormalise 24, s += h 1                                 94
-FLOP_3D_BASE = 6 * (5 + 37 + 3 + 11 + 1) + 210 + 117 + 43 + 94
+FLOP_3D_BASE = 6 * (5 + 37 + 3 + 11 + 1) + 135 + 71 + 60 + 43 + 94
 FLOP_3D_PER_ANOMALY = 6 * 49
 # Gridded media, paper model: per stage 8 float4 node loads (128 B) -> 768 B
 # of node data per trial step.

@@ -31,6 +31,35 @@ constexpr double kE1 = -277.0 / 64512.0, kE3 = 6925.0 / 370944.0,
                  kE4 = -6925.0 / 202752.0, kE5 = -277.0 / 14336.0,
                  kE6 = 277.0 / 7084.0;
 
+__device__ constexpr double ck_b(int j) {
+  return j == 0 ? kB1 : j == 2 ? kB3 : j == 3 ? kB4 : j == 5 ? kB6 : 0.0;
+}
+__device__ constexpr double ck_e(int j) {
+  return j == 0 ? kE1 : j == 2 ? kE3 : j == 3 ? kE4 : j == 4 ? kE5 : j == 5 ? kE6 : 0.0;
+}
+// Products of the tableau for the Nystrom form of a step of r'' = f(r):
+// nodes c_s = sum_j a_sj, (A^2)_si = sum_j a_sj a_ji, (bA)_i, (eA)_i.
+__device__ constexpr double ck_c(int s) {
+  double c = 0.0;
+  for (int j = 0; j < s; ++j) c += ck_a(s, j);
+  return c;
+}
+__device__ constexpr double ck_aa(int s, int i) {
+  double v = 0.0;
+  for (int j = i + 1; j < s; ++j) v += ck_a(s, j) * ck_a(j, i);
+  return v;
+}
+__device__ constexpr double ck_ba(int i) {
+  double v = 0.0;
+  for (int j = i + 1; j < 6; ++j) v += ck_b(j) * ck_a(j, i);
+  return v;
+}
+__device__ constexpr double ck_ea(int i) {
+  double v = 0.0;
+  for (int j = i + 1; j < 6; ++j) v += ck_e(j) * ck_a(j, i);
+  return v;
+}
+
 // y0 + h * sum_j a[S][j] k[j]
 template <int S>
 __device__ __forceinline__ double stage_in(double y0, double h, const double (&k)[6]) {
@@ -324,6 +353,60 @@ __device__ __forceinline__ void stage_vec(const double y[7], double h, const dou
 template <int MODEL>
 __device__ __forceinline__ void trial_3d(const KParams& P, const Medium& M, const double y[7],
                                          double h, double inv_tol, double y5[7], double& err) {
+  if constexpr (MODEL == RT_MODEL_PAPER) {
+    // w' = grad n / n depends on r alone, so the same Cash-Karp step takes
+    // its Nystrom form (equal in exact arithmetic): stage positions
+    // r_s = r0 + h c_s w0 + h^2 sum_i (A^2)_si kw_i, output
+    // r5 = r0 + h w0 + h^2 sum_i (bA)_i kw_i, position error / h
+    // = h sum_i (eA)_i kw_i (the e_j sum to zero).  Only the w-derivatives
+    // kw are kept: half the stage registers of the first-order form.
+    double kw[3][6];
+    double tsum = 0.0;
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+      double rs[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (st == 0) {
+          rs[c] = y[c];
+        } else {
+          double acc = 0.0;
+#pragma unroll
+          for (int i = 0; i + 1 < st; ++i) acc = fma(ck_aa(st, i), kw[c][i], acc);
+          rs[c] = fma(h, fma(h, acc, ck_c(st) * y[3 + c]), y[c]);
+        }
+      }
+      double n, g[3];
+      field3<MODEL>(P, M, rs[0], rs[1], rs[2], n, g);
+      const double in = rcp_nr(n);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) kw[c][st] = g[c] * in;
+      if (st == 0) tsum = kB1 * n;
+      if (st == 2) tsum = fma(kB3, n, tsum);
+      if (st == 3) tsum = fma(kB4, n, tsum);
+      if (st == 5) tsum = fma(kB6, n, tsum);
+    }
+    double dr[3], dw[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double ba = 0.0, ea = 0.0;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) {
+        ba = fma(ck_ba(i), kw[c][i], ba);
+        ea = fma(ck_ea(i), kw[c][i], ea);
+      }
+      y5[c] = fma(h, fma(h, ba, y[3 + c]), y[c]);
+      y5[3 + c] = fma(h, b_sum(kw[c]), y[3 + c]);
+      dr[c] = h * ea;
+      dw[c] = e_sum(kw[c]);
+    }
+    y5[6] = fma(h * kInvC0, tsum, y[6]);
+    const double dr_h = sqrt(fma(dr[0], dr[0], fma(dr[1], dr[1], dr[2] * dr[2])));
+    const double dw_h = sqrt(fma(dw[0], dw[0], fma(dw[1], dw[1], dw[2] * dw[2])));
+    const double iw0 = rsqrt_nr(fma(y[3], y[3], fma(y[4], y[4], y[5] * y[5])));
+    err = fmax(dr_h, h * dw_h * iw0) * inv_tol;
+    return;
+  }
   double k[6][6];  // [component][stage] for r (0..2) and w (3..5)
   double kt[6];
 #pragma unroll

@@ -20,11 +20,11 @@ def test_flop_model_per_trial():
     # a sphere and a paraboloid instead of a plane change the boundary term
     cv = W.curved(rays_per_source=1)
     assert bench.flop_per_trial(cv, 1) == 540 - 12 + 6 + 17 + 8
-    # general kernel: 812 + 294 per anomaly of the ray's region + boundaries
+    # general kernel: 745 + 294 per anomaly of the ray's region + boundaries
     f3 = W.field3d(rays_per_source=1)
     assert bench.is_general(f3)
-    assert bench.flop_per_trial(f3, 0) == 806 + 6
-    assert bench.flop_per_trial(f3, 1) == 806 + 2 * 294 + 6
+    assert bench.flop_per_trial(f3, 0) == 745 + 6
+    assert bench.flop_per_trial(f3, 1) == 745 + 2 * 294 + 6
 
 
 def test_trial_flops_weights_records_by_region():
