@@ -240,36 +240,43 @@ __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], 
                                             double inv_tol, double y5[7], double& err) {
   const double E0 = M.dn != 0.0 ? exp(-y[2] * M.inv_z0) : 0.0;
   if constexpr (MODEL == RT_MODEL_PAPER) {
-    // w = unit velocity, renormalised after every accepted step (|w| = 1)
-    double kz[6], kw[6];
+    // w = unit velocity, renormalised after every accepted step (|w| = 1).
+    // z'' = (dn/dz)/n depends on z alone: the Nystrom form of the step, as
+    // in trial_3d, keeps only the w_z derivatives.
+    double kw[6];
     double tsum = 0.0;  // sum_j b_j n_j / c0
 #pragma unroll
     for (int st = 0; st < 6; ++st) {
-      double dz = 0.0, ws = y[5];
-      if (st == 1) { dz = stage_inc<1>(h, kz); ws = stage_in<1>(y[5], h, kw); }
-      if (st == 2) { dz = stage_inc<2>(h, kz); ws = stage_in<2>(y[5], h, kw); }
-      if (st == 3) { dz = stage_inc<3>(h, kz); ws = stage_in<3>(y[5], h, kw); }
-      if (st == 4) { dz = stage_inc<4>(h, kz); ws = stage_in<4>(y[5], h, kw); }
-      if (st == 5) { dz = stage_inc<5>(h, kz); ws = stage_in<5>(y[5], h, kw); }
       double n, gz;
-      if (st == 0) strat_field_at(M, y[2], E0, n, gz);
-      else strat_field_rel(M, y[2], dz, E0, n, gz);
-      kz[st] = ws;
+      if (st == 0) {
+        strat_field_at(M, y[2], E0, n, gz);
+      } else {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i + 1 < st; ++i) acc = fma(ck_aa(st, i), kw[i], acc);
+        const double dz = h * fma(h, acc, ck_c(st) * y[5]);
+        strat_field_rel(M, y[2], dz, E0, n, gz);
+      }
       kw[st] = gz * rcp_nr(n);
       if (st == 0) tsum = kB1 * n;
       if (st == 2) tsum = fma(kB3, n, tsum);
       if (st == 3) tsum = fma(kB4, n, tsum);
       if (st == 5) tsum = fma(kB6, n, tsum);
     }
+    double ba = 0.0, ea = 0.0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      ba = fma(ck_ba(i), kw[i], ba);
+      ea = fma(ck_ea(i), kw[i], ea);
+    }
     y5[0] = fma(h, y[3], y[0]);
     y5[1] = fma(h, y[4], y[1]);
-    y5[2] = fma(h, b_sum(kz), y[2]);
+    y5[2] = fma(h, fma(h, ba, y[5]), y[2]);
     y5[3] = y[3];
     y5[4] = y[4];
     y5[5] = fma(h, b_sum(kw), y[5]);
     y5[6] = fma(h * kInvC0, tsum, y[6]);
-    // max(|dr|/h, |dw|/|w0|) / tol with |w0| = 1
-    err = fmax(fabs(e_sum(kz)), fabs(h * e_sum(kw))) * inv_tol;
+    err = fmax(fabs(h * ea), fabs(h * e_sum(kw))) * inv_tol;
   } else {
     // w = p = n dr/ds; p_x, p_y are constant in a stratified medium
     const double px = y[3], py = y[4];

@@ -13,18 +13,22 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_flop_model_per_trial():
-    # stratified kernel, two planes: the 540 FLOP breakdown
+    # the method's step: ~750 FLOP (paper model) including ~15 of plane
+    # tests, here replaced by this scene's two planes (6 each) and s += h
     sc = W.two_layer(rays_per_source=1)
     assert not bench.is_general(sc)
-    assert [bench.flop_per_trial(sc, r) for r in range(3)] == [540, 540, 540]
-    # a sphere and a paraboloid instead of a plane change the boundary term
+    assert [bench.flop_per_trial(sc, r) for r in range(3)] == [748, 748, 748]
+    # a sphere and a paraboloid next to the surface plane
     cv = W.curved(rays_per_source=1)
-    assert bench.flop_per_trial(cv, 1) == 540 - 12 + 6 + 17 + 8
-    # general kernel: 745 + 294 per anomaly of the ray's region + boundaries
+    assert bench.flop_per_trial(cv, 1) == 750 - 15 + 6 + 17 + 8 + 1
+    # non-stratified media: axis projection and 294 per anomaly of the region
     f3 = W.field3d(rays_per_source=1)
     assert bench.is_general(f3)
-    assert bench.flop_per_trial(f3, 0) == 745 + 6
-    assert bench.flop_per_trial(f3, 1) == 745 + 2 * 294 + 6
+    assert bench.flop_per_trial(f3, 0) == 750 - 15 + 7 + 30
+    assert bench.flop_per_trial(f3, 1) == 750 - 15 + 7 + 30 + 2 * 294
+    # exact model: ~830
+    ex = W.two_layer(rays_per_source=1, model=W.MODEL_EXACT)
+    assert bench.flop_per_trial(ex, 1) == 830 - 15 + 13
 
 
 def test_trial_flops_weights_records_by_region():
