@@ -51,21 +51,34 @@ BYTES_PER_TRIAL_GRID = 768
 # HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE, per dispatch), each divided by what the same
 # counter reads per byte of a plain 1 GiB device copy (--workload copy).
-# Valid only for the kernel sources with the listed SHA-256 digest; after a
-# change to them the traffic is reported as null until measured again.
+# Valid only for the kernel sources with the listed SHA-256 digest (of their
+# code: comments and whitespace removed); after a change to the code the
+# traffic is reported as null until measured again.
 TRAFFIC = {  # workload -> (fetch bytes, write bytes, digest)
     "twolayer": (1.3973e+09, 5.2915e+09,
-                 "6e8f5845d40f96c047e118f0326af46ae7e7858ba6fd4ca53db721731968b6bc"),
+                 "21aeed4f12d80489bea2a6c1229fea433b768503afe1785e7cf7f419613702e8"),
 }
 TRACE_SOURCES = ("rt_kernels.hip", "rt_device.hpp", "rt_params.hpp")
 
 
-def kernel_digest():
+def code_of(text):
+    """C/C++ source without comments and whitespace."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return "".join(text.split())
+
+
+def kernel_digest(sources=None):
     import hashlib
     h = hashlib.sha256()
     for f in TRACE_SOURCES:
-        with open(os.path.join(ROOT, "paper_1810_01780_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        if sources is None:
+            with open(os.path.join(ROOT, "paper_1810_01780_amd", "csrc", f)) as fh:
+                text = fh.read()
+        else:
+            text = sources[f]
+        h.update(code_of(text).encode())
     return h.hexdigest()
 
 

@@ -1,9 +1,10 @@
 /*
  * radiotrace -- FP64 eikonal ray tracing on MI355X (gfx950).
  *
- * C ABI of the GPU library.  It traces very many rays through a stratified
- * (analytic) or gridded refractive-index field with adaptive Cash-Karp
- * Runge-Kutta 4(5) steps, and handles planar media boundaries where a ray is
+ * C ABI of the GPU library.  It traces very many rays through an analytic
+ * (stratified along any axis, with Gaussian anomalies) or gridded
+ * refractive-index field with adaptive Cash-Karp Runge-Kutta 4(5) steps, and
+ * handles media boundaries (planes, spheres, paraboloids) where a ray is
  * reflected and a refracted secondary ray is cast, both carrying Fresnel
  * amplitudes.  This is the method of RadioPropa (T. Winchen,
  * arXiv:1810.01780), section 2:
@@ -14,7 +15,9 @@
  *     free accuracy parameters (section 2, accuracy discussion);
  *   - boundaries defined explicitly and handled apart from the propagation:
  *     reflection, a refracted secondary cast from the intersection point,
- *     Fresnel amplitudes (section 2, boundary paragraph);
+ *     Fresnel amplitudes (section 2, boundary paragraph); gridded data,
+ *     fields given by formulas and curved boundaries (section 2, set-ups
+ *     after the example);
  *   - travel-time and amplitude limits (Fig. 1 example); amplitudes are not
  *     corrected for path length (Fig. 1 caption).
  *

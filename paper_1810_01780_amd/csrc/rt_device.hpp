@@ -1,5 +1,6 @@
 // Device building blocks shared by the trace and the solve kernels:
-// Cash-Karp trial steps in stratified and gridded media, the step-size
+// Cash-Karp trial steps in stratified, general analytic and gridded media
+// (first-order and Nystrom forms), the step-size
 // controller, boundary functions and crossing selection, Fresnel
 // coefficients, per-wave statistics rows.  FP64 throughout; gfx950.
 #pragma once

@@ -2,16 +2,18 @@
 //
 // Method: RadioPropa (arXiv:1810.01780) section 2 -- the ray equation (eq. 2,
 // locally paraxial; or eq. 1, full eikonal) integrated by the Cash-Karp
-// embedded Runge-Kutta 4(5) pair with adaptive steps, and planar boundaries
-// handled apart from the propagation: the ray reflects and a refracted
-// secondary is cast from the crossing point, with Fresnel amplitudes.
+// embedded Runge-Kutta 4(5) pair with adaptive steps, and boundary surfaces
+// (planes, spheres, paraboloids) handled apart from the propagation: the ray
+// reflects and a refracted secondary is cast from the crossing point, with
+// Fresnel amplitudes.
 //
 // Execution model: one ray per lane, state in registers.  A persistent grid
 // of waves pulls rays from a queue whose slots are the caller's output
 // records; secondaries are appended to the same queue.  Every loop iteration
 // runs exactly one Cash-Karp trial step in every busy lane -- a normal step,
 // or one iterate of the crossing search -- so the expensive arithmetic never
-// diverges; only the cheap bookkeeping after the trial does.
+// diverges; only the cheap bookkeeping after the trial does.  A launch can
+// stop at a step budget, parking its rays in their slots for a resumed one.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

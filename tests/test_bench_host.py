@@ -54,3 +54,15 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_digest_follows_code_not_comments():
+    src = {f: open(os.path.join(ROOT, "paper_1810_01780_amd", "csrc", f)).read()
+           for f in bench.TRACE_SOURCES}
+    d = bench.kernel_digest(src)
+    assert d == bench.kernel_digest()
+    f0 = bench.TRACE_SOURCES[0]
+    commented = dict(src, **{f0: "// a note\n" + src[f0].replace("\n", "\n  ", 3) + "/* end */\n"})
+    assert bench.kernel_digest(commented) == d
+    changed = dict(src, **{f0: src[f0] + "\nint x_ = 1;\n"})
+    assert bench.kernel_digest(changed) != d
