@@ -92,6 +92,23 @@ class Stats(C.Structure):
     _fields_ = [(f, C.c_int64) for f in STAT_FIELDS]
 
 
+EV_SPAWNED, EV_TIR, EV_GEN, EV_AMP = range(4)
+# event record fields: name -> (ctype, numpy dtype, values per event)
+EVENT_FIELDS = {"key": (C.c_uint64, np.uint64, 1), "ordinal": (C.c_int32, np.int32, 1),
+                "boundary": (C.c_int32, np.int32, 1), "outcome": (C.c_int32, np.int32, 1),
+                "gen": (C.c_int32, np.int32, 1), "region_in": (C.c_int32, np.int32, 1),
+                "region_out": (C.c_int32, np.int32, 1), "pos": (C.c_double, np.float64, 3),
+                "dir": (C.c_double, np.float64, 3), "s": (C.c_double, np.float64, 1),
+                "t": (C.c_double, np.float64, 1), "cos_i": (C.c_double, np.float64, 1),
+                "n1": (C.c_double, np.float64, 1), "n2": (C.c_double, np.float64, 1),
+                "amp": (C.c_double, np.float64, 4), "coef": (C.c_double, np.float64, 8)}
+
+
+class Events(C.Structure):
+    _fields_ = ([(f, C.POINTER(ct)) for f, (ct, _, _) in EVENT_FIELDS.items()]
+                + [("capacity", C.c_int64)])
+
+
 _lib = None
 
 
@@ -104,6 +121,10 @@ def lib():
         L.orc_trace.restype = C.c_int
         L.orc_trace.argtypes = [C.POINTER(Problem), C.POINTER(C.c_int64), C.c_int64,
                                 C.POINTER(Records), C.POINTER(Stats), C.c_int]
+        L.orc_trace_events.restype = C.c_int
+        L.orc_trace_events.argtypes = [C.POINTER(Problem), C.POINTER(C.c_int64), C.c_int64,
+                                       C.POINTER(Records), C.POINTER(Stats),
+                                       C.POINTER(Events), C.POINTER(C.c_int64), C.c_int]
         L.orc_ck_trial.restype = None
         L.orc_ck_trial.argtypes = [C.POINTER(Problem), C.c_int32,
                                    C.POINTER(C.c_double), C.c_double,
@@ -172,8 +193,13 @@ class _Prepared:
         self.P = P
 
 
-def trace(scene, roots=None, threads: int | None = None, capacity: int | None = None):
-    """Trace (a subset of the root rays of) ``scene``; records sorted by key."""
+def trace(scene, roots=None, threads: int | None = None, capacity: int | None = None,
+          events: bool = False):
+    """Trace (a subset of the root rays of) ``scene``; records sorted by key.
+    With events=True also returns the Fresnel event records sorted by
+    (key, ordinal): (records, stats, events)."""
+    if events:
+        return _trace_events(scene, roots, threads, capacity)
     L = lib()
     prep = _Prepared(scene)
     n_roots = scene.n_rays if roots is None else len(roots)
@@ -208,6 +234,56 @@ def trace(scene, roots=None, threads: int | None = None, capacity: int | None = 
     order = np.argsort(arrs["key"][:n], kind="stable")
     out = {f: a[:n][order] for f, a in arrs.items()}
     return out, stats
+
+
+def _trace_events(scene, roots, threads, capacity, ev_capacity=None):
+    L = lib()
+    prep = _Prepared(scene)
+    n_roots = scene.n_rays if roots is None else len(roots)
+    if capacity is None:
+        capacity = max(16, 8 * n_roots + 64)
+    if threads is None:
+        threads = max(1, min(os.cpu_count() or 1, 16))
+    if ev_capacity is None:
+        ev_capacity = max(16, 4 * n_roots + 64)
+    arrs = {}
+    for f in F64_FIELDS:
+        arrs[f] = np.zeros(capacity, np.float64)
+    for f in U64_FIELDS:
+        arrs[f] = np.zeros(capacity, np.uint64)
+    for f in I32_FIELDS:
+        arrs[f] = np.zeros(capacity, np.int32)
+    rec = Records(*([_ptr(arrs[f], C.c_double) for f in F64_FIELDS]
+                    + [_ptr(arrs[f], C.c_uint64) for f in U64_FIELDS]
+                    + [_ptr(arrs[f], C.c_int32) for f in I32_FIELDS]
+                    + [capacity]))
+    ev = {f: np.zeros((ev_capacity, k) if k > 1 else ev_capacity, dt)
+          for f, (_, dt, k) in EVENT_FIELDS.items()}
+    evs = Events(*([_ptr(ev[f], ct) for f, (ct, _, _) in EVENT_FIELDS.items()]
+                   + [ev_capacity]))
+    st = Stats()
+    n_ev = C.c_int64(0)
+    rptr = None
+    if roots is not None:
+        ra = np.ascontiguousarray(roots, dtype=np.int64)
+        prep.keep.append(ra)
+        rptr = _ptr(ra, C.c_int64)
+    rc = L.orc_trace_events(C.byref(prep.P), rptr, n_roots, C.byref(rec), C.byref(st),
+                            C.byref(evs), C.byref(n_ev), threads)
+    stats = {f: int(getattr(st, f)) for f in STAT_FIELDS}
+    if rc == -2:
+        raise ValueError("oracle: unsupported problem (generations must be 1..4, planes <= 16)")
+    if rc == -1:
+        raise RuntimeError(f"oracle: record capacity {capacity} < needed {stats['needed']}")
+    if rc == -3:  # more events than room: trace again with room for all of them
+        return _trace_events(scene, roots, threads, capacity, int(n_ev.value))
+    n = stats["records"]
+    order = np.argsort(arrs["key"][:n], kind="stable")
+    out = {f: a[:n][order] for f, a in arrs.items()}
+    m = int(n_ev.value)
+    order = np.lexsort((ev["ordinal"][:m], ev["key"][:m]))
+    evout = {f: a[:m][order] for f, a in ev.items()}
+    return out, stats, evout
 
 
 def ck_trial(scene, region: int, y0, h: float):

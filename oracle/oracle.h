@@ -106,6 +106,38 @@ typedef struct {
 int orc_trace(const orc_problem* P, const int64_t* roots, int64_t n_roots,
               orc_records* out, orc_stats* stats, int n_threads);
 
+/* One record per Fresnel boundary event (section 2, boundary paragraph):
+ * where the ray met which boundary, how it arrived, the two media, the
+ * Fresnel coefficients and what became of the refracted branch. */
+enum {
+  ORC_EV_SPAWNED = 0, /* a refracted secondary was cast */
+  ORC_EV_TIR = 1,     /* total internal reflection: nothing transmitted */
+  ORC_EV_GEN = 2,     /* transmitted branch beyond the generation limit */
+  ORC_EV_AMP = 3      /* transmitted branch below the amplitude cut */
+};
+typedef struct {
+  uint64_t* key;      /* the ray that met the boundary */
+  int32_t* ordinal;   /* its event count including this event, 1..255 */
+  int32_t* boundary;  /* index of the boundary in the problem's list */
+  int32_t* outcome;   /* ORC_EV_* */
+  int32_t* gen;       /* generation of the ray */
+  int32_t *region_in, *region_out; /* medium of the ray / beyond the boundary */
+  double* pos;        /* [cap][3] crossing point (on the boundary) */
+  double* dir;        /* [cap][3] incident unit direction */
+  double *s, *t;      /* path length and travel time there */
+  double *cos_i, *n1, *n2; /* incidence cosine, index before / beyond */
+  double* amp;        /* [cap][4] incident amplitudes as_re, as_im, ap_re, ap_im */
+  double* coef;       /* [cap][8] r_s, r_p, t_s, t_p as (re, im) pairs */
+  int64_t capacity;
+} orc_events;
+
+/* orc_trace that also writes the event records (in no particular order);
+ * *n_events receives the number of events.  Returns -3 when the event
+ * capacity was too small, else as orc_trace. */
+int orc_trace_events(const orc_problem* P, const int64_t* roots, int64_t n_roots,
+                     orc_records* out, orc_stats* stats, orc_events* ev,
+                     int64_t* n_events, int n_threads);
+
 /* Single Cash-Karp trial step of the ray ODE from y0 (7 components) with step
  * h in region reg: writes the 5th-order result and the embedded error vector. */
 void orc_ck_trial(const orc_problem* P, int32_t reg, const double y0[7],

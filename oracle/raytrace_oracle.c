@@ -414,7 +414,41 @@ typedef struct {
   orc_records* out;
   orc_stats st;
   int64_t* rec_counter; /* shared */
+  orc_events* ev;       /* NULL: no event records */
+  int64_t* ev_counter;  /* shared */
 } worker_t;
+
+/* Event record of a Fresnel event of ray r at boundary k (r holds the state
+ * on the boundary and the incident amplitudes; u the incident direction). */
+static void emit_event(worker_t* W, const ray_t* r, int k, int32_t reg_out,
+                       const double u[3], double ci, double n1, double n2,
+                       const double fr[9], int32_t outcome) {
+  if (!W->ev) return;
+  int64_t e = __atomic_fetch_add(W->ev_counter, 1, __ATOMIC_RELAXED);
+  orc_events* E = W->ev;
+  if (e >= E->capacity) return;
+  E->key[e] = r->key;
+  E->ordinal[e] = r->n_ev;
+  E->boundary[e] = k;
+  E->outcome[e] = outcome;
+  E->gen[e] = r->gen;
+  E->region_in[e] = r->region;
+  E->region_out[e] = reg_out;
+  for (int a = 0; a < 3; ++a) {
+    E->pos[3 * e + a] = r->y[a];
+    E->dir[3 * e + a] = u[a];
+  }
+  E->s[e] = r->s;
+  E->t[e] = r->y[6];
+  E->cos_i[e] = ci;
+  E->n1[e] = n1;
+  E->n2[e] = n2;
+  E->amp[4 * e + 0] = r->as_re;
+  E->amp[4 * e + 1] = r->as_im;
+  E->amp[4 * e + 2] = r->ap_re;
+  E->amp[4 * e + 3] = r->ap_im;
+  for (int a = 0; a < 8; ++a) E->coef[8 * e + a] = fr[a];
+}
 
 static void emit(worker_t* W, const ray_t* r, int32_t status) {
   int64_t slot = __atomic_fetch_add(W->rec_counter, 1, __ATOMIC_RELAXED);
@@ -656,6 +690,7 @@ static void trace_tree(worker_t* W, const ray_t* root) {
       orc_field(P, reg_out, r.y, &n2, gtmp);
       double fr[9];
       int tir = orc_fresnel(n1, n2, ci, fr);
+      int32_t outcome = tir ? ORC_EV_TIR : ORC_EV_GEN;
 
       if (!tir) {
         if (r.gen + 1 < P->max_gen) {
@@ -680,14 +715,17 @@ static void trace_tree(worker_t* W, const ray_t* root) {
           double amax = fmax(hypot(c.as_re, c.as_im), hypot(c.ap_re, c.ap_im));
           if (P->amp_min > 0.0 && amax < P->amp_min) {
             W->st.suppressed_amp++;
+            outcome = ORC_EV_AMP;
           } else {
             W->st.spawned++;
+            outcome = ORC_EV_SPAWNED;
             fifo_push(&q, &c);
           }
         } else {
           W->st.suppressed_gen++;
         }
       }
+      emit_event(W, &r, k, reg_out, u, ci, n1, n2, fr, outcome);
       /* the parent continues as the reflected ray */
       {
         double ur[3];
@@ -768,17 +806,26 @@ static void* run_job(void* arg) {
 
 int orc_trace(const orc_problem* P, const int64_t* roots, int64_t n_roots,
               orc_records* out, orc_stats* stats, int n_threads) {
+  int64_t n_events;
+  return orc_trace_events(P, roots, n_roots, out, stats, NULL, &n_events, n_threads);
+}
+
+int orc_trace_events(const orc_problem* P, const int64_t* roots, int64_t n_roots,
+                     orc_records* out, orc_stats* stats, orc_events* ev,
+                     int64_t* n_events, int n_threads) {
   scene_t S;
   if (P->max_gen < 1 || P->max_gen > 4 || P->n_planes > 16) return -2;
   build_scene(P, &S);
   if (!roots) n_roots = P->n_rays;
   if (n_threads < 1) n_threads = 1;
-  int64_t counter = 0, next = 0;
+  int64_t counter = 0, next = 0, ev_counter = 0;
   job_t* jobs = (job_t*)calloc((size_t)n_threads, sizeof(job_t));
   for (int t = 0; t < n_threads; ++t) {
     jobs[t].W.S = &S;
     jobs[t].W.out = out;
     jobs[t].W.rec_counter = &counter;
+    jobs[t].W.ev = ev;
+    jobs[t].W.ev_counter = &ev_counter;
     jobs[t].roots = roots;
     jobs[t].n_roots = n_roots;
     jobs[t].next = &next;
@@ -806,8 +853,10 @@ int orc_trace(const orc_problem* P, const int64_t* roots, int64_t n_roots,
     if (s->max_gen > stats->max_gen) stats->max_gen = s->max_gen;
   }
   stats->needed = counter;
+  *n_events = ev_counter;
   free(jobs);
-  return counter > out->capacity ? -1 : 0;
+  if (counter > out->capacity) return -1;
+  return ev && ev_counter > ev->capacity ? -3 : 0;
 }
 
 /* ======================================================================== */
