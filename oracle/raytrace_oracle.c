@@ -529,6 +529,42 @@ static double G_of(const scene_t* S, const ray_t* r, int k, const double y[7]) {
   return sg * bnd_g(S, k, y);
 }
 
+/* True when the ray, standing on boundary k, moves away from it into its
+ * own side (the direction has a positive component along side * normal). */
+static int leaving(const scene_t* S, const ray_t* r, int k) {
+  if (S->pl[k].kind == KIND_TIME) return 0;
+  double nb[3], u[3];
+  bnd_normal(S, k, r->y, nb);
+  unit_direction(r->y, u);
+  return side_sign(r, k) * (u[0] * nb[0] + u[1] * nb[1] + u[2] * nb[2]) > 0.0;
+}
+
+/* The crossing of boundary k on the step [0, len] (G0 = G at the start,
+ * G1 <= 0 at the end).  A ray passes a boundary only by going through it
+ * (section 2, boundary paragraph).  A ray that starts on the boundary
+ * (G0 within the search tolerance) and heads into it passes it at
+ * sigma = 0.  One that starts on it and leaves it (after an event, the
+ * reflected ray and the secondary do) passes it only where it comes back,
+ * e.g. at the far end of a short chord through a sphere: the search then
+ * starts from the first of len/2, len/4, ... at which the ray is clearly on
+ * its own side (at sigma = 0 when there is none). */
+static double crossing(worker_t* W, const ray_t* r, int k, double G0, double len,
+                       double G1, double hp, double ystar[7]) {
+  if (G0 > LOC_GTOL) return locate(W, r, k, 0.0, G0, len, G1, hp, ystar);
+  if (leaving(W->S, r, k)) {
+    double a = len, dl[7];
+    for (int it = 0; it < LOC_MAXIT; ++it) {
+      a *= 0.5;
+      orc_ck_trial(W->S->P, r->region, r->y, a, ystar, dl);
+      W->st.relocation++;
+      double Ga = G_of(W->S, r, k, ystar);
+      if (Ga > LOC_GTOL) return locate(W, r, k, a, Ga, len, G1, hp, ystar);
+    }
+  }
+  memcpy(ystar, r->y, 7 * sizeof(double));
+  return 0.0;
+}
+
 /* Among the boundaries crossed at the end of a step (G1 <= 0, except 'skip'),
  * pick the one whose linear estimate of the crossing point is earliest. */
 static int pick_crossing(const scene_t* S, const ray_t* r, const double y0[7],
@@ -628,24 +664,14 @@ static void trace_tree(worker_t* W, const ray_t* root) {
       }
 
       /* locate the earliest crossing on the Cash-Karp step map */
-      double ystar[7], sig;
-      if (G0 <= 0.0) {
-        sig = 0.0;
-        memcpy(ystar, r.y, sizeof ystar);
-      } else {
-        sig = locate(W, &r, k, 0.0, G0, hp, G1, hp, ystar);
-      }
+      double ystar[7];
+      double sig = crossing(W, &r, k, G0, hp, G1, hp, ystar);
       for (int pass = 0; pass < LOC_MAXPASS; ++pass) {
         double H0, H1;
         int j = pick_crossing(S, &r, r.y, ystar, sig, k, &H0, &H1);
         if (j < 0) break;
         k = j;
-        if (H0 <= 0.0) {
-          sig = 0.0;
-          memcpy(ystar, r.y, sizeof ystar);
-        } else {
-          sig = locate(W, &r, k, 0.0, H0, sig, H1, hp, ystar);
-        }
+        sig = crossing(W, &r, k, H0, sig, H1, hp, ystar);
       }
       const bplane_t* b = &S->pl[k];
       bnd_snap(S, k, ystar);

@@ -14,7 +14,7 @@ import pytest
 
 from paper_1810_01780_amd import workloads as W
 
-from .event_checks import SPAWNED, TIR, check_geometry, check_tree
+from .event_checks import GEN, SPAWNED, TIR, check_geometry, check_tree
 
 N_SURF = 1.78 - 0.43
 W_C0 = 299792458.0
@@ -120,3 +120,62 @@ def test_planted_mistake_is_caught(oracle_lib):
     bad["pos"][0, 2] += 1e-6
     with pytest.raises(AssertionError):
         check_geometry(sc, bad)
+
+
+def _void_chord_scene(model, theta_deg=40.0, radius=10.0):
+    """Ice of constant n = 1.5 holding a spherical void (n = 1, radius 10 m,
+    centre at 100 m depth); one ray travels straight down at the impact
+    parameter R sin(theta) and meets the void at incidence theta."""
+    b = radius * np.sin(np.radians(theta_deg))
+    regions = [W.Region(a=1.5, z_top=-np.inf, z_bot=np.inf),
+               W.Region(a=1.0, z_top=np.inf, z_bot=np.inf)]
+    planes = [W.Plane(point=(0.0, 0.0, 100.0), normal=(0.0, 0.0, 1.0), region_pos=0,
+                      region_neg=1, shape=W.SHAPE_SPHERE, param=radius)]
+    return W.Scene(name="void-chord", regions=regions, planes=planes,
+                   sources=np.array([[b, 0.0, 50.0]]), ray_src=np.zeros(1, np.int32),
+                   dirs=np.array([[0.0, 0.0, 1.0]]),
+                   limits=W.Limits(tol=1e-6, h_min=1e-3, h_max=10.0, s_max=60.0,
+                                   max_generations=2, model=model))
+
+
+@pytest.mark.parametrize("model", [W.MODEL_PAPER, W.MODEL_EXACT])
+def test_short_chord_through_a_void(oracle_lib, model):
+    """Closed form in constant media: the refracted secondary crosses the
+    void along a chord of 2 R cos(theta_t) = 5.3 m, shorter than its step,
+    and meets the wall again where the straight line leaves the sphere; it
+    keeps bouncing inside along chords of the same length and incidence (it
+    must not stall on the wall it was cast from)."""
+    R, c = 10.0, np.array([0.0, 0.0, 100.0])
+    sc = _void_chord_scene(model)
+    rec, st, ev = oracle_lib.trace(sc, events=True)
+    th = np.radians(40.0)
+    p1 = np.array([R * np.sin(th), 0.0, 100.0 - R * np.cos(th)])
+    prim = ev["gen"] == 0
+    assert np.linalg.norm(ev["pos"][prim][0] - p1) <= 1e-9
+    assert abs(ev["cos_i"][prim][0] - np.cos(th)) <= 1e-12
+    assert ev["outcome"][prim][0] == SPAWNED
+    # Snell's law in vector form at p1 (normal pointing back into the ice)
+    u = np.array([0.0, 0.0, 1.0])
+    nin = (p1 - c) / R
+    ci = -u @ nin
+    eta = 1.5 / 1.0
+    ct = np.sqrt(1.0 - eta ** 2 * (1.0 - ci ** 2))
+    ut = eta * u + (eta * ci - ct) * nin
+    chord = 2.0 * R * ct
+    assert 5.0 < chord < 6.0
+    child = ev["gen"] == 1
+    pos, s, t = ev["pos"][child], ev["s"][child], ev["t"][child]
+    assert len(pos) >= 2
+    assert np.linalg.norm(pos[0] - (p1 + chord * ut)) <= 1e-9
+    # the search stops within 1e-10 m of the wall: the normal there turns by
+    # up to 1e-11 per bounce
+    assert np.all(np.abs(ev["cos_i"][child] - ct) <= 1e-10)
+    assert np.all(np.abs(np.linalg.norm(np.diff(pos, axis=0), axis=1) - chord) <= 1e-9)
+    assert abs(s[0] - ev["s"][prim][0] - chord) <= 1e-9
+    assert np.all(np.abs(np.diff(s) - chord) <= 1e-9)
+    assert np.all(np.abs(np.diff(t) - chord / W_C0) <= 1e-17)
+    # inside the void the secondary is beyond the generation limit: no more rays
+    assert np.all(ev["outcome"][child] == GEN) and st["records"] == 2
+    assert np.all(rec["status"] == oracle_lib.ST_PATH)
+    check_geometry(sc, ev)
+    check_tree(sc, rec, st, ev)
