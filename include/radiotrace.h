@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define RT_ABI_VERSION 4
+#define RT_ABI_VERSION 5
 #define RT_MAX_REGIONS 8
 #define RT_MAX_PLANES 16
 #define RT_MAX_ANOMALIES 8
@@ -217,7 +217,44 @@ typedef struct {
   int64_t sched_errors; /* scheduler waits that timed out (must stay 0) */
   int64_t spilled;    /* secondaries handed to other waves (global queue) */
   int64_t interrupted; /* 1: this launch stopped at max_steps_per_launch */
+  int64_t events_lost; /* event records that did not fit out->ev_capacity */
 } rt_stats;
+
+/* Outcome of a Fresnel event for its transmitted branch. */
+enum {
+  RT_EV_SPAWNED = 0, /* a refracted secondary was cast */
+  RT_EV_TIR = 1,     /* total internal reflection: nothing is transmitted */
+  RT_EV_GEN = 2,     /* not cast: the secondary would exceed max_generations */
+  RT_EV_AMP = 3      /* not cast: its amplitude is below amp_min */
+};
+
+/* Optional record of one Fresnel boundary event, the interaction section 2
+ * describes for a ray passing a boundary: the ray is reflected (it keeps its
+ * key and continues) and a refracted secondary is cast from the crossing
+ * point, both with amplitudes scaled by Fresnel's coefficients.  Events at
+ * absorbing boundaries, box faces and the travel-time limit end the ray and
+ * are not recorded here (the final record holds them).  216 bytes. */
+typedef struct {
+  uint64_t key;       /* key of the ray that met the boundary */
+  int32_t ordinal;    /* its event count including this event, 1..255; a
+                         secondary cast here has key
+                         key | ordinal << (8 * (2 - gen)) */
+  int32_t boundary;   /* index into rt_boundaries.planes */
+  int32_t outcome;    /* RT_EV_* */
+  int32_t gen;        /* generation of the ray */
+  int32_t region_in;  /* medium of the ray */
+  int32_t region_out; /* medium beyond the boundary */
+  double pos[3];      /* crossing point, on the boundary */
+  double dir[3];      /* incident unit direction */
+  double s, t;        /* path length and travel time at the crossing */
+  double cos_i;       /* cosine of the angle of incidence */
+  double n1, n2;      /* refractive index of region_in and region_out there */
+  double amp[4];      /* incident amplitudes: as_re, as_im, ap_re, ap_im */
+  double coef[8];     /* Fresnel coefficients as (re, im) pairs: r_s, r_p,
+                         t_s, t_p (t = 0 under total internal reflection);
+                         the reflected ray's amplitudes are amp * r, the
+                         secondary's amp * t */
+} rt_event;
 
 /* Caller-owned output records, one per ray (primary or secondary), in no
  * particular order, in slots [0, records + invalid) (primaries first, in
@@ -239,6 +276,10 @@ typedef struct {
   uint32_t* side;
   int64_t capacity; /* >= number of primary rays */
   rt_stats* stats;  /* device, one struct; overwritten by each launch */
+  rt_event* events; /* device, ev_capacity event records in no particular
+                       order, or NULL; the first min(stats.events,
+                       ev_capacity) entries are written */
+  int64_t ev_capacity; /* 0 = no event records (events may be NULL) */
 } rt_outputs;
 
 /* Optional launch tuning; NULL selects the defaults. */
@@ -284,7 +325,9 @@ rt_status rt_workspace_bytes(const rt_field* field, int64_t capacity, size_t* by
  * on the device land in out->stats; after synchronising, copy the stats to
  * the host and pass them to rt_collect.  'workspace' is device memory of at
  * least rt_workspace_bytes; it is overwritten.  Launches sharing a
- * workspace or outputs must not overlap. */
+ * workspace or outputs must not overlap.  With out->ev_capacity > 0 every
+ * Fresnel event also appends an rt_event to out->events (RT_ERR_INVALID_ARG
+ * for a negative ev_capacity, or a positive one with events NULL). */
 rt_status raytrace_launch(const rt_field* field,
                           const rt_boundaries* boundaries,
                           const rt_sources* sources,
@@ -297,7 +340,10 @@ rt_status raytrace_launch(const rt_field* field,
  * the scheduler reported an error, RT_ERR_INVALID_ARG when input rays were
  * invalid, RT_ERR_CAPACITY when stats.needed exceeds
  * capacity (records of the slots below capacity are still valid; relaunch
- * with a capacity of at least stats.needed), RT_INTERRUPTED when the launch
+ * with a capacity of at least stats.needed) or when event records were lost
+ * (stats.events_lost > 0; the ev_capacity records written are valid, which
+ * events they hold is unspecified; relaunch with ev_capacity >=
+ * stats.events), RT_INTERRUPTED when the launch
  * stopped at its step budget (the slots then hold finished records, parked
  * and queued rays and unused slots; continue with resume = 1), else RT_OK.
  * Rays that ended RT_ST_NONFINITE are per-ray results and do not fail the

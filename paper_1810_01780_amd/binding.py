@@ -81,7 +81,8 @@ class rt_step_limits(C.Structure):
 
 STAT_FIELDS = ["accepted", "rejected", "relocation", "forced", "events", "spawned",
                "suppressed_gen", "suppressed_amp", "records", "needed", "nonfinite",
-               "max_gen", "invalid", "refills", "sched_errors", "spilled", "interrupted"]
+               "max_gen", "invalid", "refills", "sched_errors", "spilled", "interrupted",
+               "events_lost"]
 
 
 class rt_stats(C.Structure):
@@ -97,7 +98,29 @@ RECORD_FIELDS = F64_FIELDS + U64_FIELDS + I32_FIELDS + U32_FIELDS
 
 class rt_outputs(C.Structure):
     _fields_ = ([(f, C.c_void_p) for f in RECORD_FIELDS]
-                + [("capacity", C.c_int64), ("stats", C.c_void_p)])
+                + [("capacity", C.c_int64), ("stats", C.c_void_p), ("events", C.c_void_p),
+                   ("ev_capacity", C.c_int64)])
+
+
+RT_EV_SPAWNED, RT_EV_TIR, RT_EV_GEN, RT_EV_AMP = range(4)
+
+
+class rt_event(C.Structure):
+    _fields_ = [("key", C.c_uint64), ("ordinal", C.c_int32), ("boundary", C.c_int32),
+                ("outcome", C.c_int32), ("gen", C.c_int32), ("region_in", C.c_int32),
+                ("region_out", C.c_int32), ("pos", C.c_double * 3), ("dir", C.c_double * 3),
+                ("s", C.c_double), ("t", C.c_double), ("cos_i", C.c_double),
+                ("n1", C.c_double), ("n2", C.c_double), ("amp", C.c_double * 4),
+                ("coef", C.c_double * 8)]
+
+
+# the same layout as a numpy record type (for event arrays copied from the device)
+EVENT_DTYPE = np.dtype([("key", np.uint64), ("ordinal", np.int32), ("boundary", np.int32),
+                        ("outcome", np.int32), ("gen", np.int32), ("region_in", np.int32),
+                        ("region_out", np.int32), ("pos", np.float64, 3),
+                        ("dir", np.float64, 3), ("s", np.float64), ("t", np.float64),
+                        ("cos_i", np.float64), ("n1", np.float64), ("n2", np.float64),
+                        ("amp", np.float64, 4), ("coef", np.float64, 8)])
 
 
 class rt_tuning(C.Structure):
@@ -352,7 +375,8 @@ class DeviceScene:
     """Device-resident inputs, outputs and workspace for one Scene (torch
     tensors on cuda:0 by default), reusable across launches."""
 
-    def __init__(self, scene: W.Scene, capacity: Optional[int] = None, device="cuda"):
+    def __init__(self, scene: W.Scene, capacity: Optional[int] = None, device="cuda",
+                 ev_capacity: int = 0):
         import torch
         self.torch = torch
         self.scene = scene
@@ -379,8 +403,15 @@ class DeviceScene:
         for f in I32_FIELDS + U32_FIELDS:
             self.rec[f] = torch.empty(cap, dtype=torch.int32, device=dev)
         self.stats_dev = torch.zeros(len(STAT_FIELDS), dtype=torch.int64, device=dev)
+        self.ev_capacity = int(ev_capacity)
+        self.events_dev = None
+        if self.ev_capacity > 0:
+            self.events_dev = torch.empty(self.ev_capacity * EVENT_DTYPE.itemsize,
+                                          dtype=torch.uint8, device=dev)
         self.out = rt_outputs(*([self.rec[f].data_ptr() for f in RECORD_FIELDS]
-                                + [self.capacity, self.stats_dev.data_ptr()]))
+                                + [self.capacity, self.stats_dev.data_ptr(),
+                                   self.events_dev.data_ptr() if self.ev_capacity else None,
+                                   self.ev_capacity]))
         self.ws_bytes = rt_workspace_bytes(self.desc.field, self.capacity)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
 
@@ -425,13 +456,28 @@ class DeviceScene:
             out[f] = a
         return out, stats
 
+    def events(self):
+        """Event records written by the last launch (after collect), as a
+        dict of numpy arrays sorted by (key, ordinal)."""
+        if self.events_dev is None:
+            return None
+        m = min(self.stats()["events"], self.ev_capacity)
+        raw = self.events_dev[:m * EVENT_DTYPE.itemsize].cpu().numpy()
+        ev = raw.view(EVENT_DTYPE)
+        order = np.lexsort((ev["ordinal"], ev["key"]))
+        return {f: np.ascontiguousarray(ev[f][order]) for f in EVENT_DTYPE.names}
+
 
 def trace(scene: W.Scene, capacity: Optional[int] = None, tuning: Optional[rt_tuning] = None,
-          check: bool = True):
-    """Trace a scene on the GPU; returns (records in slot order, stats)."""
-    ds = DeviceScene(scene, capacity=capacity)
+          check: bool = True, ev_capacity: Optional[int] = None):
+    """Trace a scene on the GPU; returns (records in slot order, stats), and
+    with ev_capacity also the event records: (records, stats, events)."""
+    ds = DeviceScene(scene, capacity=capacity, ev_capacity=ev_capacity or 0)
     ds.launch(tuning=tuning)
-    return ds.collect(check=check)
+    out, stats = ds.collect(check=check)
+    if ev_capacity:
+        return out, stats, ds.events()
+    return out, stats
 
 
 # --- emitter -> receiver solves: C entry points and device-side helpers -------

@@ -477,6 +477,12 @@ constexpr double kErrCon = 1.889568e-4;
 // Crossing search (Illinois false position) limits.
 constexpr double kLocGTol = 1e-10, kLocWRel = 1e-14;
 constexpr int kLocMaxIt = 60, kLocMaxPass = 8, kMaxEvents = 255;
+// A step starts on a boundary when G0 <= 2^-33 m (~1.2e-10 m, about the
+// search tolerance), tested as G0 * 2^33 <= 1 with immediate operands only
+// (a 64-bit constant would occupy scalar registers across the step loop).
+__device__ __forceinline__ bool on_boundary(double G0) {
+  return __builtin_amdgcn_ldexp(G0, 33) <= 1.0;
+}
 
 __device__ __forceinline__ double clamp_h(const KParams& P, double h) {
   return fmin(fmax(h, P.h_min), P.h_max);
@@ -545,6 +551,28 @@ __device__ __forceinline__ double bnd_G(const KParams& P, const KBnd& B, int k, 
   if (B.kind == B_TIME) return (P.t_max - y[6]) * 299792458.0;
   const double g = bnd_value(B, y);
   return ((side >> k) & 1u) ? g : -g;
+}
+
+// Departure rate of a ray standing on boundary k: the cosine between its
+// direction and the normal pointing into its own side (> 0 when it leaves
+// the boundary; -1 for the travel-time limit, which a ray only approaches).
+__device__ __forceinline__ double bnd_rate(const KBnd& B, int k, uint32_t side,
+                                           const double y[7]) {
+  if (B.kind == B_TIME) return -1.0;
+  double n0 = B.nrm[0], n1 = B.nrm[1], n2 = B.nrm[2];
+  if (B.shape == SH_SPHERE) {
+    n0 = y[0] - n0;
+    n1 = y[1] - n1;
+    n2 = y[2] - n2;
+  } else if (B.shape == SH_PARABOLOID) {
+    n0 = -2.0 * B.d * (y[0] - n0);
+    n1 = -2.0 * B.d * (y[1] - n1);
+    n2 = 1.0;
+  }
+  const double nn = fma(n0, n0, fma(n1, n1, n2 * n2));
+  const double uu = fma(y[3], y[3], fma(y[4], y[4], y[5] * y[5]));
+  const double c = fma(y[5], n2, fma(y[4], n1, y[3] * n0)) * rsqrt_nr(nn * uu);
+  return ((side >> k) & 1u) ? c : -c;
 }
 
 // Earliest (by linear estimate) boundary crossed at the end of a step of

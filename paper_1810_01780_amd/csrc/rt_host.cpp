@@ -207,6 +207,11 @@ rt_status rt_collect(const rt_stats* s, int64_t capacity) {
                        (long long)s->needed);
     return RT_ERR_CAPACITY;
   }
+  if (s->events_lost > 0) {
+    rt::set_last_error("%lld of %lld event records did not fit; relaunch with ev_capacity >= %lld",
+                       (long long)s->events_lost, (long long)s->events, (long long)s->events);
+    return RT_ERR_CAPACITY;
+  }
   if (s->interrupted) {
     rt::set_last_error("step budget reached; relaunch with resume = 1 to continue");
     return RT_INTERRUPTED;

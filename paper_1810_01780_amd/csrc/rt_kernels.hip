@@ -231,7 +231,7 @@ __device__ __forceinline__ int32_t pretrial_status(const KParams& P, const Ray& 
 
 // Boundary event at the located state ys (boundary k, at sigma along the
 // step); returns the final status of the ray or 0 when it continues.
-template <int MODEL, int FIELD>
+template <int MODEL, int FIELD, bool EV>
 __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int k, double sig,
                                                   double ys[7], double h_next, const Counters& C,
                                                   const WaveQueue& WQ) {
@@ -268,6 +268,7 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
   const int tl = (int)threadIdx.x;
   const double as_re = s_as_re[tl], as_im = s_as_im[tl];
   const double ap_re = s_ap_re[tl], ap_im = s_ap_im[tl];
+  int32_t outcome = tir ? RT_EV_TIR : RT_EV_GEN;
   if (!tir) {
     if (R.gen + 1 < P.max_gen) {
       const double cs_re = as_re * rt[4] - as_im * rt[5];
@@ -277,8 +278,10 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
       const double amax = fmax(hypot(cs_re, cs_im), hypot(cp_re, cp_im));
       if (P.amp_min > 0.0 && amax < P.amp_min) {
         C.bump(S_SUPP_AMP);
+        outcome = RT_EV_AMP;
       } else {
         C.bump(S_SPAWNED);
+        outcome = RT_EV_SPAWNED;
         const uint64_t c = wave_slot(P, (int)threadIdx.x / 64);
         if (c >= (uint64_t)P.capacity) {
           C.bump(S_FIN);  // no record slot: reported via stats.needed
@@ -337,6 +340,35 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
       C.bump(S_SUPP_GEN);
     }
   }
+  if constexpr (EV) {  // instances that record events run only with ev_capacity > 0
+    const uint64_t e = wave_append(&P.q->ev_tail);
+    if (e < (uint64_t)P.ev_capacity) {
+      rt_event* E = P.events + e;
+      E->key = s_key[tl];
+      E->ordinal = R.n_ev;
+      E->boundary = k;
+      E->outcome = outcome;
+      E->gen = R.gen;
+      E->region_in = R.region;
+      E->region_out = reg_out;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        E->pos[a] = R.y[a];
+        E->dir[a] = u[a];
+      }
+      E->s = R.s;
+      E->t = R.y[6];
+      E->cos_i = ci;
+      E->n1 = n1;
+      E->n2 = n2;
+      E->amp[0] = as_re;
+      E->amp[1] = as_im;
+      E->amp[2] = ap_re;
+      E->amp[3] = ap_im;
+#pragma unroll
+      for (int a = 0; a < 8; ++a) E->coef[a] = rt[a];
+    }
+  }
   // the parent continues as the reflected ray
   const double rs_re = as_re * rt[0] - as_im * rt[1];
   const double rs_im = as_re * rt[1] + as_im * rt[0];
@@ -371,7 +403,7 @@ __device__ __forceinline__ void publish_idle(const KParams& P, const Counters& C
 
 // ---------------------------------------------------------------------------
 // Persistent trace kernel.
-template <int MODEL, int FIELD>
+template <int MODEL, int FIELD, bool EV>
 __device__ __forceinline__ void trace_body(const KParams& P) {
   for (int i = threadIdx.x; i < P.n_regions; i += blockDim.x) s_reg[i] = P.reg[i];
   for (int i = threadIdx.x; i < P.n_bnd; i += blockDim.x) s_bnd[i] = P.bnd[i];
@@ -385,6 +417,15 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
   // loop: bracket [a, b] with its function values, the full step length, the
   // controller's proposal for the step after the event, the boundary being
   // searched and (pass << 16 | iterations << 2 | last side + 1).
+  //
+  // A ray passes a boundary only by going through it.  One that starts on
+  // the boundary (on_boundary(G0)) and heads into it passes it at sigma = 0;
+  // one that starts on it and leaves it (the reflected ray and the
+  // secondary after an event) passes it only where it comes back, e.g. at
+  // the far end of a short chord through a sphere.  Its bracket starts with
+  // G(0) taken as rate * len, the distance from the boundary a straight
+  // departure at that rate would gain over the step, in place of G(0) ~ 0,
+  // which would draw the iterates to the departure point.
   __shared__ double s_a[256], s_Ga[256], s_b[256], s_Gb[256], s_hp[256], s_hn[256];
   __shared__ int32_t s_k[256], s_meta[256];
   __syncthreads();
@@ -445,7 +486,7 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
     // ---- boundary events located in the previous iteration ----
     if (mode == 2) {
       mode = 0;
-      int32_t fin = boundary_event<MODEL, FIELD>(P, R, s_k[tid], lc, R.y, s_hn[tid], C, WQ);
+      int32_t fin = boundary_event<MODEL, FIELD, EV>(P, R, s_k[tid], lc, R.y, s_hn[tid], C, WQ);
       if (!fin) fin = pretrial_status(P, R);
       if (fin) {
         write_record(P, R, fin, C);
@@ -629,19 +670,23 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
           s_hp[tid] = ht;
           s_hn[tid] = hn;
           s_k[tid] = k;
-          if (G0 <= 0.0) {
+          const bool on = on_boundary(G0);
+          double rate = 0.0;
+          if (__builtin_expect(on, 0)) rate = bnd_rate(s_bnd[k], k, R.side, R.y);
+          if (on && !(rate > 0.0)) {  // on the boundary, heading in
             s_meta[tid] = 1;  // pass 0, no iterations, last side 0
             located = true;
             sig = 0.0;
 #pragma unroll
             for (int i = 0; i < 7; ++i) y5[i] = R.y[i];
           } else {
+            const double Ga = on ? rate * ht : G0;
             s_a[tid] = 0.0;
-            s_Ga[tid] = G0;
+            s_Ga[tid] = Ga;
             s_b[tid] = ht;
             s_Gb[tid] = G1;
             s_meta[tid] = 1;
-            lc = ht - G1 * ht / (G1 - G0);
+            lc = ht - G1 * ht / (G1 - Ga);
             mode = 1;
           }
         }
@@ -702,19 +747,23 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
         }
         ++pass;
         k = j;
-        if (H0 <= 0.0) {
+        const bool on = on_boundary(H0);
+        double rate = 0.0;
+        if (__builtin_expect(on, 0)) rate = bnd_rate(s_bnd[k], k, R.side, R.y);
+        if (on && !(rate > 0.0)) {
           sig = 0.0;
 #pragma unroll
           for (int i = 0; i < 7; ++i) y5[i] = R.y[i];
           continue;
         }
+        const double Ha = on ? rate * sig : H0;
         s_k[tid] = k;
         s_a[tid] = 0.0;
-        s_Ga[tid] = H0;
+        s_Ga[tid] = Ha;
         s_b[tid] = sig;
         s_Gb[tid] = H1;
         s_meta[tid] = (pass << 16) | 1;
-        lc = sig - H1 * sig / (H1 - H0);
+        lc = sig - H1 * sig / (H1 - Ha);
         mode = 1;
         break;
       }
@@ -764,19 +813,21 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
 // scratch: its node gathers mostly miss L2 (about a third hit), and the
 // extra wave hides more of that latency (1.28x faster on the 256^3 grid
 // than two waves without spills; the analytic case is 1.34x slower so).
-template <int MODEL>
+// EV: the instance also writes event records (launched only when the
+// caller asks for them, so that the others carry none of that code).
+template <int MODEL, bool EV>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 trace_strat_kernel(KParams P) {
-  trace_body<MODEL, 0>(P);
+  trace_body<MODEL, 0, EV>(P);
 }
-template <int MODEL>
+template <int MODEL, bool EV>
 __global__ void __launch_bounds__(256) trace_general_kernel(KParams P) {
-  trace_body<MODEL, 1>(P);
+  trace_body<MODEL, 1, EV>(P);
 }
-template <int MODEL>
+template <int MODEL, bool EV>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 trace_grid_kernel(KParams P) {
-  trace_body<MODEL, 1>(P);
+  trace_body<MODEL, 1, EV>(P);
 }
 
 // Record slots in use: [0, min(tail, capacity)).
@@ -802,6 +853,7 @@ __global__ void reset_kernel(KParams P) {
     P.q->steps = 0;
     P.q->stop = 0;
     P.q->holes = 0;
+    P.q->ev_tail = 0;
   }
 }
 
@@ -930,6 +982,9 @@ __global__ void finish_kernel(KParams P) {
   if (threadIdx.x == 0) {
     P.stats->needed = P.n_primary + P.stats->spawned + (P.q->dropped ? (int64_t)P.reserve : 0);
     P.stats->interrupted = P.q->stop ? 1 : 0;
+    const uint64_t ev = P.q->ev_tail;
+    P.stats->events_lost =
+        ev > (uint64_t)P.ev_capacity ? (int64_t)(ev - (uint64_t)P.ev_capacity) : 0;
   }
 }
 
@@ -1030,12 +1085,14 @@ struct DeviceInfo {
 };
 thread_local DeviceInfo g_dev;
 
-// Kernel instances: 0 stratified, 1 general analytic, 2 gridded.
+// Kernel instances: 0 stratified, 1 general analytic, 2 gridded; plus 3 for
+// the instances that write event records.
 template <int MODEL, int KIND>
 void* trace_kernel_ptr() {
-  if constexpr (KIND == 2) return reinterpret_cast<void*>(&trace_grid_kernel<MODEL>);
-  if constexpr (KIND == 1) return reinterpret_cast<void*>(&trace_general_kernel<MODEL>);
-  return reinterpret_cast<void*>(&trace_strat_kernel<MODEL>);
+  constexpr bool EV = KIND >= 3;
+  if constexpr (KIND % 3 == 2) return reinterpret_cast<void*>(&trace_grid_kernel<MODEL, EV>);
+  if constexpr (KIND % 3 == 1) return reinterpret_cast<void*>(&trace_general_kernel<MODEL, EV>);
+  return reinterpret_cast<void*>(&trace_strat_kernel<MODEL, EV>);
 }
 
 template <int MODEL, int FIELD>
@@ -1055,27 +1112,38 @@ int max_blocks_per_cu(int block) {
 
 template <int MODEL, int KIND>
 hipError_t launch_trace(const KParams& P, int grid, int block, hipStream_t s) {
-  if constexpr (KIND == 2)
-    hipLaunchKernelGGL((trace_grid_kernel<MODEL>), dim3(grid), dim3(block), 0, s, P);
-  else if constexpr (KIND == 1)
-    hipLaunchKernelGGL((trace_general_kernel<MODEL>), dim3(grid), dim3(block), 0, s, P);
+  constexpr bool EV = KIND >= 3;
+  if constexpr (KIND % 3 == 2)
+    hipLaunchKernelGGL((trace_grid_kernel<MODEL, EV>), dim3(grid), dim3(block), 0, s, P);
+  else if constexpr (KIND % 3 == 1)
+    hipLaunchKernelGGL((trace_general_kernel<MODEL, EV>), dim3(grid), dim3(block), 0, s, P);
   else
-    hipLaunchKernelGGL((trace_strat_kernel<MODEL>), dim3(grid), dim3(block), 0, s, P);
+    hipLaunchKernelGGL((trace_strat_kernel<MODEL, EV>), dim3(grid), dim3(block), 0, s, P);
   return hipGetLastError();
 }
 
 template <int MODEL>
 int blocks_per_cu(int kind, int block) {
-  if (kind == 2) return max_blocks_per_cu<MODEL, 2>(block);
-  if (kind == 1) return max_blocks_per_cu<MODEL, 1>(block);
-  return max_blocks_per_cu<MODEL, 0>(block);
+  switch (kind) {
+    case 5: return max_blocks_per_cu<MODEL, 5>(block);
+    case 4: return max_blocks_per_cu<MODEL, 4>(block);
+    case 3: return max_blocks_per_cu<MODEL, 3>(block);
+    case 2: return max_blocks_per_cu<MODEL, 2>(block);
+    case 1: return max_blocks_per_cu<MODEL, 1>(block);
+    default: return max_blocks_per_cu<MODEL, 0>(block);
+  }
 }
 
 template <int MODEL>
 hipError_t launch_kind(int kind, const KParams& P, int grid, int block, hipStream_t s) {
-  if (kind == 2) return launch_trace<MODEL, 2>(P, grid, block, s);
-  if (kind == 1) return launch_trace<MODEL, 1>(P, grid, block, s);
-  return launch_trace<MODEL, 0>(P, grid, block, s);
+  switch (kind) {
+    case 5: return launch_trace<MODEL, 5>(P, grid, block, s);
+    case 4: return launch_trace<MODEL, 4>(P, grid, block, s);
+    case 3: return launch_trace<MODEL, 3>(P, grid, block, s);
+    case 2: return launch_trace<MODEL, 2>(P, grid, block, s);
+    case 1: return launch_trace<MODEL, 1>(P, grid, block, s);
+    default: return launch_trace<MODEL, 0>(P, grid, block, s);
+  }
 }
 
 hipError_t launch_compaction(const KParams& P, unsigned cap_blocks, hipStream_t s) {
@@ -1124,6 +1192,10 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   }
   if (out->capacity < dirs->n || out->capacity > (int64_t)0x7fffffff) {
     set_last_error("capacity must be >= number of rays and < 2^31");
+    return RT_ERR_INVALID_ARG;
+  }
+  if (out->ev_capacity < 0 || (out->ev_capacity > 0 && !out->events)) {
+    set_last_error("ev_capacity must be >= 0, with an events array when > 0");
     return RT_ERR_INVALID_ARG;
   }
   size_t need = 0;
@@ -1227,12 +1299,14 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
                 out->n_rej, out->n_ev,  out->region, out->side};
   P.capacity = out->capacity;
   P.n_primary = dirs->n;
+  P.events = out->events;
+  P.ev_capacity = out->ev_capacity;
   P.q = static_cast<QueueCounters*>(workspace);
   P.gq = reinterpret_cast<int32_t*>(static_cast<char*>(workspace) + 4096);
   const size_t gq_bytes = ((size_t)out->capacity * 4 + 4095) / 4096 * 4096;
   P.stats = out->stats;
   const bool has_grid = field_uses_grid(field);
-  const int kind = has_grid ? 2 : field_is_general(field) ? 1 : 0;
+  const int kind = (has_grid ? 2 : field_is_general(field) ? 1 : 0) + (P.ev_capacity > 0 ? 3 : 0);
   if (has_grid) {
     const rt_grid& g = field->grid;
     P.nodes = static_cast<char*>(workspace) + 4096 + gq_bytes;

@@ -59,6 +59,7 @@ struct QueueCounters {
   uint64_t steps;     // trial steps of this launch (added every 64 wave iterations)
   uint64_t stop;      // 1 once the step budget is reached
   uint64_t holes;     // slot compaction: empty slots among the secondaries
+  uint64_t ev_tail;   // event records reserved so far
 };
 
 struct KParams {
@@ -83,6 +84,8 @@ struct KParams {
   // record pool (= caller's outputs)
   Pool pool;
   int64_t capacity, n_primary;
+  rt_event* events;     // optional event records (ev_capacity > 0)
+  int64_t ev_capacity;
   QueueCounters* q;
   int32_t* gq;  // overflow queue: record slots of published secondaries, -1 = not yet
   rt_stats* stats;

@@ -126,3 +126,72 @@ def compare_conditioned(got, ref, ref_pert, tol, label="", ill_factor=10.0, ill_
         assert summ["ill_median_rel"] <= ill_factor * max(summ["ill_median_spread"], POS_REL), \
             f"{label}: GPU deviates more than the oracle's own sensitivity {summ}"
     return summ
+
+
+# largest |grad n| of the analytic media used in the tests (firn profile
+# 0.43 / 75 m at the surface), to turn a position tolerance into one on n
+GRAD_N_MAX = 6e-3
+
+
+def event_pairs(ev):
+    return ev["key"].astype(np.uint64) * np.uint64(256) + ev["ordinal"].astype(np.uint64)
+
+
+def compare_events(got_ev, ref_ev, got_rec, ref_rec, label=""):
+    """Event records of the GPU against the oracle's, matched by (key,
+    ordinal), for the rays whose step counts agree (see compare): the same
+    events exist; boundary, outcome, generation and media are equal; the
+    crossing point, path length and travel time meet the record bars; the
+    incidence direction and cosine, the indices (through the position) and
+    the incident amplitudes and coefficients (through the direction) follow
+    from those."""
+    g = sort_by_key(got_rec)
+    r = ref_rec
+    common, gi, ri = np.intersect1d(g["key"], r["key"], assume_unique=True, return_indices=True)
+    same = (g["n_acc"][gi] == r["n_acc"][ri]) & (g["n_rej"][gi] == r["n_rej"][ri])
+    good = set(common[same].tolist())
+    gsel = np.array([int(k) in good for k in got_ev["key"]], dtype=bool)
+    rsel = np.array([int(k) in good for k in ref_ev["key"]], dtype=bool)
+    gp, rp = event_pairs(got_ev)[gsel], event_pairs(ref_ev)[rsel]
+    assert np.array_equal(gp, rp), f"{label}: event sets differ ({len(gp)} vs {len(rp)})"
+    G = {f: a[gsel] for f, a in got_ev.items()}
+    R = {f: a[rsel] for f, a in ref_ev.items()}
+    for f in ("boundary", "outcome", "gen", "region_in", "region_out"):
+        assert np.array_equal(G[f], R[f]), f"{label}: event {f} differs"
+    s = np.maximum(R["s"], 1.0)
+    dpos = np.linalg.norm(G["pos"] - R["pos"], axis=1) / s
+    ds = np.abs(G["s"] - R["s"]) / s
+    dt = np.abs(G["t"] - R["t"]) / np.maximum(np.abs(R["t"]), 1e-300)
+    du = np.linalg.norm(G["dir"] - R["dir"], axis=1)
+    dn = np.maximum(np.abs(G["n1"] - R["n1"]), np.abs(G["n2"] - R["n2"]))
+    dci = np.abs(G["cos_i"] - R["cos_i"])
+    damp = np.max(np.abs(G["amp"] - R["amp"]), axis=1)
+    dcoef = np.max(np.abs(G["coef"] - R["coef"]), axis=1)
+    summary = dict(events=len(rp), of=len(ref_ev["key"]), pos=float(dpos.max(initial=0)),
+                   s=float(ds.max(initial=0)), t=float(dt.max(initial=0)),
+                   dir=float(du.max(initial=0)), n=float(dn.max(initial=0)),
+                   cos_i=float(dci.max(initial=0)), amp=float(damp.max(initial=0)),
+                   coef=float(dcoef.max(initial=0)))
+    assert summary["pos"] <= POS_REL and summary["s"] <= POS_REL and summary["t"] <= POS_REL, \
+        f"{label}: event position / path / time {summary}"
+    assert np.all(dn <= GRAD_N_MAX * POS_REL * s + 1e-14), f"{label}: event indices {summary}"
+    # the normal turns by |dpos| / R between two nearby points of a surface of
+    # curvature radius R (25 m for the smallest, the spherical void)
+    assert np.all(dci <= du + dpos * s / 25.0 + 1e-14), f"{label}: incidence cosine {summary}"
+    bar = AMP_ABS + AMP_DIR_SENS * du
+    assert np.all(damp <= bar), f"{label}: incident amplitudes {summary}"
+    # Fresnel coefficients are steep functions of the incidence near the
+    # critical angle: their bar adds how far the oracle's coefficients move
+    # between the two sides' inputs (n1, n2, cos_i)
+    sens = np.array([_coef_shift(G["n1"][i], G["n2"][i], G["cos_i"][i],
+                                 R["n1"][i], R["n2"][i], R["cos_i"][i])
+                     for i in range(len(rp))])
+    assert np.all(dcoef <= bar + 2.0 * sens), f"{label}: coefficients {summary}"
+    return summary
+
+
+def _coef_shift(n1a, n2a, cia, n1b, n2b, cib):
+    import oracle
+    fa = oracle.fresnel(float(n1a), float(n2a), float(cia))[:4]
+    fb = oracle.fresnel(float(n1b), float(n2b), float(cib))[:4]
+    return max(max(abs(x.real - y.real), abs(x.imag - y.imag)) for x, y in zip(fa, fb))

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
                           "raytrace_launch", "rt_collect", "rt_last_error"}
     for n in names:
         assert hasattr(lib, n), n
-    assert B.rt_abi_version() == 4
+    assert B.rt_abi_version() == 5
 
 
 def test_struct_layouts_match_header():
@@ -40,7 +40,11 @@ def test_struct_layouts_match_header():
     assert C.sizeof(B.rt_plane) == 72
     assert C.sizeof(B.rt_step_limits) == 80
     assert C.sizeof(B.rt_stats) == 8 * len(B.STAT_FIELDS)
-    assert C.sizeof(B.rt_outputs) == 8 * (len(B.RECORD_FIELDS) + 2)
+    assert C.sizeof(B.rt_outputs) == 8 * (len(B.RECORD_FIELDS) + 4)
+    assert C.sizeof(B.rt_event) == 216 == B.EVENT_DTYPE.itemsize
+    assert B.rt_event.pos.offset == 32 and B.rt_event.coef.offset == 152
+    for f in B.EVENT_DTYPE.names:
+        assert B.EVENT_DTYPE.fields[f][1] == getattr(B.rt_event, f).offset, f
 
 
 def _descs(scene=None, **lim):
@@ -148,6 +152,9 @@ def test_collect_maps_statistics():
     s2 = B.rt_stats()
     s2.nonfinite = 3          # per-ray status, not a launch failure
     assert B.rt_collect(s2, 0) == B.RT_OK
+    s3 = B.rt_stats()
+    s3.events, s3.events_lost = 12, 2
+    assert B.rt_collect(s3, 0) == B.RT_ERR_CAPACITY and "ev_capacity >= 12" in B.rt_last_error()
 
 
 def test_launch_validates_before_touching_the_device():
@@ -158,6 +165,19 @@ def test_launch_validates_before_touching_the_device():
     d = _descs()
     st = B.raytrace_launch(d.field, d.bnd, d.sources, d.dirs, d.tol, d.limits, out, 0, 0, 0)
     assert st == B.RT_ERR_INVALID_ARG and "null" in B.rt_last_error()
+    # fake (never dereferenced) output arrays: the event arguments are checked
+    # on the host before anything is enqueued
+    out = B.rt_outputs(*([0x10000 * (i + 1) for i in range(len(B.RECORD_FIELDS))]
+                         + [d.dirs.n, 0x900000, None, -1]))
+    ws = 0xA00000
+    st = B.raytrace_launch(d.field, d.bnd, d.sources, d.dirs, d.tol, d.limits, out, ws, 0, 0)
+    assert st == B.RT_ERR_INVALID_ARG and "ev_capacity" in B.rt_last_error()
+    out.ev_capacity = 16
+    st = B.raytrace_launch(d.field, d.bnd, d.sources, d.dirs, d.tol, d.limits, out, ws, 0, 0)
+    assert st == B.RT_ERR_INVALID_ARG and "ev_capacity" in B.rt_last_error()
+    out.ev_capacity = 0   # then the workspace size is the next check
+    st = B.raytrace_launch(d.field, d.bnd, d.sources, d.dirs, d.tol, d.limits, out, ws, 0, 0)
+    assert st == B.RT_ERR_INVALID_ARG and "workspace" in B.rt_last_error()
 
 
 # --- emitter -> receiver solves ---------------------------------------------
