@@ -991,24 +991,14 @@ static shot_t shoot(worker_t* W, const scene_t* S, double zs, double zr, double 
       r.h = h_next;
       continue;
     }
-    double ystar[7], sig;
-    if (G0 <= 0.0) {
-      sig = 0.0;
-      memcpy(ystar, r.y, sizeof ystar);
-    } else {
-      sig = locate(W, &r, k, 0.0, G0, hp, G1, hp, ystar);
-    }
+    double ystar[7];
+    double sig = crossing(W, &r, k, G0, hp, G1, hp, ystar);
     for (int pass = 0; pass < LOC_MAXPASS; ++pass) {
       double H0, H1;
       int j = pick_crossing(S, &r, r.y, ystar, sig, k, &H0, &H1);
       if (j < 0) break;
       k = j;
-      if (H0 <= 0.0) {
-        sig = 0.0;
-        memcpy(ystar, r.y, sizeof ystar);
-      } else {
-        sig = locate(W, &r, k, 0.0, H0, sig, H1, hp, ystar);
-      }
+      sig = crossing(W, &r, k, H0, sig, H1, hp, ystar);
     }
     const bplane_t* b = &S->pl[k];
     bnd_snap(S, k, ystar);
