@@ -597,17 +597,25 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
           s_hn[tid] = hn;
           s_k[tid] = k;
           s_meta[tid] = 1;
-          if (G0 <= 0.0) {
+          // as in the trace: a shot standing on a plane and leaving it (after
+          // a transmission or reflection) searches for its return from the
+          // bracket value rate * len; the receiver plane is never left
+          const bool on = on_boundary(G0);
+          double rate = -1.0;
+          if (__builtin_expect(on, 0) && k != kRecv)
+            rate = bnd_rate(s_bnd[k], k, R.side, R.y);
+          if (on && !(rate > 0.0)) {
             located = true;
             sig = 0.0;
 #pragma unroll
             for (int i = 0; i < 7; ++i) y5[i] = R.y[i];
           } else {
+            const double Ga = on ? rate * ht : G0;
             s_a[tid] = 0.0;
-            s_Ga[tid] = G0;
+            s_Ga[tid] = Ga;
             s_b[tid] = ht;
             s_Gb[tid] = G1;
-            lc = ht - G1 * ht / (G1 - G0);
+            lc = ht - G1 * ht / (G1 - Ga);
             mode = 1;
           }
         }
@@ -668,19 +676,23 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
         }
         ++pass;
         k = j;
-        if (H0 <= 0.0) {
+        const bool on = on_boundary(H0);
+        double rate = -1.0;
+        if (__builtin_expect(on, 0) && k != kRecv) rate = bnd_rate(s_bnd[k], k, R.side, R.y);
+        if (on && !(rate > 0.0)) {
           sig = 0.0;
 #pragma unroll
           for (int i = 0; i < 7; ++i) y5[i] = R.y[i];
           continue;
         }
+        const double Ha = on ? rate * sig : H0;
         s_k[tid] = k;
         s_a[tid] = 0.0;
-        s_Ga[tid] = H0;
+        s_Ga[tid] = Ha;
         s_b[tid] = sig;
         s_Gb[tid] = H1;
         s_meta[tid] = (pass << 16) | 1;
-        lc = sig - H1 * sig / (H1 - H0);
+        lc = sig - H1 * sig / (H1 - Ha);
         mode = 1;
         break;
       }
