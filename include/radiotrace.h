@@ -314,7 +314,9 @@ rt_status rt_validate(const rt_field* field, const rt_boundaries* boundaries,
 
 /* Bytes of device workspace raytrace_launch needs for this field and record
  * capacity: queue counters, a queue of record indices (4 bytes per record,
- * for secondaries shared between waves), plus the prepared grid (16 bytes
+ * for secondaries shared between waves), the order in which the primaries
+ * are handed out (4 bytes per record: by source, then by direction, so that
+ * the lanes of a wave follow nearby paths), plus the prepared grid (16 bytes
  * per node) for gridded fields. */
 rt_status rt_workspace_bytes(const rt_field* field, int64_t capacity, size_t* bytes);
 

@@ -177,6 +177,7 @@ rt_status rt_workspace_bytes(const rt_field* field, int64_t capacity, size_t* by
   }
   size_t b = 4096;                                      // queue counters, padded
   b += ((size_t)capacity * 4 + 4095) / 4096 * 4096;     // overflow queue
+  b += ((size_t)capacity * 4 + 4095) / 4096 * 4096;     // hand-out order of the primaries
   if (field->n_regions > 0 && field->regions && rt::field_uses_grid(field)) {
     const rt_grid& g = field->grid;
     if (g.nx < 2 || g.ny < 2 || g.nz < 2) {

@@ -443,8 +443,11 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
   double lc = 0.0;  // search iterate (mode 1) or located sigma (mode 2)
 
   // Scheduler.
-  //  * Primaries (record slots [0, n_primary)) are handed out in slot order,
-  //    one fetch_add on q->head per wave refill.
+  //  * Primaries (record slots [0, n_primary)) are handed out by ticket, one
+  //    fetch_add on q->head per wave refill, ticket t taking slot P.perm[t]:
+  //    rays of one source with neighbouring directions (order_kernel), so
+  //    that the lanes of a wave follow nearby paths (shared cache lines of
+  //    a gridded field, alike branches).
   //  * A secondary gets its record slot from q->tail.  Up to local_limit
   //    wait on the wave that cast them (ring in LDS; producer and consumer
   //    are the same wave, so a workgroup-scope fence suffices).  Beyond that
@@ -527,8 +530,9 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
         if (lane_idle && rank >= nr) {
           const uint64_t ti = base + (rank - nr);
           if (ti < (uint64_t)P.n_primary) {
-            if (Q.status[ti] == RT_ST_QUEUED) {
-              load_ray<MODEL, FIELD>(P, (int32_t)ti, R, C);
+            const int32_t slot = P.perm[ti];
+            if (Q.status[slot] == RT_ST_QUEUED) {
+              load_ray<MODEL, FIELD>(P, slot, R, C);
               mode = 0;
             } else {
               C.bump(S_FIN);  // an invalid primary: its record is already final
@@ -884,16 +888,29 @@ __global__ void resume_queue_kernel(KParams P) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t M = used_slots(P);
   const uint64_t head = P.q->head;
+  // slot s: a parked ray, or a queued secondary (after resume_fix_kernel
+  // M is the number of occupied slots)
   bool pending = false;
-  if (s < M) {  // after resume_fix_kernel: M = the occupied slots
+  if (s < M) {
     const int32_t st = P.pool.status[s];
-    pending = st == RT_ST_PARKED ||
-              (st == RT_ST_QUEUED && (s >= P.n_primary || (uint64_t)s < head));
+    pending = st == RT_ST_PARKED || (st == RT_ST_QUEUED && s >= P.n_primary);
   }
   if (__ballot(pending)) {
     if (pending) {
       const uint64_t e = wave_append(&P.q->gq_tail);
       if (e < (uint64_t)P.capacity) P.gq[e] = (int32_t)s;
+    }
+  }
+  // ticket s: a primary handed out before the interruption and still queued
+  int32_t slot = -1;
+  if (s < P.n_primary && (uint64_t)s < head) {
+    slot = P.perm[s];
+    if (P.pool.status[slot] != RT_ST_QUEUED) slot = -1;
+  }
+  if (__ballot(slot >= 0)) {
+    if (slot >= 0) {
+      const uint64_t e = wave_append(&P.q->gq_tail);
+      if (e < (uint64_t)P.capacity) P.gq[e] = slot;
     }
   }
 }
@@ -986,6 +1003,72 @@ __global__ void finish_kernel(KParams P) {
     P.stats->events_lost =
         ev > (uint64_t)P.ev_capacity ? (int64_t)(ev - (uint64_t)P.ev_capacity) : 0;
   }
+}
+
+// Hand-out order of the primaries: within each chunk of kOrderChunk
+// consecutive rays, by source and then by a Morton code of the direction's
+// octahedral map (9 bits per axis), ties by index; a bitonic sort of the
+// chunk's 64-bit keys in LDS (128 KiB of the 160 KiB of a CU).  Only the order in which lanes take the rays
+// changes: every ray keeps its record slot and its result.
+constexpr int kOrderChunk = 16384;
+
+__device__ __forceinline__ uint32_t spread9(uint32_t v) {  // bits 0..8 -> even bits
+  v &= 0x1ffu;
+  v = (v | (v << 8)) & 0x00ff00ffu;
+  v = (v | (v << 4)) & 0x0f0f0f0fu;
+  v = (v | (v << 2)) & 0x33333333u;
+  v = (v | (v << 1)) & 0x55555555u;
+  return v;
+}
+
+__global__ void __launch_bounds__(1024) order_kernel(KParams P,
+                                                     const double* __restrict__ dir_xyz,
+                                                     const int32_t* __restrict__ ray_src) {
+  __shared__ unsigned long long key[kOrderChunk];
+  const int64_t base = (int64_t)blockIdx.x * kOrderChunk;
+  const int n = (int)min((int64_t)kOrderChunk, P.n_primary - base);
+  for (int j = threadIdx.x; j < kOrderChunk; j += blockDim.x) {
+    unsigned long long k = ~0ull;
+    if (j < n) {
+      const int64_t i = base + j;
+      const double dx = dir_xyz[3 * i], dy = dir_xyz[3 * i + 1], dz = dir_xyz[3 * i + 2];
+      const double l1 = fabs(dx) + fabs(dy) + fabs(dz);
+      double ox = 0.0, oy = 0.0;
+      if (l1 > 0.0 && isfinite(l1)) {
+        ox = dx / l1;
+        oy = dy / l1;
+        if (dz < 0.0) {  // fold the lower hemisphere onto the corners
+          const double fx = (1.0 - fabs(oy)) * copysign(1.0, ox);
+          oy = (1.0 - fabs(ox)) * copysign(1.0, oy);
+          ox = fx;
+        }
+      }
+      const uint32_t ix = min(511u, (uint32_t)((ox + 1.0) * 256.0));
+      const uint32_t iy = min(511u, (uint32_t)((oy + 1.0) * 256.0));
+      const uint32_t code = spread9(ix) | (spread9(iy) << 1);
+      k = ((unsigned long long)(uint32_t)ray_src[i] << 32) |
+          ((unsigned long long)code << 14) | (unsigned long long)j;
+    }
+    key[j] = k;
+  }
+  __syncthreads();
+  for (int size = 2; size <= kOrderChunk; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < kOrderChunk; t += blockDim.x) {
+        const int u = t ^ stride;
+        if (u > t) {
+          const unsigned long long a = key[t], b = key[u];
+          if ((a > b) == ((t & size) == 0)) {
+            key[t] = b;
+            key[u] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int j = threadIdx.x; j < n; j += blockDim.x)
+    P.perm[base + j] = (int32_t)(base + (int64_t)(key[j] & 0x3fffu));
 }
 
 // FP32 grid -> float4 nodes (n, Dx, Dy, Dz): D is the central difference of
@@ -1304,12 +1387,13 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   P.q = static_cast<QueueCounters*>(workspace);
   P.gq = reinterpret_cast<int32_t*>(static_cast<char*>(workspace) + 4096);
   const size_t gq_bytes = ((size_t)out->capacity * 4 + 4095) / 4096 * 4096;
+  P.perm = reinterpret_cast<int32_t*>(static_cast<char*>(workspace) + 4096 + gq_bytes);
   P.stats = out->stats;
   const bool has_grid = field_uses_grid(field);
   const int kind = (has_grid ? 2 : field_is_general(field) ? 1 : 0) + (P.ev_capacity > 0 ? 3 : 0);
   if (has_grid) {
     const rt_grid& g = field->grid;
-    P.nodes = static_cast<char*>(workspace) + 4096 + gq_bytes;
+    P.nodes = static_cast<char*>(workspace) + 4096 + 2 * gq_bytes;
     P.gnx = g.nx;
     P.gny = g.ny;
     P.gnz = g.nz;
@@ -1359,6 +1443,11 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   if (out->capacity > 0 && !L->resume) {
     hipLaunchKernelGGL(init_kernel, dim3((unsigned)((out->capacity + 255) / 256)), dim3(256), 0,
                        s, P, src->xyz, src->n, dirs->xyz, dirs->src, P.h_init);
+    HIP_TRY(hipGetLastError());
+  }
+  if (dirs->n > 0 && !L->resume) {  // a resumed launch keeps the order it had
+    hipLaunchKernelGGL(order_kernel, dim3((unsigned)((dirs->n + kOrderChunk - 1) / kOrderChunk)),
+                       dim3(1024), 0, s, P, dirs->xyz, dirs->src);
     HIP_TRY(hipGetLastError());
   }
 

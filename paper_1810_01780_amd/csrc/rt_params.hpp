@@ -88,6 +88,7 @@ struct KParams {
   int64_t ev_capacity;
   QueueCounters* q;
   int32_t* gq;  // overflow queue: record slots of published secondaries, -1 = not yet
+  int32_t* perm;  // hand-out order of the primaries: ticket -> record slot
   rt_stats* stats;
 };
 
