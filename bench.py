@@ -55,8 +55,8 @@ BYTES_PER_TRIAL_GRID = 768
 # code: comments and whitespace removed); after a change to the code the
 # traffic is reported as null until measured again.
 TRAFFIC = {  # workload -> (fetch bytes, write bytes, digest)
-    "twolayer": (1.3948e+09, 5.2792e+09,
-                 "5b7e42a1b0cd0030114614fb496c5e3b51047949eefcaef5d5b63ce0b1309072"),
+    "twolayer": (2.9467e+09, 4.8619e+09,
+                 "8a97328fa8328dcd1f6427df8faf845a651512b67b80574c297503a5853d7393"),
 }
 TRACE_SOURCES = ("rt_kernels.hip", "rt_device.hpp", "rt_params.hpp")
 
@@ -169,12 +169,18 @@ def cpu_baseline(scene, target_s, threads, log):
     _, st = oracle.trace(scene, roots=probe, threads=threads)
     dt = time.perf_counter() - t0
     per_root = dt / len(probe)
-    stride = max(1, int(np.ceil(n * per_root / target_s)))
-    roots = np.arange(0, n, stride, dtype=np.int64)
-    log(f"cpu baseline: {len(roots)} of {n} roots (every {stride}th), {threads} threads")
-    t0 = time.perf_counter()
-    _, st = oracle.trace(scene, roots=roots, threads=threads)
-    dt = time.perf_counter() - t0
+    for attempt in range(2):
+        # the probe is short and its time noisy: a sample that ran for less
+        # than half the target is sized again from its own rate, once
+        stride = max(1, int(np.ceil(n * per_root / target_s)))
+        roots = np.arange(0, n, stride, dtype=np.int64)
+        log(f"cpu baseline: {len(roots)} of {n} roots (every {stride}th), {threads} threads")
+        t0 = time.perf_counter()
+        _, st = oracle.trace(scene, roots=roots, threads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= 0.5 * target_s or stride == 1:
+            break
+        per_root = dt / len(roots)
     return {"value": st["accepted"] / dt, "unit": "ray-steps/s", "cores": threads,
             "kind": "oracle",
             "sample": f"every {stride}th root ray ({len(roots)} of {n}) with its full "
@@ -190,12 +196,16 @@ def cpu_solve_baseline(sp, target_s, threads, log):
     t0 = time.perf_counter()
     oracle.solve(sp.scene, sp.zs, sp.zr, sp.dist, pairs=probe, threads=threads)
     per_pair = (time.perf_counter() - t0) / len(probe)
-    stride = max(1, int(np.ceil(n * per_pair / target_s)))
-    pick = np.arange(0, n, stride, dtype=np.int64)
-    log(f"cpu baseline: {len(pick)} of {n} pairs (every {stride}th), {threads} threads")
-    t0 = time.perf_counter()
-    oracle.solve(sp.scene, sp.zs, sp.zr, sp.dist, pairs=pick, threads=threads)
-    dt = time.perf_counter() - t0
+    for attempt in range(2):
+        stride = max(1, int(np.ceil(n * per_pair / target_s)))
+        pick = np.arange(0, n, stride, dtype=np.int64)
+        log(f"cpu baseline: {len(pick)} of {n} pairs (every {stride}th), {threads} threads")
+        t0 = time.perf_counter()
+        oracle.solve(sp.scene, sp.zs, sp.zr, sp.dist, pairs=pick, threads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= 0.5 * target_s or stride == 1:
+            break
+        per_pair = dt / len(pick)
     return {"value": len(pick) / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
             "sample": f"every {stride}th pair ({len(pick)} of {n}), both families, "
                       f"in {dt:.1f} s"}
