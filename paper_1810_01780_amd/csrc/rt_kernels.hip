@@ -811,12 +811,11 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
 
 // Persistent trace kernels.  The stratified variants are held to three
 // waves per SIMD (168 VGPRs), where they fit with few spills.  The general
-// 3-D gradient body runs in two instances: for analytic media, arithmetic
-// bound, with the registers it wants (two waves per SIMD); for gridded
-// media, held to three waves per SIMD although ~120 VGPRs then spill to
-// scratch: its node gathers mostly miss L2 (about a third hit), and the
-// extra wave hides more of that latency (1.28x faster on the 256^3 grid
-// than two waves without spills; the analytic case is 1.34x slower so).
+// 3-D gradient body (analytic media along any axis, anomalies, grids) runs
+// with the registers it wants, two waves per SIMD.  Gridded media were once
+// held to three waves despite ~120 spilled VGPRs, while their node gathers
+// mostly missed L2 (a third hit); with the primaries handed out by source
+// and direction two thirds hit, and two waves without spills are faster.
 // EV: the instance also writes event records (launched only when the
 // caller asks for them, so that the others carry none of that code).
 template <int MODEL, bool EV>
@@ -826,11 +825,6 @@ trace_strat_kernel(KParams P) {
 }
 template <int MODEL, bool EV>
 __global__ void __launch_bounds__(256) trace_general_kernel(KParams P) {
-  trace_body<MODEL, 1, EV>(P);
-}
-template <int MODEL, bool EV>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-trace_grid_kernel(KParams P) {
   trace_body<MODEL, 1, EV>(P);
 }
 
@@ -1168,13 +1162,12 @@ struct DeviceInfo {
 };
 thread_local DeviceInfo g_dev;
 
-// Kernel instances: 0 stratified, 1 general analytic, 2 gridded; plus 3 for
-// the instances that write event records.
+// Kinds of launch: 0 stratified, 1 general analytic, 2 gridded (both on the
+// general kernel); plus 3 for the instances that write event records.
 template <int MODEL, int KIND>
 void* trace_kernel_ptr() {
   constexpr bool EV = KIND >= 3;
-  if constexpr (KIND % 3 == 2) return reinterpret_cast<void*>(&trace_grid_kernel<MODEL, EV>);
-  if constexpr (KIND % 3 == 1) return reinterpret_cast<void*>(&trace_general_kernel<MODEL, EV>);
+  if constexpr (KIND % 3 != 0) return reinterpret_cast<void*>(&trace_general_kernel<MODEL, EV>);
   return reinterpret_cast<void*>(&trace_strat_kernel<MODEL, EV>);
 }
 
@@ -1196,9 +1189,7 @@ int max_blocks_per_cu(int block) {
 template <int MODEL, int KIND>
 hipError_t launch_trace(const KParams& P, int grid, int block, hipStream_t s) {
   constexpr bool EV = KIND >= 3;
-  if constexpr (KIND % 3 == 2)
-    hipLaunchKernelGGL((trace_grid_kernel<MODEL, EV>), dim3(grid), dim3(block), 0, s, P);
-  else if constexpr (KIND % 3 == 1)
+  if constexpr (KIND % 3 != 0)
     hipLaunchKernelGGL((trace_general_kernel<MODEL, EV>), dim3(grid), dim3(block), 0, s, P);
   else
     hipLaunchKernelGGL((trace_strat_kernel<MODEL, EV>), dim3(grid), dim3(block), 0, s, P);
