@@ -1284,7 +1284,7 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
     set_last_error("block_size must be 64, 128, 192 or 256");
     return RT_ERR_INVALID_ARG;
   }
-  const int refill = tuning && tuning->refill_threshold ? tuning->refill_threshold : 16;
+  const int refill = tuning && tuning->refill_threshold ? tuning->refill_threshold : 32;
   if (refill < 1 || refill > 64) {
     set_last_error("refill_threshold must be 1..64");
     return RT_ERR_INVALID_ARG;
