@@ -57,6 +57,8 @@ BYTES_PER_TRIAL_GRID = 768
 TRAFFIC = {  # workload -> (fetch bytes, write bytes, digest)
     "twolayer": (3.1704e+09, 4.4601e+09,
                  "4f4e5f27d9049e074e23341616bc1c23a6c83f33d1dee3fbf8e03e735f5c2058"),
+    "grid256": (3.3810e+11, 2.5610e+09,
+                "4f4e5f27d9049e074e23341616bc1c23a6c83f33d1dee3fbf8e03e735f5c2058"),
 }
 TRACE_SOURCES = ("rt_kernels.hip", "rt_device.hpp", "rt_params.hpp")
 
