@@ -1,0 +1,47 @@
+"""Small seeded scenes for tests that use every slot of the descriptor
+tables at once: RT_MAX_REGIONS media, RT_MAX_PLANES boundaries (plus the
+six box faces and the travel-time limit), RT_MAX_ANOMALIES anomalies."""
+import numpy as np
+
+from paper_1810_01780_amd import workloads as W
+
+
+def maximal(n_rays=256, anomalies=False, model=W.MODEL_PAPER, seed=7):
+    """Air over seven firn layers (8 media) separated by the surface and six
+    horizontal Fresnel interfaces; nine vertical planes (four Fresnel
+    between the same medium on both sides, five absorbing) make 16
+    boundaries; a box, a travel-time and an amplitude limit; four
+    generations; with anomalies=True also 8 Gaussian anomalies spread over
+    the layers (the general kernel)."""
+    rng = np.random.default_rng(seed)
+    depths = [0.0, 20.0, 45.0, 80.0, 120.0, 170.0, 230.0]
+    regions = [W.air_region()]
+    for i, top in enumerate(depths):
+        bot = depths[i + 1] if i + 1 < len(depths) else np.inf
+        regions.append(W.Region(a=1.78 + 0.004 * i, dn=0.43, z0=75.0, z_top=top, z_bot=bot))
+    planes = [W.surface_plane(ice=1, air=0)]
+    for i, z in enumerate(depths[1:]):
+        planes.append(W.Plane(point=(0.0, 0.0, z), normal=(0.0, 0.0, 1.0),
+                              region_pos=i + 2, region_neg=i + 1))
+    # vertical planes x = const: Fresnel ones join a layer to itself (n1 = n2:
+    # full transmission, no reflection), absorbing ones end the ray
+    for j, x in enumerate((-300.0, -220.0, -150.0, 160.0, 240.0, 310.0, 380.0, 450.0, 520.0)):
+        kind = W.PLANE_FRESNEL if j % 2 == 0 and j < 8 else W.PLANE_ABSORB
+        planes.append(W.Plane(point=(x, 0.0, 0.0), normal=(1.0, 0.0, 0.0), region_pos=3,
+                              region_neg=3, kind=kind))
+    assert len(planes) == 16 and len(regions) == 8
+    anoms = []
+    if anomalies:
+        for k in range(8):
+            anoms.append(W.Anomaly(centre=(rng.uniform(-200, 200), rng.uniform(-50, 50),
+                                           rng.uniform(30, 260)),
+                                   amplitude=float(rng.choice([-1, 1]) * rng.uniform(0.005, 0.03)),
+                                   sigma=float(rng.uniform(10, 30)), region=1 + k % 7))
+    sources = np.array([[0.0, 0.0, 100.0], [30.0, 10.0, 200.0]])
+    dirs = W.isotropic(rng, n_rays)
+    ray_src = (np.arange(n_rays) % 2).astype(np.int32)
+    return W.Scene(name="maximal", regions=regions, planes=planes, sources=sources,
+                   ray_src=ray_src, dirs=dirs, anomalies=anoms,
+                   limits=W.Limits(tol=1e-6, h_min=1e-3, h_max=10.0, s_max=1500.0,
+                                   t_max=6e-6, amp_min=1e-4, max_generations=4, model=model),
+                   box_lo=(-1000.0, -1000.0, -800.0), box_hi=(1000.0, 1000.0, 1000.0))

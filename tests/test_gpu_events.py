@@ -11,6 +11,7 @@ from paper_1810_01780_amd import workloads as W
 
 from .event_checks import check_geometry, check_tree
 from .parity import compare, compare_events, event_pairs, sort_by_key
+from .scenes import maximal
 from .test_oracle_events import _void_chord_scene
 
 pytestmark = pytest.mark.gpu
@@ -40,6 +41,9 @@ CASES = {
     "field3d": lambda: W.field3d(rays_per_source=128),
     "void-chord-paper": lambda: _void_chord_scene(W.MODEL_PAPER),
     "void-chord-exact": lambda: _void_chord_scene(W.MODEL_EXACT),
+    # every descriptor slot in use: 8 media, 16 boundaries + box + time limit
+    "maximal-tables": lambda: maximal(),
+    "maximal-tables-anomalies-exact": lambda: maximal(anomalies=True, model=W.MODEL_EXACT),
 }
 
 

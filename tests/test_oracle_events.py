@@ -179,3 +179,18 @@ def test_short_chord_through_a_void(oracle_lib, model):
     assert np.all(rec["status"] == oracle_lib.ST_PATH)
     check_geometry(sc, ev)
     check_tree(sc, rec, st, ev)
+
+
+@pytest.mark.parametrize("anomalies", [False, True])
+def test_full_descriptor_tables(oracle_lib, anomalies):
+    """8 media, 16 boundaries, a box, a travel-time and an amplitude limit
+    (and 8 anomalies): every event valid and tied to the records, and every
+    kind of end occurs."""
+    from .scenes import maximal
+    sc = maximal(anomalies=anomalies)
+    rec, st, ev = oracle_lib.trace(sc, events=True)
+    ends = set(np.unique(rec["status"]).tolist())
+    assert {oracle_lib.ST_BOX, oracle_lib.ST_TIME, oracle_lib.ST_AMP, oracle_lib.ST_ABSORB} <= ends
+    assert st["max_gen"] == 3 and st["suppressed_gen"] > 0
+    check_geometry(sc, ev, media=not anomalies)
+    check_tree(sc, rec, st, ev)
