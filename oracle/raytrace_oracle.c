@@ -553,6 +553,22 @@ static double departure_rate(const scene_t* S, const ray_t* r, int k) {
   return side_sign(r, k) * c;
 }
 
+/* Start value of the return search of a ray leaving boundary k: rate * len,
+ * the distance from the boundary a straight departure would gain over the
+ * step; inside a sphere, where a straight line leaving the wall at cosine
+ * rate meets it again after the chord 2 R rate, the value that puts the
+ * first false-position iterate at that chord when it lies inside the step
+ * (exact for a straight ray, as in a void of constant index). */
+static double departure_start(const scene_t* S, const ray_t* r, int k, double rate,
+                              double len, double G1) {
+  const bplane_t* b = &S->pl[k];
+  if (b->shape == ORC_SHAPE_SPHERE && side_sign(r, k) < 0.0) {
+    const double chord = 2.0 * b->param * rate;
+    if (chord < len) return -G1 * chord / (len - chord);
+  }
+  return rate * len;
+}
+
 /* The crossing of boundary k on the step [0, len] (G0 = G at the start,
  * G1 <= 0 at the end).  A ray passes a boundary only by going through it
  * (section 2, boundary paragraph).  A ray that starts on the boundary
@@ -560,14 +576,14 @@ static double departure_rate(const scene_t* S, const ray_t* r, int k) {
  * sigma = 0.  One that starts on it and leaves it (after an event, the
  * reflected ray and the secondary do) passes it only where it comes back,
  * e.g. at the far end of a short chord through a sphere.  For that search
- * the start of the bracket takes the value rate * len, the distance from
- * the boundary a straight departure at that rate would gain over the step,
- * in place of G0 ~ 0, which would draw the iterates to the departure point. */
+ * the start of the bracket takes a positive value (departure_start) in
+ * place of G0 ~ 0, which would draw the iterates to the departure point. */
 static double crossing(worker_t* W, const ray_t* r, int k, double G0, double len,
                        double G1, double hp, double ystar[7]) {
   if (G0 > ON_BND) return locate(W, r, k, 0.0, G0, len, G1, hp, ystar);
   const double rate = departure_rate(W->S, r, k);
-  if (rate > 0.0) return locate(W, r, k, 0.0, rate * len, len, G1, hp, ystar);
+  if (rate > 0.0) return locate(W, r, k, 0.0, departure_start(W->S, r, k, rate, len, G1),
+                                len, G1, hp, ystar);
   memcpy(ystar, r->y, 7 * sizeof(double));
   return 0.0;
 }
