@@ -575,6 +575,21 @@ __device__ __forceinline__ double bnd_rate(const KBnd& B, int k, uint32_t side,
   return ((side >> k) & 1u) ? c : -c;
 }
 
+// Start value of the return search of a ray leaving boundary k: rate * len,
+// the distance from the boundary a straight departure would gain over the
+// step; inside a sphere, where a straight line leaving the wall at cosine
+// rate meets it again after the chord 2 R rate, the value that puts the
+// first false-position iterate at that chord when it lies inside the step
+// (exact for a straight ray, as in a void of constant index).
+__device__ __forceinline__ double departure_start(const KBnd& B, int k, uint32_t side,
+                                                  double rate, double len, double G1) {
+  if (B.shape == SH_SPHERE && !((side >> k) & 1u)) {
+    const double chord = 2.0 * B.d * rate;
+    if (chord < len) return -G1 * chord / (len - chord);
+  }
+  return rate * len;
+}
+
 // Earliest (by linear estimate) boundary crossed at the end of a step of
 // length len from y0 to y1, skipping boundary 'skip'; -1 if none.
 __device__ __forceinline__ int pick_crossing(const KParams& P, uint32_t side, const double y0[7],

@@ -423,9 +423,8 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
   // one that starts on it and leaves it (the reflected ray and the
   // secondary after an event) passes it only where it comes back, e.g. at
   // the far end of a short chord through a sphere.  Its bracket starts with
-  // G(0) taken as rate * len, the distance from the boundary a straight
-  // departure at that rate would gain over the step, in place of G(0) ~ 0,
-  // which would draw the iterates to the departure point.
+  // a positive value for G(0) (departure_start) in place of G(0) ~ 0, which
+  // would draw the iterates to the departure point.
   __shared__ double s_a[256], s_Ga[256], s_b[256], s_Gb[256], s_hp[256], s_hn[256];
   __shared__ int32_t s_k[256], s_meta[256];
   __syncthreads();
@@ -675,8 +674,11 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
           s_hn[tid] = hn;
           s_k[tid] = k;
           const bool on = on_boundary(G0);
-          double rate = 0.0;
-          if (__builtin_expect(on, 0)) rate = bnd_rate(s_bnd[k], k, R.side, R.y);
+          double rate = 0.0, Gd = 0.0;
+          if (__builtin_expect(on, 0)) {
+            rate = bnd_rate(s_bnd[k], k, R.side, R.y);
+            Gd = departure_start(s_bnd[k], k, R.side, rate, ht, G1);
+          }
           if (on && !(rate > 0.0)) {  // on the boundary, heading in
             s_meta[tid] = 1;  // pass 0, no iterations, last side 0
             located = true;
@@ -684,7 +686,7 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
 #pragma unroll
             for (int i = 0; i < 7; ++i) y5[i] = R.y[i];
           } else {
-            const double Ga = on ? rate * ht : G0;
+            const double Ga = on ? Gd : G0;
             s_a[tid] = 0.0;
             s_Ga[tid] = Ga;
             s_b[tid] = ht;
@@ -752,15 +754,18 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
         ++pass;
         k = j;
         const bool on = on_boundary(H0);
-        double rate = 0.0;
-        if (__builtin_expect(on, 0)) rate = bnd_rate(s_bnd[k], k, R.side, R.y);
+        double rate = 0.0, Hd = 0.0;
+        if (__builtin_expect(on, 0)) {
+          rate = bnd_rate(s_bnd[k], k, R.side, R.y);
+          Hd = departure_start(s_bnd[k], k, R.side, rate, sig, H1);
+        }
         if (on && !(rate > 0.0)) {
           sig = 0.0;
 #pragma unroll
           for (int i = 0; i < 7; ++i) y5[i] = R.y[i];
           continue;
         }
-        const double Ha = on ? rate * sig : H0;
+        const double Ha = on ? Hd : H0;
         s_k[tid] = k;
         s_a[tid] = 0.0;
         s_Ga[tid] = Ha;
