@@ -55,10 +55,10 @@ BYTES_PER_TRIAL_GRID = 768
 # code: comments and whitespace removed); after a change to the code the
 # traffic is reported as null until measured again.
 TRAFFIC = {  # workload -> (fetch bytes, write bytes, digest)
-    "twolayer": (3.1704e+09, 4.4601e+09,
-                 "4f4e5f27d9049e074e23341616bc1c23a6c83f33d1dee3fbf8e03e735f5c2058"),
-    "grid256": (3.3810e+11, 2.5610e+09,
-                "4f4e5f27d9049e074e23341616bc1c23a6c83f33d1dee3fbf8e03e735f5c2058"),
+    "twolayer": (3.0967e+09, 4.4689e+09,
+                 "e49bb62aae513bc6909c0a87957c8d03d49392faef5611ac92e48678d5f8d9e6"),
+    "grid256": (3.3721e+11, 2.5610e+09,
+                "e49bb62aae513bc6909c0a87957c8d03d49392faef5611ac92e48678d5f8d9e6"),
 }
 TRACE_SOURCES = ("rt_kernels.hip", "rt_device.hpp", "rt_params.hpp")
 
