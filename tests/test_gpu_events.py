@@ -136,3 +136,23 @@ def test_events_across_interrupt_and_resume(gpu):
     assert st["events"] == bst["events"] and st["events_lost"] == 0
     for f in ev:
         assert np.array_equal(ev[f], bev[f]), f
+
+
+def test_events_full_size_sampled(gpu, oracle_lib):
+    """The benchmark workload at full size (1,048,576 primaries, four
+    generations, 5.8e6 events) with event records on: the records and events
+    of 512 evenly spaced primaries' trees against the oracle's."""
+    sc = W.two_layer()
+    _announce("events-twolayer-full", sc)
+    got, gst, gev = gpu.trace(sc, ev_capacity=8 << 20)
+    assert gst["events_lost"] == 0 and len(gev["key"]) == gst["events"]
+    roots = np.arange(0, sc.n_rays, sc.n_rays // 512, dtype=np.int64)
+    ref, rst, rev = oracle_lib.trace(sc, roots=roots, events=True)
+    sel = np.isin((got["key"] >> np.uint64(24)).astype(np.int64), roots)
+    sub = {f: a[sel] for f, a in got.items()}
+    esel = np.isin((gev["key"] >> np.uint64(24)).astype(np.int64), roots)
+    esub = {f: a[esel] for f, a in gev.items()}
+    compare(sub, ref, sc.limits.tol, label="events-twolayer-full")
+    summ = compare_events(esub, rev, sub, ref, label="events-twolayer-full")
+    print(f"[gpu-case] events-twolayer-full: {summ}", flush=True)
+    assert summ["events"] == len(rev["key"]) > 1000
