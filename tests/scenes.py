@@ -1,6 +1,8 @@
-"""Small seeded scenes for tests that use every slot of the descriptor
-tables at once: RT_MAX_REGIONS media, RT_MAX_PLANES boundaries (plus the
-six box faces and the travel-time limit), RT_MAX_ANOMALIES anomalies."""
+"""Small seeded scenes shared by the oracle and GPU tests: one that uses
+every slot of the descriptor tables at once (RT_MAX_REGIONS media,
+RT_MAX_PLANES boundaries plus the six box faces and the travel-time limit,
+RT_MAX_ANOMALIES anomalies), and a single ray crossing a spherical void
+along a chord shorter than its step."""
 import numpy as np
 
 from paper_1810_01780_amd import workloads as W
@@ -45,3 +47,19 @@ def maximal(n_rays=256, anomalies=False, model=W.MODEL_PAPER, seed=7):
                    limits=W.Limits(tol=1e-6, h_min=1e-3, h_max=10.0, s_max=1500.0,
                                    t_max=6e-6, amp_min=1e-4, max_generations=4, model=model),
                    box_lo=(-1000.0, -1000.0, -800.0), box_hi=(1000.0, 1000.0, 1000.0))
+
+
+def void_chord(model, theta_deg=40.0, radius=10.0):
+    """Ice of constant n = 1.5 holding a spherical void (n = 1, radius 10 m,
+    centre at 100 m depth); one ray travels straight down at the impact
+    parameter R sin(theta) and meets the void at incidence theta."""
+    b = radius * np.sin(np.radians(theta_deg))
+    regions = [W.Region(a=1.5, z_top=-np.inf, z_bot=np.inf),
+               W.Region(a=1.0, z_top=np.inf, z_bot=np.inf)]
+    planes = [W.Plane(point=(0.0, 0.0, 100.0), normal=(0.0, 0.0, 1.0), region_pos=0,
+                      region_neg=1, shape=W.SHAPE_SPHERE, param=radius)]
+    return W.Scene(name="void-chord", regions=regions, planes=planes,
+                   sources=np.array([[b, 0.0, 50.0]]), ray_src=np.zeros(1, np.int32),
+                   dirs=np.array([[0.0, 0.0, 1.0]]),
+                   limits=W.Limits(tol=1e-6, h_min=1e-3, h_max=10.0, s_max=60.0,
+                                   max_generations=2, model=model))

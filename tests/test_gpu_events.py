@@ -11,8 +11,7 @@ from paper_1810_01780_amd import workloads as W
 
 from .event_checks import check_geometry, check_tree
 from .parity import compare, compare_events, event_pairs, sort_by_key
-from .scenes import maximal
-from .test_oracle_events import _void_chord_scene
+from .scenes import maximal, void_chord
 
 pytestmark = pytest.mark.gpu
 
@@ -39,8 +38,8 @@ CASES = {
     "curved-fresnel-bed": lambda: W.curved(rays_per_source=128, bed_kind=W.PLANE_FRESNEL),
     "paper-example-cuts": lambda: W.paper_example(n_rays=256),
     "field3d": lambda: W.field3d(rays_per_source=128),
-    "void-chord-paper": lambda: _void_chord_scene(W.MODEL_PAPER),
-    "void-chord-exact": lambda: _void_chord_scene(W.MODEL_EXACT),
+    "void-chord-paper": lambda: void_chord(W.MODEL_PAPER),
+    "void-chord-exact": lambda: void_chord(W.MODEL_EXACT),
     # every descriptor slot in use: 8 media, 16 boundaries + box + time limit
     "maximal-tables": lambda: maximal(),
     "maximal-tables-anomalies-exact": lambda: maximal(anomalies=True, model=W.MODEL_EXACT),

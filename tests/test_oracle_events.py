@@ -15,6 +15,7 @@ import pytest
 from paper_1810_01780_amd import workloads as W
 
 from .event_checks import GEN, SPAWNED, TIR, check_geometry, check_tree
+from .scenes import void_chord
 
 N_SURF = 1.78 - 0.43
 W_C0 = 299792458.0
@@ -122,22 +123,6 @@ def test_planted_mistake_is_caught(oracle_lib):
         check_geometry(sc, bad)
 
 
-def _void_chord_scene(model, theta_deg=40.0, radius=10.0):
-    """Ice of constant n = 1.5 holding a spherical void (n = 1, radius 10 m,
-    centre at 100 m depth); one ray travels straight down at the impact
-    parameter R sin(theta) and meets the void at incidence theta."""
-    b = radius * np.sin(np.radians(theta_deg))
-    regions = [W.Region(a=1.5, z_top=-np.inf, z_bot=np.inf),
-               W.Region(a=1.0, z_top=np.inf, z_bot=np.inf)]
-    planes = [W.Plane(point=(0.0, 0.0, 100.0), normal=(0.0, 0.0, 1.0), region_pos=0,
-                      region_neg=1, shape=W.SHAPE_SPHERE, param=radius)]
-    return W.Scene(name="void-chord", regions=regions, planes=planes,
-                   sources=np.array([[b, 0.0, 50.0]]), ray_src=np.zeros(1, np.int32),
-                   dirs=np.array([[0.0, 0.0, 1.0]]),
-                   limits=W.Limits(tol=1e-6, h_min=1e-3, h_max=10.0, s_max=60.0,
-                                   max_generations=2, model=model))
-
-
 @pytest.mark.parametrize("model", [W.MODEL_PAPER, W.MODEL_EXACT])
 def test_short_chord_through_a_void(oracle_lib, model):
     """Closed form in constant media: the refracted secondary crosses the
@@ -146,7 +131,7 @@ def test_short_chord_through_a_void(oracle_lib, model):
     keeps bouncing inside along chords of the same length and incidence (it
     must not stall on the wall it was cast from)."""
     R, c = 10.0, np.array([0.0, 0.0, 100.0])
-    sc = _void_chord_scene(model)
+    sc = void_chord(model)
     rec, st, ev = oracle_lib.trace(sc, events=True)
     th = np.radians(40.0)
     p1 = np.array([R * np.sin(th), 0.0, 100.0 - R * np.cos(th)])
