@@ -55,10 +55,10 @@ BYTES_PER_TRIAL_GRID = 768
 # code: comments and whitespace removed); after a change to the code the
 # traffic is reported as null until measured again.
 TRAFFIC = {  # workload -> (fetch bytes, write bytes, digest)
-    "twolayer": (3.0967e+09, 4.4689e+09,
-                 "e49bb62aae513bc6909c0a87957c8d03d49392faef5611ac92e48678d5f8d9e6"),
-    "grid256": (3.3721e+11, 2.5610e+09,
-                "e49bb62aae513bc6909c0a87957c8d03d49392faef5611ac92e48678d5f8d9e6"),
+    "twolayer": (3.1804e+09, 4.4587e+09,
+                 "bf410121989010093698db940360f57eeb820f75b91e6e86b9cb934a66e39902"),
+    "grid256": (3.3663e+11, 2.5610e+09,
+                "bf410121989010093698db940360f57eeb820f75b91e6e86b9cb934a66e39902"),
 }
 TRACE_SOURCES = ("rt_kernels.hip", "rt_device.hpp", "rt_params.hpp")
 
@@ -440,6 +440,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--ev-capacity", type=int, default=0,
+                    help="record Fresnel events too (rt_event array of this many entries)")
     args = ap.parse_args()
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
 
@@ -461,7 +463,7 @@ def main():
         return bench_surrogate(args, log)
     scene, cfg = make_scene(args.workload)
     log(f"workload {cfg['workload']}: {scene.n_rays} rays")
-    ds = binding.DeviceScene(scene)
+    ds = binding.DeviceScene(scene, ev_capacity=args.ev_capacity)
     hip = _hip()
 
     def event():
@@ -508,6 +510,8 @@ def main():
     roof["kernel"] = "trace_kernel"
     roof["kernel_ms"] = kern_s * 1e3
 
+    if args.ev_capacity:
+        cfg.update(event_records=st["events"])
     cfg.update(trial_steps=trials, accepted_steps=st["accepted"], records=st["records"],
                spawned=st["spawned"])
     value = st["accepted"] * args.steps / wall

@@ -114,6 +114,10 @@ __device__ __forceinline__ uint64_t wave_slot(const KParams& P, int wv) {
   return rank < t1 ? b1 + rank : b2 + (rank - t1);
 }
 
+// Event-record array and its capacity, copied into LDS at kernel start.
+__shared__ rt_event* s_ev_base;
+__shared__ unsigned long long s_ev_cap;
+
 // Reserve consecutive entries of a counter for the calling wave's active
 // lanes (one atomic per wave); returns this lane's index.
 __device__ __forceinline__ uint64_t wave_append(uint64_t* tail) {
@@ -341,9 +345,11 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
     }
   }
   if constexpr (EV) {  // instances that record events run only with ev_capacity > 0
+    // the array and its size come from LDS: kept as kernel arguments they
+    // would occupy scalar registers for the whole step loop
     const uint64_t e = wave_append(&P.q->ev_tail);
-    if (e < (uint64_t)P.ev_capacity) {
-      rt_event* E = P.events + e;
+    if (e < s_ev_cap) {
+      rt_event* E = s_ev_base + e;
       E->key = s_key[tl];
       E->ordinal = R.n_ev;
       E->boundary = k;
@@ -427,6 +433,10 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
   // would draw the iterates to the departure point.
   __shared__ double s_a[256], s_Ga[256], s_b[256], s_Gb[256], s_hp[256], s_hn[256];
   __shared__ int32_t s_k[256], s_meta[256];
+  if (EV && tid == 0) {
+    s_ev_base = P.events;
+    s_ev_cap = (unsigned long long)P.ev_capacity;
+  }
   __syncthreads();
 
   s_nacc[tid] = 0;
