@@ -176,7 +176,7 @@ def cpu_baseline(scene, target_s, threads, log):
         # than half the target is sized again from its own rate, once
         stride = max(1, int(np.ceil(n * per_root / target_s)))
         roots = np.arange(0, n, stride, dtype=np.int64)
-        log(f"cpu baseline: {len(roots)} of {n} roots (every {stride}th), {threads} threads")
+        log(f"cpu baseline: {len(roots)} of {n} roots (one in {stride}), {threads} threads")
         t0 = time.perf_counter()
         _, st = oracle.trace(scene, roots=roots, threads=threads)
         dt = time.perf_counter() - t0
@@ -185,7 +185,7 @@ def cpu_baseline(scene, target_s, threads, log):
         per_root = dt / len(roots)
     return {"value": st["accepted"] / dt, "unit": "ray-steps/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"every {stride}th root ray ({len(roots)} of {n}) with its full "
+            "sample": f"one root ray in {stride} ({len(roots)} of {n}) with its full "
                       f"secondary tree: {st['accepted']} accepted steps in {dt:.1f} s"}
 
 
@@ -201,7 +201,7 @@ def cpu_solve_baseline(sp, target_s, threads, log):
     for attempt in range(2):
         stride = max(1, int(np.ceil(n * per_pair / target_s)))
         pick = np.arange(0, n, stride, dtype=np.int64)
-        log(f"cpu baseline: {len(pick)} of {n} pairs (every {stride}th), {threads} threads")
+        log(f"cpu baseline: {len(pick)} of {n} pairs (one in {stride}), {threads} threads")
         t0 = time.perf_counter()
         oracle.solve(sp.scene, sp.zs, sp.zr, sp.dist, pairs=pick, threads=threads)
         dt = time.perf_counter() - t0
@@ -209,7 +209,7 @@ def cpu_solve_baseline(sp, target_s, threads, log):
             break
         per_pair = dt / len(pick)
     return {"value": len(pick) / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"every {stride}th pair ({len(pick)} of {n}), both families, "
+            "sample": f"one pair in {stride} ({len(pick)} of {n}), both families, "
                       f"in {dt:.1f} s"}
 
 
@@ -507,7 +507,7 @@ def main():
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
                 "traffic": measured_traffic(args.workload)}
-    roof["kernel"] = "trace_kernel"
+    roof["kernel"] = "trace_general_kernel" if is_general(scene) else "trace_strat_kernel"
     roof["kernel_ms"] = kern_s * 1e3
 
     if args.ev_capacity:
