@@ -136,6 +136,13 @@ def is_general(scene):
         for r in scene.regions)
 
 
+def trace_kernel_name(scene):
+    """The trace kernel a launch on this scene runs: gridded and general
+    fields take the general 3-D kernel, depth-stratified ones the
+    stratified kernel (the same test as the C launcher's)."""
+    return "trace_general_kernel" if is_general(scene) else "trace_strat_kernel"
+
+
 def flop_per_trial(scene, region):
     """Algorithmic FP64 work of one trial step of a ray in region (analytic
     media): the method's per-step count for the model, with the boundary
@@ -507,7 +514,7 @@ def main():
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
                 "traffic": measured_traffic(args.workload)}
-    roof["kernel"] = "trace_general_kernel" if is_general(scene) else "trace_strat_kernel"
+    roof["kernel"] = trace_kernel_name(scene)
     roof["kernel_ms"] = kern_s * 1e3
 
     if args.ev_capacity:

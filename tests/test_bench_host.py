@@ -66,3 +66,12 @@ def test_digest_follows_code_not_comments():
     assert bench.kernel_digest(commented) == d
     changed = dict(src, **{f0: src[f0] + "\nint x_ = 1;\n"})
     assert bench.kernel_digest(changed) != d
+
+
+def test_kernel_named_after_the_scene():
+    # the roofline names the kernel that rocprofv3 lists for the workload
+    names = {w: bench.trace_kernel_name(bench.make_scene(w)[0])
+             for w in ("twolayer", "grid256", "curved", "field3d", "fan1024")}
+    assert names == {"twolayer": "trace_strat_kernel", "grid256": "trace_general_kernel",
+                     "curved": "trace_strat_kernel", "field3d": "trace_general_kernel",
+                     "fan1024": "trace_strat_kernel"}
