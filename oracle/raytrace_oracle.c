@@ -530,60 +530,39 @@ static double G_of(const scene_t* S, const ray_t* r, int k, const double y[7]) {
   return sg * bnd_g(S, k, y);
 }
 
-/* Departure rate of a ray standing on boundary k: the cosine between its
- * direction and the normal pointing into its own side (> 0 when it leaves
- * the boundary; -1 for the travel-time limit, which a ray only approaches). */
-static double departure_rate(const scene_t* S, const ray_t* r, int k) {
-  const bplane_t* b = &S->pl[k];
-  if (b->kind == KIND_TIME) return -1.0;
-  double gr[3];
-  if (b->shape == ORC_SHAPE_SPHERE) {
-    for (int i = 0; i < 3; ++i) gr[i] = r->y[i] - b->pt[i];
-  } else if (b->shape == ORC_SHAPE_PARABOLOID) {
-    gr[0] = -2.0 * b->param * (r->y[0] - b->pt[0]);
-    gr[1] = -2.0 * b->param * (r->y[1] - b->pt[1]);
-    gr[2] = 1.0;
-  } else {
-    for (int i = 0; i < 3; ++i) gr[i] = b->nrm[i];
-  }
-  const double* d = r->y + 3;
-  const double gg = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
-  const double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-  const double c = (gr[0] * d[0] + gr[1] * d[1] + gr[2] * d[2]) / sqrt(gg * dd);
-  return side_sign(r, k) * c;
-}
-
-/* Start value of the return search of a ray leaving boundary k: rate * len,
- * the distance from the boundary a straight departure would gain over the
- * step; inside a sphere, where a straight line leaving the wall at cosine
- * rate meets it again after the chord 2 R rate, the value that puts the
- * first false-position iterate at that chord when it lies inside the step
- * (exact for a straight ray, as in a void of constant index). */
-static double departure_start(const scene_t* S, const ray_t* r, int k, double rate,
-                              double len, double G1) {
-  const bplane_t* b = &S->pl[k];
-  if (b->shape == ORC_SHAPE_SPHERE && side_sign(r, k) < 0.0) {
-    const double chord = 2.0 * b->param * rate;
-    if (chord < len) return -G1 * chord / (len - chord);
-  }
-  return rate * len;
+/* True when the ray, standing on boundary k, moves away from it into its
+ * own side: its direction has a positive component along the normal that
+ * points into that side.  A ray only approaches the travel-time limit. */
+static int leaving(const scene_t* S, const ray_t* r, int k) {
+  if (S->pl[k].kind == KIND_TIME) return 0;
+  double nb[3], u[3];
+  bnd_normal(S, k, r->y, nb);
+  unit_direction(r->y, u);
+  return side_sign(r, k) * (u[0] * nb[0] + u[1] * nb[1] + u[2] * nb[2]) > 0.0;
 }
 
 /* The crossing of boundary k on the step [0, len] (G0 = G at the start,
  * G1 <= 0 at the end).  A ray passes a boundary only by going through it
  * (section 2, boundary paragraph).  A ray that starts on the boundary
- * (G0 <= ON_BND) and heads into it passes it at
- * sigma = 0.  One that starts on it and leaves it (after an event, the
- * reflected ray and the secondary do) passes it only where it comes back,
- * e.g. at the far end of a short chord through a sphere.  For that search
- * the start of the bracket takes a positive value (departure_start) in
- * place of G0 ~ 0, which would draw the iterates to the departure point. */
+ * (G0 <= ON_BND) and heads into it passes it at sigma = 0.  One that starts
+ * on it and leaves it (after an event, the reflected ray and the secondary
+ * do) passes it only where it comes back, e.g. at the far end of a short
+ * chord through a sphere: the search then starts from the first of len/2,
+ * len/4, ... at which the ray is clearly on its own side (G > ON_BND), and
+ * the crossing is placed at sigma = 0 when there is none. */
 static double crossing(worker_t* W, const ray_t* r, int k, double G0, double len,
                        double G1, double hp, double ystar[7]) {
   if (G0 > ON_BND) return locate(W, r, k, 0.0, G0, len, G1, hp, ystar);
-  const double rate = departure_rate(W->S, r, k);
-  if (rate > 0.0) return locate(W, r, k, 0.0, departure_start(W->S, r, k, rate, len, G1),
-                                len, G1, hp, ystar);
+  if (leaving(W->S, r, k)) {
+    double a = len, dl[7];
+    for (int it = 0; it < LOC_MAXIT; ++it) {
+      a *= 0.5;
+      orc_ck_trial(W->S->P, r->region, r->y, a, ystar, dl);
+      W->st.relocation++;
+      const double Ga = G_of(W->S, r, k, ystar);
+      if (Ga > ON_BND) return locate(W, r, k, a, Ga, len, G1, hp, ystar);
+    }
+  }
   memcpy(ystar, r->y, 7 * sizeof(double));
   return 0.0;
 }
