@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define RT_ABI_VERSION 5
+#define RT_ABI_VERSION 6
 #define RT_MAX_REGIONS 8
 #define RT_MAX_PLANES 16
 #define RT_MAX_ANOMALIES 8
@@ -338,6 +338,34 @@ rt_status raytrace_launch(const rt_field* field,
                           const rt_step_limits* limits, rt_outputs* out,
                           void* workspace, size_t workspace_bytes,
                           void* stream, const rt_tuning* tuning);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * launch as raytrace_launch with the same arguments and results, minus the
+ * workspace.  Its scratch memory (queue counters, the shared queue of
+ * record slots, the hand-out order and, for gridded fields, the prepared
+ * grid: rt_workspace_bytes of it) is a device array of
+ * RT_STATIC_SCRATCH_BYTES inside the library, one per GPU, held from the
+ * first call on that GPU until the process ends.  The call allocates
+ * nothing: no hipMalloc, no hipFree, no allocating library routine; it
+ * enqueues kernels on 'stream' like raytrace_launch.  A launch whose
+ * rt_workspace_bytes(field, out->capacity) exceeds RT_STATIC_SCRATCH_BYTES
+ * (about 8.3 million record slots for analytic fields, fewer with a grid)
+ * returns RT_ERR_UNSUPPORTED without enqueuing anything.  Every call on a GPU
+ * shares that GPU's array, which keeps the last call's contents (each launch
+ * re-initialises what it reads): calls that overlap on one GPU, on any
+ * streams, race and must not be issued; resume = 1 continues the last
+ * static launch on that GPU, so no other static launch may run on it in
+ * between.  The first call on a device looks up the array's device address
+ * (hipGetSymbolAddress) with that device current; RT_ERR_DEVICE when that
+ * fails. */
+#define RT_STATIC_SCRATCH_BYTES (64ull << 20)
+rt_status raytrace_launch_static(const rt_field* field,
+                                 const rt_boundaries* boundaries,
+                                 const rt_sources* sources,
+                                 const rt_directions* directions, double tol,
+                                 const rt_step_limits* limits, rt_outputs* out,
+                                 void* stream, const rt_tuning* tuning);
 
 /* Map the statistics of a finished launch to a status: RT_ERR_DEVICE when
  * the scheduler reported an error, RT_ERR_INVALID_ARG when input rays were

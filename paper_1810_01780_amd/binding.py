@@ -221,6 +221,12 @@ def lib() -> C.CDLL:
                                       C.POINTER(rt_sources), C.POINTER(rt_directions), C.c_double,
                                       C.POINTER(rt_step_limits), C.POINTER(rt_outputs),
                                       C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(rt_tuning)]
+        L.raytrace_launch_static.restype = C.c_int
+        L.raytrace_launch_static.argtypes = [C.POINTER(rt_field), C.POINTER(rt_boundaries),
+                                             C.POINTER(rt_sources), C.POINTER(rt_directions),
+                                             C.c_double, C.POINTER(rt_step_limits),
+                                             C.POINTER(rt_outputs), C.c_void_p,
+                                             C.POINTER(rt_tuning)]
         L.rt_collect.restype = C.c_int
         L.rt_collect.argtypes = [C.POINTER(rt_stats), C.c_int64]
         L.rt_last_error.restype = C.c_char_p
@@ -317,6 +323,17 @@ def raytrace_launch(field, boundaries, sources, directions, tol, limits, outputs
         C.c_void_p(stream), C.byref(tuning) if tuning is not None else None))
 
 
+def raytrace_launch_static(field, boundaries, sources, directions, tol, limits, outputs,
+                           stream, tuning=None) -> int:
+    return int(lib().raytrace_launch_static(C.byref(field), C.byref(boundaries),
+                                            C.byref(sources), C.byref(directions), tol,
+                                            C.byref(limits), C.byref(outputs), stream,
+                                            C.byref(tuning) if tuning is not None else None))
+
+
+RT_STATIC_SCRATCH_BYTES = 64 << 20
+
+
 def rt_collect(stats, capacity: int) -> int:
     return int(lib().rt_collect(C.byref(stats), C.c_int64(capacity)))
 
@@ -376,7 +393,7 @@ class DeviceScene:
     tensors on cuda:0 by default), reusable across launches."""
 
     def __init__(self, scene: W.Scene, capacity: Optional[int] = None, device="cuda",
-                 ev_capacity: int = 0):
+                 ev_capacity: int = 0, static_scratch: bool = False):
         import torch
         self.torch = torch
         self.scene = scene
@@ -413,7 +430,12 @@ class DeviceScene:
                                    self.events_dev.data_ptr() if self.ev_capacity else None,
                                    self.ev_capacity]))
         self.ws_bytes = rt_workspace_bytes(self.desc.field, self.capacity)
-        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        # static_scratch: launches use raytrace_launch_static, whose scratch
+        # is the library's own device array (no workspace is allocated)
+        self.static_scratch = static_scratch
+        self.workspace = None
+        if not static_scratch:
+            self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
 
     def launch(self, stream=None, tuning: Optional[rt_tuning] = None, resume: bool = False) -> None:
         """Enqueue one trace on the stream (torch's current stream by default);
@@ -423,10 +445,15 @@ class DeviceScene:
             stream = torch.cuda.current_stream(self.device)
         self.desc.limits.resume = 1 if resume else 0
         try:
-            st = raytrace_launch(self.desc.field, self.desc.bnd, self.desc.sources,
-                                 self.desc.dirs, self.desc.tol, self.desc.limits, self.out,
-                                 self.workspace.data_ptr(), self.ws_bytes, stream.cuda_stream,
-                                 tuning)
+            if self.static_scratch:
+                st = raytrace_launch_static(self.desc.field, self.desc.bnd, self.desc.sources,
+                                            self.desc.dirs, self.desc.tol, self.desc.limits,
+                                            self.out, stream.cuda_stream, tuning)
+            else:
+                st = raytrace_launch(self.desc.field, self.desc.bnd, self.desc.sources,
+                                     self.desc.dirs, self.desc.tol, self.desc.limits, self.out,
+                                     self.workspace.data_ptr(), self.ws_bytes,
+                                     stream.cuda_stream, tuning)
         finally:
             self.desc.limits.resume = 0
         if st != RT_OK:

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "rt_device.hpp"
 
@@ -1254,12 +1255,15 @@ hipError_t launch_compaction(const KParams& P, unsigned cap_blocks, hipStream_t 
     }                                                                         \
   } while (0)
 
-extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries* bnd,
-                                     const rt_sources* src, const rt_directions* dirs, double tol,
-                                     const rt_step_limits* L, rt_outputs* out, void* workspace,
-                                     size_t workspace_bytes, void* stream,
-                                     const rt_tuning* tuning) {
-  using namespace rt;
+namespace rt {
+namespace {
+
+// Body of raytrace_launch and raytrace_launch_static: everything after the
+// caller's scratch memory has been chosen.
+rt_status launch_trace(const rt_field* field, const rt_boundaries* bnd, const rt_sources* src,
+                       const rt_directions* dirs, double tol, const rt_step_limits* L,
+                       rt_outputs* out, void* workspace, size_t workspace_bytes, void* stream,
+                       const rt_tuning* tuning) {
   rt_status st = validate(field, bnd, src, dirs, tol, L);
   if (st != RT_OK) return st;
   if (!out || !out->stats || !workspace) {
@@ -1491,4 +1495,76 @@ extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries*
   hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, P);
   HIP_TRY(hipGetLastError());
   return RT_OK;
+}
+
+// Scratch memory of raytrace_launch_static, a file-scope device array: every
+// GPU the library runs on holds its own copy, at its own address, until the
+// process ends.  In host code 'scratch' names a host-side stand-in, never the
+// device memory: the device address comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+__device__ __align__(256) unsigned char scratch[RT_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+rt_status static_scratch(void** ptr) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_last_error("device %d beyond the %d devices the static scratch supports", dev,
+                   kMaxDevices);
+    return RT_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) {
+      set_last_error("hipGetSymbolAddress returned no address for the static scratch");
+      return RT_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return RT_OK;
+}
+
+}  // namespace
+}  // namespace rt
+
+extern "C" rt_status raytrace_launch(const rt_field* field, const rt_boundaries* bnd,
+                                     const rt_sources* src, const rt_directions* dirs, double tol,
+                                     const rt_step_limits* L, rt_outputs* out, void* workspace,
+                                     size_t workspace_bytes, void* stream,
+                                     const rt_tuning* tuning) {
+  return rt::launch_trace(field, bnd, src, dirs, tol, L, out, workspace, workspace_bytes, stream,
+                          tuning);
+}
+
+extern "C" rt_status raytrace_launch_static(const rt_field* field, const rt_boundaries* bnd,
+                                            const rt_sources* src, const rt_directions* dirs,
+                                            double tol, const rt_step_limits* L,
+                                            rt_outputs* out, void* stream,
+                                            const rt_tuning* tuning) {
+  using namespace rt;
+  rt_status st = validate(field, bnd, src, dirs, tol, L);
+  if (st != RT_OK) return st;
+  if (!out) {
+    set_last_error("null outputs");
+    return RT_ERR_INVALID_ARG;
+  }
+  size_t need = 0;
+  st = rt_workspace_bytes(field, out->capacity, &need);
+  if (st != RT_OK) return st;
+  if (need > (size_t)RT_STATIC_SCRATCH_BYTES) {
+    set_last_error("launch needs %zu bytes of scratch; the static scratch holds %zu "
+                   "(use raytrace_launch with a workspace)",
+                   need, (size_t)RT_STATIC_SCRATCH_BYTES);
+    return RT_ERR_UNSUPPORTED;
+  }
+  void* ws = nullptr;
+  st = static_scratch(&ws);
+  if (st != RT_OK) return st;
+  return launch_trace(field, bnd, src, dirs, tol, L, out, ws, need, stream, tuning);
 }
