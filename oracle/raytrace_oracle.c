@@ -58,10 +58,13 @@ static const double CK_E[6] = {-277.0 / 64512.0, 0.0, 6925.0 / 370944.0,
 #define SHRINK_MIN 0.1
 #define ERRCON 1.889568e-4 /* (0.9/5)^5 */
 
-/* Crossing search: Illinois false position until |g| <= LOC_GTOL metres, the
- * bracket is narrower than LOC_WREL times the step, or LOC_MAXIT trials. */
-#define LOC_GTOL 1e-10
-#define LOC_WREL 1e-14
+/* Crossing search: Illinois false position until the bracket on the step
+ * parameter is narrower than LOC_WREL times the step, g is exactly zero, or
+ * LOC_MAXIT trials.  The stop is on the bracket, not on |g|: a ray that
+ * meets a boundary at grazing incidence changes g by little along its path,
+ * and a small |g| would leave the crossing point undetermined along the ray
+ * (by |g| / |dg/dsigma|). */
+#define LOC_WREL 1e-12
 #define LOC_MAXIT 60
 #define LOC_MAXPASS 8 /* re-searches for an earlier crossing of another plane */
 #define ON_BND 0x1p-33 /* a step starts on a boundary when G0 <= 2^-33 m */
@@ -508,7 +511,7 @@ static double locate(worker_t* W, const ray_t* r, int k, double a, double Ga,
     orc_ck_trial(S->P, r->region, r->y, c, ystar, dl);
     W->st.relocation++;
     double Gc = sg * bnd_g(S, k, ystar);
-    if (fabs(Gc) <= LOC_GTOL) break;
+    if (Gc == 0.0) break;
     if (Gc < 0.0) {
       b = c;
       Gb = Gc;

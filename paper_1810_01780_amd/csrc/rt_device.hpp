@@ -474,8 +474,11 @@ __device__ __forceinline__ void trial_3d(const KParams& P, const Medium& M, cons
 // [h_min, h_max].
 constexpr double kSafety = 0.9, kGrowMax = 5.0, kShrinkMin = 0.1;
 constexpr double kErrCon = 1.889568e-4;
-// Crossing search (Illinois false position) limits.
-constexpr double kLocGTol = 1e-10, kLocWRel = 1e-14;
+// Crossing search (Illinois false position) limits: it stops when the
+// bracket on the step parameter is narrower than kLocWRel times the step, or
+// when |g| <= kLocGTol, which is 0: only an exact zero, since at grazing
+// incidence a small |g| leaves the crossing undetermined along the ray.
+constexpr double kLocGTol = 0.0, kLocWRel = 1e-12;
 constexpr int kLocMaxIt = 60, kLocMaxPass = 8, kMaxEvents = 255;
 // A step starts on a boundary when G0 <= 2^-33 m (~1.2e-10 m, about the
 // search tolerance), tested as G0 * 2^33 <= 1 with immediate operands only

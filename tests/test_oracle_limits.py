@@ -36,7 +36,12 @@ from .test_oracle_pins import C0, exp_profile, launch, ray_integrals, scene
 # ---------------------------------------------------------------------------
 # Travel-time limit
 # ---------------------------------------------------------------------------
-TIME_C0 = ("return (S->P->t_max - y[6]) * C0;", "return (S->P->t_max - y[6]);")
+TIME_MISTAKES = {
+    # travel time integrated as path / c0, dropping the index
+    "no-index": ("  f[6] = n / C0;", "  f[6] = 1.0 / C0;"),
+    # the time 'distance' with its sign flipped
+    "sign": ("return (S->P->t_max - y[6]) * C0;", "return (y[6] - S->P->t_max) * C0;"),
+}
 
 
 @pytest.mark.parametrize("model", [W.MODEL_PAPER, W.MODEL_EXACT])
@@ -84,10 +89,13 @@ def test_time_limit_firn_closed_form(oracle_lib, theta_up):
     assert rec["s"][0] == pytest.approx(L, abs=1e-6)
 
 
-def test_time_limit_pins_catch_a_dropped_c0():
-    """With the travel-time 'distance' left in seconds (no c0 factor) the
-    search stops ~1e-10 s early or late: the firn pin fails."""
-    with mutant(*TIME_C0) as bad:
+@pytest.mark.parametrize("mistake", list(TIME_MISTAKES))
+def test_time_limit_pins_catch_planted_mistakes(mistake):
+    """Travel time integrated without the index, or the limit's sign
+    flipped: the constant-medium and firn pins fail."""
+    with mutant(*TIME_MISTAKES[mistake]) as bad:
+        with pytest.raises(AssertionError):
+            test_time_limit_constant_medium(bad, W.MODEL_PAPER)
         with pytest.raises(AssertionError):
             for th in (120.0, 150.0, 175.0):
                 test_time_limit_firn_closed_form(bad, th)
