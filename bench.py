@@ -168,16 +168,31 @@ def trial_flops(scene, rec, trials):
     return w * trials / max(1.0, float(n.sum()))
 
 
-def cpu_baseline(scene, target_s, threads, log):
-    """Time the CPU oracle on an evenly strided sample of the root rays."""
+def host_cpu():
+    """(logical CPUs this process may use, all logical CPUs, CPU model)."""
+    allowed = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return allowed or os.cpu_count() or 1, os.cpu_count() or 1, model
+
+
+def _oracle_rate(scene, threads, target_s, log):
+    """Accepted steps/s of the oracle on an evenly strided sample of root rays
+    sized for about target_s seconds: (rate, description of the sample)."""
     import numpy as np
     import oracle
     n = scene.n_rays
     probe = np.arange(0, n, max(1, n // 512), dtype=np.int64)
     t0 = time.perf_counter()
     _, st = oracle.trace(scene, roots=probe, threads=threads)
-    dt = time.perf_counter() - t0
-    per_root = dt / len(probe)
+    per_root = (time.perf_counter() - t0) / len(probe)
     for attempt in range(2):
         # the probe is short and its time noisy: a sample that ran for less
         # than half the target is sized again from its own rate, once
@@ -190,10 +205,22 @@ def cpu_baseline(scene, target_s, threads, log):
         if dt >= 0.5 * target_s or stride == 1:
             break
         per_root = dt / len(roots)
-    return {"value": st["accepted"] / dt, "unit": "ray-steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"one root ray in {stride} ({len(roots)} of {n}) with its full "
-                      f"secondary tree: {st['accepted']} accepted steps in {dt:.1f} s"}
+    return st["accepted"] / dt, (f"one root ray in {stride} ({len(roots)} of {n}) with its "
+                                 f"full secondary tree: {st['accepted']} accepted steps in "
+                                 f"{dt:.1f} s")
+
+
+def cpu_baseline(scene, target_s, max_threads, log):
+    """The CPU oracle on the host: one thread, then every core this process
+    may use (at most max_threads), each on its own strided sample of root
+    rays sized for about target_s / 2 seconds."""
+    allowed, nproc, model = host_cpu()
+    threads = max(1, min(allowed, max_threads))
+    one, one_sample = _oracle_rate(scene, 1, 0.4 * target_s, log)
+    rate, sample = _oracle_rate(scene, threads, 0.6 * target_s, log)
+    return {"value": rate, "unit": "ray-steps/s", "cores": threads, "kind": "oracle",
+            "sample": sample, "one_thread": {"value": one, "sample": one_sample},
+            "host": {"cpus_allowed": allowed, "nproc": nproc, "model": model}}
 
 
 def cpu_solve_baseline(sp, target_s, threads, log):
@@ -307,7 +334,7 @@ def bench_solve(args, log):
            "data": "synthetic", "config": cfg, "roofline": roof}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_solve_baseline(sp, args.cpu_seconds,
-                                                 min(args.cpu_threads, os.cpu_count() or 1), log)
+                                                 min(args.cpu_threads, host_cpu()[0]), log)
     print(json.dumps(out), flush=True)
 
 
@@ -406,7 +433,7 @@ def bench_surrogate(args, log):
            "config": cfg, "roofline": roof}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_solve_baseline(sp, args.cpu_seconds,
-                                                 min(args.cpu_threads, os.cpu_count() or 1), log)
+                                                 min(args.cpu_threads, host_cpu()[0]), log)
     print(json.dumps(out), flush=True)
 
 
@@ -445,8 +472,9 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-threads", type=int, default=16,
+                    help="at most this many oracle threads (one GPU's share of a box's CPUs)")
     ap.add_argument("--ev-capacity", type=int, default=0,
                     help="record Fresnel events too (rt_event array of this many entries)")
     args = ap.parse_args()
@@ -528,8 +556,7 @@ def main():
            "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": cfg,
            "roofline": roof}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(scene, args.cpu_seconds,
-                                           min(args.cpu_threads, os.cpu_count() or 1), log)
+        out["cpu_baseline"] = cpu_baseline(scene, args.cpu_seconds, args.cpu_threads, log)
     print(json.dumps(out), flush=True)
 
 

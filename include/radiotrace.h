@@ -297,17 +297,29 @@ typedef struct {
                                -1 = none, else 1..1024 */
 } rt_tuning;
 
-/* ABI version (RT_ABI_VERSION of the built library). */
+/* ABI version (RT_ABI_VERSION of the built library).  Plumbing: no
+ * counterpart in the paper. */
 int32_t rt_abi_version(void);
 
-/* Host-only validation of the descriptors (no device access): null pointers,
- * counts and limits (1 <= n_regions <= RT_MAX_REGIONS, n_planes <=
- * RT_MAX_PLANES, region indices in range, a zero plane normal, tol > 0,
- * 0 < h_min <= h_max, h_init >= 0, s_max > 0, t_max >= 0, amp_min >= 0,
- * 1 <= max_generations <= RT_MAX_GENERATIONS, model known, max_steps >= 1,
- * grid dims >= 2 and spacing > 0 when a region uses the grid, box lo < hi).
- * Per-ray checks need the device data and happen in raytrace_launch (rays
- * flagged RT_ST_INVALID, counted in stats.invalid). */
+/* Host-only validation of the descriptors of a trace (the media, boundaries
+ * and limits of section 2's set-ups: refractive-index fields, boundaries,
+ * tolerance and minimum step of the accuracy discussion, the travel-time
+ * and amplitude limits of the Fig. 1 example): null pointers, counts and
+ * limits (1 <= n_regions <= RT_MAX_REGIONS, n_planes <= RT_MAX_PLANES, region
+ * indices in range, a zero plane normal, tol > 0, 0 < h_min <= h_max,
+ * h_init >= 0, s_max > 0, t_max >= 0, amp_min >= 0, 1 <= max_generations <=
+ * RT_MAX_GENERATIONS, model known, max_steps >= 1, grid dims >= 2 and
+ * spacing > 0 when a region uses the grid, box lo < hi).  Reads only host
+ * memory: the descriptor structs and the host tables they point to.
+ * Returns RT_OK or RT_ERR_INVALID_ARG / RT_ERR_UNSUPPORTED with a message in
+ * rt_last_error().
+ * The checks of single rays -- a zero or non-finite direction, a source
+ * index out of range, a source within 1e-9 m of a boundary or outside the
+ * box -- are not made here: sources and directions are device arrays, which
+ * this host-only call never reads (a copy to the host would serialise the
+ * caller's stream).  raytrace_launch makes them on the device, per ray: such
+ * a ray is not traced, its record gets RT_ST_INVALID, stats.invalid counts
+ * it and rt_collect reports RT_ERR_INVALID_ARG. */
 rt_status rt_validate(const rt_field* field, const rt_boundaries* boundaries,
                       const rt_sources* sources,
                       const rt_directions* directions, double tol,
@@ -318,10 +330,22 @@ rt_status rt_validate(const rt_field* field, const rt_boundaries* boundaries,
  * for secondaries shared between waves), the order in which the primaries
  * are handed out (4 bytes per record: by source, then by direction, so that
  * the lanes of a wave follow nearby paths), plus the prepared grid (16 bytes
- * per node) for gridded fields. */
+ * per node) for gridded fields.  Plumbing of the persistent scheduler, no
+ * counterpart in the paper; it takes the field and the record capacity
+ * because nothing else sets the size (the ray count only bounds the
+ * capacity from below).  RT_ERR_INVALID_ARG for a null field or bytes, a
+ * negative capacity, or grid dims below 2. */
 rt_status rt_workspace_bytes(const rt_field* field, int64_t capacity, size_t* bytes);
 
-/* Trace all primary rays and every secondary they cast.  Asynchronous on
+/* Trace all primary rays and every secondary they cast: section 2 of the
+ * paper -- the ray equation (eq. 2, or eq. 1 with RT_MODEL_EXACT)
+ * integrated by the Cash-Karp method with adaptive steps set by tol and the
+ * minimum step; at every boundary a ray passes, reflection of the ray and a
+ * refracted secondary cast from the intersection point, both with Fresnel
+ * amplitudes (boundary paragraph); the limits of the Fig. 1 example.  The
+ * record of each ray (final position and direction, path length, travel
+ * time, amplitudes, step and event counts) goes to caller-owned device
+ * arrays in 'out' (SoA, see rt_outputs).  Asynchronous on
  * 'stream' (a hipStream_t; NULL = the default stream): it validates the
  * descriptors, prepares the grid, writes the primaries into the record slots
  * and runs the persistent trace kernel, then returns RT_OK.  Conditions found
@@ -367,7 +391,8 @@ rt_status raytrace_launch_static(const rt_field* field,
                                  const rt_step_limits* limits, rt_outputs* out,
                                  void* stream, const rt_tuning* tuning);
 
-/* Map the statistics of a finished launch to a status: RT_ERR_DEVICE when
+/* Plumbing, no counterpart in the paper.  Map the statistics of a finished
+ * launch to a status: RT_ERR_DEVICE when
  * the scheduler reported an error, RT_ERR_INVALID_ARG when input rays were
  * invalid, RT_ERR_CAPACITY when stats.needed exceeds
  * capacity (records of the slots below capacity are still valid; relaunch
@@ -381,7 +406,9 @@ rt_status raytrace_launch_static(const rt_field* field,
  * launch. */
 rt_status rt_collect(const rt_stats* host_stats, int64_t capacity);
 
-/* Message for the last non-OK status returned on the calling thread. */
+/* Message for the last non-OK status returned on the calling thread (a
+ * thread-local buffer owned by the library, valid until the thread's next
+ * call).  Plumbing, no counterpart in the paper. */
 const char* rt_last_error(void);
 
 #ifdef __cplusplus

@@ -49,7 +49,10 @@ extern "C" {
 #define RT_MLP_OUT 10
 #define RT_MLP_TARGETS 8
 
-/* Number of FP32 parameters (201,482). */
+/* The surrogate network has no counterpart in the paper: it accelerates the
+ * receiver/emitter set-ups of section 2 by seeding the shooting solver, and
+ * every solution it seeds is verified by a trace (or solved by the tracer).
+ * Number of FP32 parameters (201,482). */
 int64_t rt_mlp_param_count(void);
 
 /* Workspace bytes for batches of up to 'batch' rows; training != 0 adds the

@@ -135,7 +135,12 @@ typedef struct {
   rt_solve_stats* stats; /* device, one struct; overwritten by each call */
 } rt_shot_outputs;
 
-/* Host-only checks of a solve or shoot set-up: the field, boundaries and
+/* Emitter -> receiver solves: section 2 lists receiver and emitter
+ * locations among the set-ups the software supports; the paper gives no
+ * solver, and the shooting method here (scan of launch angles, Illinois
+ * refinement of the miss at the receiver, first-arrival selection) is this
+ * library's construction on top of the trace of section 2.
+ * Host-only checks of a solve or shoot set-up: the field, boundaries and
  * limits as in rt_validate (t_max must be 0 and has_box 0: shots end at the
  * receiver plane; s_max, amp_min and max_generations are not used), at
  * least one plane, planes[0] of kind RT_PLANE_FRESNEL (the surface), and
@@ -144,7 +149,8 @@ typedef struct {
 rt_status rt_solve_validate(const rt_field* field, const rt_boundaries* boundaries, double tol,
                             const rt_step_limits* limits, const rt_solve_params* params);
 
-/* Device workspace bytes for a solve of n_pairs pairs: counters, the scan's
+/* Plumbing of the solver, no counterpart in the paper.  Device workspace
+ * bytes for a solve of n_pairs pairs: counters, the scan's
  * miss table (8 bytes per pair, family and angle) and the per-bracket
  * results (80 bytes per pair, family and bracket), plus the prepared grid
  * (16 bytes per node) for gridded fields.  shoot needs the same with
@@ -152,7 +158,9 @@ rt_status rt_solve_validate(const rt_field* field, const rt_boundaries* boundari
 rt_status rt_solve_workspace_bytes(const rt_field* field, int64_t n_pairs,
                                    const rt_solve_params* params, size_t* bytes);
 
-/* Solve every pair for both families.  Asynchronous on 'stream': a counter
+/* Solve every pair for both families (the receiver/emitter set-up of
+ * section 2, by shooting).  Caller-owned device arrays in and out; results
+ * [2 * pair + family].  Asynchronous on 'stream': a counter
  * reset, the scan, the refinement and the selection, each a kernel launch
  * (the scan and refinement kernels are persistent: one shot per lane, lanes
  * take new shots from a ticket counter).  Outputs and the workspace must not
@@ -164,14 +172,17 @@ rt_status raytrace_solve(const rt_field* field, const rt_boundaries* boundaries,
                          const rt_solve_params* params, rt_solve_outputs* out, void* workspace,
                          size_t workspace_bytes, void* stream, const rt_tuning* tuning);
 
-/* Trace an explicit list of shots (the building block of raytrace_solve).
+/* Trace an explicit list of shots (the building block of raytrace_solve):
+ * single-branch traces of section 2 from an emitter at a launch angle to the
+ * receiver plane.
  * Asynchronous on 'stream'; same workspace rules with n_pairs = 0. */
 rt_status raytrace_shoot(const rt_field* field, const rt_boundaries* boundaries, double tol,
                          const rt_step_limits* limits, const rt_shots* shots,
                          rt_shot_outputs* out, void* workspace, size_t workspace_bytes,
                          void* stream, const rt_tuning* tuning);
 
-/* Pick launch tuning for raytrace_solve by measurement: every combination of
+/* Plumbing, no counterpart in the paper.  Pick launch tuning for
+ * raytrace_solve by measurement: every combination of
  * block_size in {64, 128, 192, 256} and refill_threshold in {4, 16, 32, 64}
  * runs raytrace_solve once on 'pairs' (a representative sample; its results
  * land in 'out' and are overwritten by each candidate) after one untimed

@@ -8,20 +8,42 @@ medium, accepted/rejected step counts -- equal.
 The adaptive controller turns a continuous error estimate into an accept or
 reject decision.  The GPU evaluates exp, division and square root with
 different (1-ulp) rounding and contracts products into FMAs, so a trial whose
-error estimate lies within ~1e-12 of the threshold can be decided the other
-way.  Such a ray follows a different but equally valid step sequence and its
-results then differ by about the tolerance.  These "flipped" rays are counted
-(step counts differ) and must be rare; they are held to 10 * tol instead.
+error estimate lies within ~1e-12 of the threshold could be decided the other
+way; such a "flipped" ray would follow a different but equally valid step
+sequence.  Analytic media show none, so by default none is allowed; a caller
+that expects them passes max_flips, and flipped rays are then held to
+10 * tol.
+
+A Fresnel factor is a function of the incidence at its event, which both
+sides know to rounding times the event's conditioning; the amplitude of a
+record is the product of the factors of every event on its path (its own
+and its ancestors' up to its casting), so the amplitude bar is 1e-12 per
+event on that path (1e-12 for a ray without events).
+
+Gridded media (trilinear, C0 gradient) move the direction at the end of a
+ray by more than rounding, and a Fresnel factor moves with the incidence:
+their comparisons pass amp_dir_sens = 10, which adds 10 |du| to the
+amplitude bar of each record (|du| the difference of the final unit
+directions); the records above 1e-12 are counted and reported.  Analytic
+media get no such allowance: the per-event bar alone.
 """
 import numpy as np
 
 POS_REL = 1e-9
 AMP_ABS = 1e-12
-# Fresnel factors are smooth functions of the incidence direction away from
-# the critical angle (|dA/du| of order 1 for ice/air and the firn layers), so
-# two trajectories whose directions differ by |du| may differ in amplitude by
-# about |du|: the amplitude bar is AMP_ABS + AMP_DIR_SENS * |du| per record.
-AMP_DIR_SENS = 10.0
+# allowance per unit direction difference for gridded media (see above)
+AMP_DIR_SENS_GRID = 10.0
+
+
+def events_on_path(rec):
+    """Fresnel events on the path of each record: its own plus, for a
+    secondary, the event ordinals of its ancestors at which each generation
+    was cast (the key's low three bytes)."""
+    key = rec["key"].astype(np.uint64)
+    n = rec["n_ev"].astype(np.int64)
+    for shift in (16, 8, 0):
+        n = n + ((key >> np.uint64(shift)) & np.uint64(0xFF)).astype(np.int64)
+    return n
 
 
 def sort_by_key(rec):
@@ -29,7 +51,7 @@ def sort_by_key(rec):
     return {f: a[order] for f, a in rec.items()}
 
 
-def compare(got, ref, tol, max_flip_frac=1e-3, label=""):
+def compare(got, ref, tol, label="", max_flips=0, amp_dir_sens=0.0):
     """Returns a summary dict; raises AssertionError when a bar is missed."""
     g = sort_by_key(got)
     r = ref  # the oracle returns key order
@@ -43,9 +65,13 @@ def compare(got, ref, tol, max_flip_frac=1e-3, label=""):
     same_steps = (g["n_acc"][gi] == r["n_acc"][ri]) & (g["n_rej"][gi] == r["n_rej"][ri])
     flips = int(np.sum(~same_steps))
     n = len(common)
-    assert missing + extra <= max(2, max_flip_frac * n_ref) * 4, \
-        f"{label}: ray trees differ: {missing} missing, {extra} extra of {n_ref}"
-    assert flips <= max(2, max_flip_frac * n_ref), f"{label}: {flips} of {n} rays flipped"
+    if max_flips == 0:
+        assert missing == 0 and extra == 0, \
+            f"{label}: ray trees differ: {missing} missing, {extra} extra of {n_ref}"
+    else:
+        assert missing + extra <= 4 * max_flips, \
+            f"{label}: ray trees differ: {missing} missing, {extra} extra of {n_ref}"
+    assert flips <= max_flips, f"{label}: {flips} of {n} rays flipped (at most {max_flips})"
 
     s = np.maximum(r["s"][ri], 1.0)
     dpos = np.sqrt((g["x"][gi] - r["x"][ri]) ** 2 + (g["y"][gi] - r["y"][ri]) ** 2
@@ -56,19 +82,30 @@ def compare(got, ref, tol, max_flip_frac=1e-3, label=""):
                             ("as_re", "as_im", "ap_re", "ap_im")]), axis=0)
     du = np.sqrt((g["ux"][gi] - r["ux"][ri]) ** 2 + (g["uy"][gi] - r["uy"][ri]) ** 2
                  + (g["uz"][gi] - r["uz"][ri]) ** 2)
-    amp_excess = damp - (AMP_ABS + AMP_DIR_SENS * du)
+    amp_bar = AMP_ABS * np.maximum(1, events_on_path(r)[ri])
+    amp_excess = damp - (amp_bar + amp_dir_sens * du)
     ok = same_steps
+    plain = ok & (du <= 1e-12) & (amp_dir_sens == 0.0)
     summary = dict(rays=n_ref, common=n, flips=flips, missing=missing, extra=extra,
                    pos=float(dpos[ok].max(initial=0.0)), s=float(ds[ok].max(initial=0.0)),
                    t=float(dt[ok].max(initial=0.0)), amp=float(damp[ok].max(initial=0.0)),
                    dir=float(du[ok].max(initial=0.0)),
-                   amp_excess=float(amp_excess[ok].max(initial=-1.0)))
+                   amp_excess=float(amp_excess[ok].max(initial=-1.0)),
+                   amp_over_1e12=int(np.sum(ok & (damp > AMP_ABS))),
+                   amp_plain=float((damp - amp_bar)[plain].max(initial=-1.0)))
+    if n:
+        w = int(np.argmax(np.where(ok, dpos, -1.0)))
+        summary["worst_pos"] = dict(key=int(r["key"][ri][w]), gen=int(r["gen"][ri][w]),
+                                    status=int(r["status"][ri][w]), n_ev=int(r["n_ev"][ri][w]),
+                                    n_acc=int(r["n_acc"][ri][w]), s=float(r["s"][ri][w]),
+                                    z=float(r["z"][ri][w]), dpos=float(dpos[w]))
     assert np.array_equal(g["status"][gi][ok], r["status"][ri][ok]), f"{label}: status differs"
     assert np.array_equal(g["region"][gi][ok], r["region"][ri][ok]), f"{label}: region differs"
     assert summary["pos"] <= POS_REL, f"{label}: position {summary}"
     assert summary["s"] <= POS_REL, f"{label}: path length {summary}"
     assert summary["t"] <= POS_REL, f"{label}: travel time {summary}"
     assert summary["amp_excess"] <= 0.0, f"{label}: amplitude {summary}"
+    assert summary["amp_plain"] <= 0.0, f"{label}: amplitude {summary}"
     if flips:
         bad = ~ok
         loose = 10 * tol
@@ -84,19 +121,28 @@ def perturbed(scene, eps=1e-15):
     return dataclasses.replace(scene, dirs=scene.dirs * (1.0 + eps * pat))
 
 
-def compare_conditioned(got, ref, ref_pert, tol, label="", ill_factor=10.0, ill_cap=1e-3):
-    """Parity for inputs where the method itself is ill-conditioned.
+def compare_conditioned(got, ref, ref_pert, tol, label="", ill_factor=10.0, ill_cap=1e-3,
+                        amp_dir_sens=0.0, amp_cap=1e-2):
+    """Parity where the method itself is ill-conditioned for some rays.
 
-    In a trilinear (C0-gradient) medium at tight tolerance the step-size
-    controller amplifies rounding-level differences: the oracle run on the
-    same rays with launch directions changed by 1e-15 ('ref_pert') already
-    differs by far more than 1e-9 on some rays.  Rays whose oracle result is
-    stable under that perturbation (same step counts, positions within 1e-11
-    relative) must meet the standard bars.  For the others the GPU deviation
-    from the oracle must be of the same size as the oracle's own deviation
-    under the perturbation: median within ill_factor times the median spread,
-    and every ray within ill_cap relative.  The ray tree and final statuses
-    must agree for every ray.
+    The oracle run on the same rays with launch directions changed by 1e-15
+    ('ref_pert') shows each record's own sensitivity.  Rays whose oracle
+    result is stable under that perturbation -- same step counts, positions
+    within 1e-12 relative, amplitudes within a tenth of their per-event bar
+    -- must meet the standard bars (compare): the GPU's own rounding
+    differences act like a perturbation some 100 times larger, which such a
+    ray turns into at most ~1e-10.  For the others the GPU deviation
+    from the oracle must be of the size of the oracle's own deviation under
+    the perturbation: median within ill_factor times the median spread (or
+    the standard bar, whichever is larger), and every ray within ill_cap
+    relative in position and amp_cap in amplitude (the amplitude of such a
+    ray follows its incidence at each event, which moves with the
+    trajectory: the oracle's own spread reaches a few 1e-3).  This is how a
+    trilinear
+    (C0-gradient) field at tight tolerance, where the step controller
+    amplifies rounding, and rays that graze a boundary many times, whose
+    Fresnel factors are steep in the incidence, are judged.  The ray tree
+    and final statuses must agree for every ray.
     """
     g = sort_by_key(got)
     r, p = ref, ref_pert
@@ -106,25 +152,40 @@ def compare_conditioned(got, ref, ref_pert, tol, label="", ill_factor=10.0, ill_
     s = np.maximum(r["s"], 1.0)
 
     def dpos(a, b):
-        return np.sqrt((a["x"] - b["x"]) ** 2 + (a["y"] - b["y"]) ** 2
-                       + (a["z"] - b["z"]) ** 2) / s
+        return np.maximum(np.sqrt((a["x"] - b["x"]) ** 2 + (a["y"] - b["y"]) ** 2
+                                  + (a["z"] - b["z"]) ** 2) / s, np.abs(a["s"] - b["s"]) / s)
 
-    spread = np.maximum(dpos(p, r), np.abs(p["s"] - r["s"]) / s)
-    stable = (spread <= 1e-11) & (p["n_acc"] == r["n_acc"]) & (p["n_rej"] == r["n_rej"])
+    def damp(a, b):
+        return np.max(np.stack([np.abs(a[f] - b[f]) for f in
+                                ("as_re", "as_im", "ap_re", "ap_im")]), axis=0)
+
+    amp_bar = AMP_ABS * np.maximum(1, events_on_path(r))
+    spread, aspread = dpos(p, r), damp(p, r)
+    stable = ((spread <= 1e-12) & (aspread <= 0.1 * amp_bar)
+              & (p["n_acc"] == r["n_acc"]) & (p["n_rej"] == r["n_rej"]))
     well = {f: a[stable] for f, a in g.items()}
     well_ref = {f: a[stable] for f, a in r.items()}
-    summ = compare(well, well_ref, tol, label=label + "/well-conditioned")
-    dg = np.maximum(dpos(g, r), np.abs(g["s"] - r["s"]) / s)
+    summ = compare(well, well_ref, tol, label=label + "/well-conditioned",
+                   amp_dir_sens=amp_dir_sens)
+    dg, ag = dpos(g, r), damp(g, r)
     ill = ~stable
     summ.update(well_conditioned=int(stable.sum()), ill_conditioned=int(ill.sum()),
                 ill_max_rel=float(dg[ill].max(initial=0.0)),
-                ill_max_spread=float(spread[ill].max(initial=0.0)))
+                ill_max_spread=float(spread[ill].max(initial=0.0)),
+                ill_max_amp=float(ag[ill].max(initial=0.0)),
+                ill_max_amp_spread=float(aspread[ill].max(initial=0.0)))
     if ill.any():
         summ.update(ill_median_rel=float(np.median(dg[ill])),
-                    ill_median_spread=float(np.median(spread[ill])))
+                    ill_median_spread=float(np.median(spread[ill])),
+                    ill_median_amp=float(np.median(ag[ill])),
+                    ill_median_amp_spread=float(np.median(aspread[ill])))
         assert summ["ill_max_rel"] <= ill_cap, f"{label}: ill-conditioned ray beyond cap {summ}"
+        assert summ["ill_max_amp"] <= amp_cap, f"{label}: ill-conditioned amplitude {summ}"
         assert summ["ill_median_rel"] <= ill_factor * max(summ["ill_median_spread"], POS_REL), \
             f"{label}: GPU deviates more than the oracle's own sensitivity {summ}"
+        assert summ["ill_median_amp"] <= ill_factor * max(summ["ill_median_amp_spread"],
+                                                          AMP_ABS), \
+            f"{label}: GPU amplitudes deviate more than the oracle's own sensitivity {summ}"
     return summ
 
 
@@ -137,7 +198,7 @@ def event_pairs(ev):
     return ev["key"].astype(np.uint64) * np.uint64(256) + ev["ordinal"].astype(np.uint64)
 
 
-def compare_events(got_ev, ref_ev, got_rec, ref_rec, label=""):
+def compare_events(got_ev, ref_ev, got_rec, ref_rec, label="", amp_dir_sens=0.0):
     """Event records of the GPU against the oracle's, matched by (key,
     ordinal), for the rays whose step counts agree (see compare): the same
     events exist; boundary, outcome, generation and media are equal; the
@@ -178,8 +239,12 @@ def compare_events(got_ev, ref_ev, got_rec, ref_rec, label=""):
     # the normal turns by |dpos| / R between two nearby points of a surface of
     # curvature radius R (25 m for the smallest, the spherical void)
     assert np.all(dci <= du + dpos * s / 25.0 + 1e-14), f"{label}: incidence cosine {summary}"
-    bar = AMP_ABS + AMP_DIR_SENS * du
+    # the incident amplitude is the product of the Fresnel factors of the
+    # events before this one on the ray's path: 1e-12 per such event
+    prior = {"key": R["key"], "n_ev": R["ordinal"] - 1}
+    bar = AMP_ABS * np.maximum(1, events_on_path(prior)) + amp_dir_sens * du
     assert np.all(damp <= bar), f"{label}: incident amplitudes {summary}"
+    bar = AMP_ABS + amp_dir_sens * du
     # Fresnel coefficients are steep functions of the incidence near the
     # critical angle: their bar adds how far the oracle's coefficients move
     # between the two sides' inputs (n1, n2, cos_i)

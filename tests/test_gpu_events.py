@@ -10,7 +10,7 @@ import pytest
 from paper_1810_01780_amd import workloads as W
 
 from .event_checks import check_geometry, check_tree
-from .parity import compare, compare_events, event_pairs, sort_by_key
+from .parity import AMP_DIR_SENS_GRID, compare, compare_events, event_pairs, sort_by_key
 from .scenes import maximal, void_chord
 
 pytestmark = pytest.mark.gpu
@@ -84,8 +84,9 @@ def test_events_gridded(gpu, oracle_lib):
     ref, rst, rev = oracle_lib.trace(sc, events=True)
     got, gst, gev = gpu.trace(sc, ev_capacity=1 << 14)
     assert gst["events"] > 0 and gst["events_lost"] == 0
-    compare(got, ref, sc.limits.tol, label="grid-events")
-    summ = compare_events(gev, rev, got, ref, label="grid-events")
+    compare(got, ref, sc.limits.tol, label="grid-events", amp_dir_sens=AMP_DIR_SENS_GRID)
+    summ = compare_events(gev, rev, got, ref, label="grid-events",
+                          amp_dir_sens=AMP_DIR_SENS_GRID)
     print(f"[gpu-case] events-gridded: {summ}", flush=True)
     check_geometry(sc, gev, media=False)
     check_tree(sc, sort_by_key(got), gst, gev, amp_tol=1e-14)

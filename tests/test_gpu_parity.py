@@ -11,7 +11,7 @@ import pytest
 
 from paper_1810_01780_amd import workloads as W
 
-from .parity import compare, compare_conditioned, perturbed, sort_by_key
+from .parity import AMP_DIR_SENS_GRID, compare, compare_conditioned, perturbed, sort_by_key
 
 pytestmark = pytest.mark.gpu
 
@@ -66,7 +66,8 @@ def test_two_layer_reduced(gpu, oracle_lib, model):
     sc = W.two_layer(rays_per_source=32, model=model)
     got, gst, ref, rst, s = run_pair(gpu, oracle_lib, sc, f"twolayer-m{model}")
     assert gst["max_gen"] == rst["max_gen"]
-    assert abs(gst["accepted"] - rst["accepted"]) <= 1e-4 * rst["accepted"]
+    for f in ("accepted", "rejected", "events", "spawned", "records"):
+        assert gst[f] == rst[f], f
 
 
 @pytest.mark.parametrize("bed", [W.PLANE_ABSORB, W.PLANE_FRESNEL])
@@ -106,7 +107,8 @@ def test_grid_with_anomalies(gpu, oracle_lib):
     sc = dataclasses.replace(sc, anomalies=[
         W.Anomaly(centre=(0.0, 0.0, 150.0), amplitude=0.05, sigma=25.0, region=1),
         W.Anomaly(centre=(20.0, -10.0, 80.0), amplitude=-0.1, sigma=10.0, region=1)])
-    got, gst, ref, rst, s = run_pair(gpu, oracle_lib, sc, "grid-anomalies")
+    got, gst, ref, rst, s = run_pair(gpu, oracle_lib, sc, "grid-anomalies",
+                                     amp_dir_sens=AMP_DIR_SENS_GRID)
     assert gst["accepted"] == rst["accepted"] and gst["rejected"] == rst["rejected"]
 
 
@@ -129,7 +131,8 @@ def test_gridded_reduced(gpu, oracle_lib):
     got, gst = gpu.trace(sc)
     ref, rst = oracle_lib.trace(sc)
     ref2, _ = oracle_lib.trace(perturbed(sc))
-    summ = compare_conditioned(got, ref, ref2, sc.limits.tol, label="grid-tol1e-7")
+    summ = compare_conditioned(got, ref, ref2, sc.limits.tol, label="grid-tol1e-7",
+                               amp_dir_sens=AMP_DIR_SENS_GRID)
     print(f"[gpu-case] grid-tol1e-7: {summ}", flush=True)
     assert summ["well_conditioned"] > 0.5 * sc.n_rays
     assert abs(gst["accepted"] - rst["accepted"]) <= 1e-3 * rst["accepted"]
@@ -139,7 +142,8 @@ def test_gridded_reduced_tol1e6(gpu, oracle_lib):
     """Same field and rays at tolerance 1e-6, where every ray is well
     conditioned: the standard element-by-element bars."""
     sc = W.gridded(rays_per_source=4, tol=1e-6)
-    got, gst, ref, rst, s = run_pair(gpu, oracle_lib, sc, "grid-tol1e-6")
+    got, gst, ref, rst, s = run_pair(gpu, oracle_lib, sc, "grid-tol1e-6",
+                                     amp_dir_sens=AMP_DIR_SENS_GRID)
     assert gst["accepted"] == rst["accepted"] and gst["rejected"] == rst["rejected"]
 
 
@@ -151,7 +155,8 @@ def test_gridded_small_grid_exact_model(gpu, oracle_lib):
     got, gst = gpu.trace(sc)
     ref, rst = oracle_lib.trace(sc)
     ref2, _ = oracle_lib.trace(perturbed(sc))
-    summ = compare_conditioned(got, ref, ref2, sc.limits.tol, label="grid-small-exact")
+    summ = compare_conditioned(got, ref, ref2, sc.limits.tol, label="grid-small-exact",
+                               amp_dir_sens=AMP_DIR_SENS_GRID)
     print(f"[gpu-case] grid-small-exact: {summ}", flush=True)
     assert summ["well_conditioned"] > 0.5 * sc.n_rays
 
@@ -290,20 +295,46 @@ def test_secondaries_shared_between_waves(gpu, oracle_lib, local_queue):
         assert np.array_equal(a[f], b[f]), f
 
 
-def test_two_layer_full_size_sampled(gpu, oracle_lib):
+def test_two_layer_full_size_all_roots(gpu, oracle_lib):
     """The benchmark workload at full size (1,048,576 primaries, 4
-    generations) in the benchmark's launch configuration; 512 evenly spaced
-    primaries and their whole ray trees are compared with the oracle."""
+    generations) in the benchmark's launch configuration: every record of
+    the GPU (5.8 million) against the oracle's full run, with the launch
+    statistics equal.  The few rays that the oracle itself shows to be
+    sensitive (rays trapped along the 150 m layer at grazing incidence,
+    hundreds of total reflections) are judged against that sensitivity; all
+    others at the standard bars."""
     sc = W.two_layer()
     _announce("twolayer-full", sc)
     got, gst = gpu.trace(sc)
-    roots = np.arange(0, sc.n_rays, sc.n_rays // 512, dtype=np.int64)
-    ref, rst = oracle_lib.trace(sc, roots=roots)
-    sel = np.isin((got["key"] >> np.uint64(24)).astype(np.int64), roots)
-    sub = {f: a[sel] for f, a in got.items()}
-    summ = compare(sub, ref, sc.limits.tol, label="twolayer-full-sample")
+    print("[gpu-case] twolayer-full: GPU done, oracle running", flush=True)
+    ref, rst = oracle_lib.trace(sc)
+    ref2, _ = oracle_lib.trace(perturbed(sc))
+    summ = compare_conditioned(got, ref, ref2, sc.limits.tol, label="twolayer-full")
     print(f"[gpu-case] twolayer-full: {summ}; stats {gst}", flush=True)
     assert gst["records"] == gst["needed"] and gst["sched_errors"] == 0
+    assert summ["well_conditioned"] >= 0.95 * len(ref["key"])
+    for f in ("accepted", "rejected", "events", "spawned", "records", "max_gen",
+              "suppressed_gen", "suppressed_amp", "nonfinite"):
+        assert gst[f] == rst[f], f
+
+
+def test_gridded_full_size_all_roots_tol1e6(gpu, oracle_lib):
+    """The gridded bench field at full size (4,194,304 rays from 256
+    sources) at tolerance 1e-6, where the method is well conditioned for
+    all but a few rays: every record against the oracle's full run, the
+    element-by-element bars for the rays the oracle shows to be stable."""
+    sc = W.gridded(tol=1e-6)
+    _announce("grid256-full-tol1e-6", sc)
+    got, gst = gpu.trace(sc)
+    print("[gpu-case] grid256-full-tol1e-6: GPU done, oracle running", flush=True)
+    ref, rst = oracle_lib.trace(sc)
+    ref2, _ = oracle_lib.trace(perturbed(sc))
+    summ = compare_conditioned(got, ref, ref2, sc.limits.tol, label="grid256-full-tol1e-6",
+                               amp_dir_sens=AMP_DIR_SENS_GRID)
+    print(f"[gpu-case] grid256-full-tol1e-6: {summ}; stats {gst}", flush=True)
+    assert summ["well_conditioned"] >= 0.95 * sc.n_rays
+    for f in ("accepted", "rejected", "events", "records"):
+        assert gst[f] == rst[f], f
 
 
 def _sampled(gpu, oracle_lib, sc, name, n_roots=512, conditioned=False):
@@ -317,9 +348,11 @@ def _sampled(gpu, oracle_lib, sc, name, n_roots=512, conditioned=False):
     sub = {f: a[sel] for f, a in got.items()}
     if conditioned:
         ref2, _ = oracle_lib.trace(perturbed(sc), roots=roots)
-        summ = compare_conditioned(sub, ref, ref2, sc.limits.tol, label=name)
+        summ = compare_conditioned(sub, ref, ref2, sc.limits.tol, label=name,
+                                   amp_dir_sens=AMP_DIR_SENS_GRID)
     else:
         summ = compare(sub, ref, sc.limits.tol, label=name)
+    print(f"[gpu-case] {name}: {len(roots)} roots", flush=True)
     print(f"[gpu-case] {name}: {summ}; stats {gst}", flush=True)
     assert gst["records"] + gst["invalid"] == gst["needed"] and gst["sched_errors"] == 0
     return summ
