@@ -115,18 +115,28 @@ __device__ __forceinline__ double pow_neg_inv(double x) {
   return y;
 }
 
+// a * b + c as one three-operand FP64 FMA (v_fma_f64) whatever registers
+// hold c.  Written out because the compiler otherwise picks the
+// two-operand form, whose addend is also its destination, and copies a
+// loop-held coefficient into it before every term of a polynomial.
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
 // e^x for |x| <= 0.25: Taylor polynomial to degree 11 (truncation below
 // 2^-52 relative), Horner form.
 __device__ __forceinline__ double exp_small(double x) {
   double p = 1.0 / 39916800.0;
-  p = fma(p, x, 1.0 / 3628800.0);
-  p = fma(p, x, 1.0 / 362880.0);
-  p = fma(p, x, 1.0 / 40320.0);
-  p = fma(p, x, 1.0 / 5040.0);
-  p = fma(p, x, 1.0 / 720.0);
-  p = fma(p, x, 1.0 / 120.0);
-  p = fma(p, x, 1.0 / 24.0);
-  p = fma(p, x, 1.0 / 6.0);
+  p = fma3(p, x, 1.0 / 3628800.0);
+  p = fma3(p, x, 1.0 / 362880.0);
+  p = fma3(p, x, 1.0 / 40320.0);
+  p = fma3(p, x, 1.0 / 5040.0);
+  p = fma3(p, x, 1.0 / 720.0);
+  p = fma3(p, x, 1.0 / 120.0);
+  p = fma3(p, x, 1.0 / 24.0);
+  p = fma3(p, x, 1.0 / 6.0);
   p = fma(p, x, 0.5);
   p = fma(p, x, 1.0);
   return fma(p, x, 1.0);
