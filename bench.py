@@ -55,12 +55,13 @@ BYTES_PER_TRIAL_GRID = 768
 # code: comments and whitespace removed); after a change to the code the
 # traffic is reported as null until measured again.
 TRAFFIC = {  # workload -> (fetch bytes, write bytes, digest)
-    "twolayer": (3.1804e+09, 4.4587e+09,
-                 "bf410121989010093698db940360f57eeb820f75b91e6e86b9cb934a66e39902"),
-    "grid256": (3.3663e+11, 2.5610e+09,
-                "bf410121989010093698db940360f57eeb820f75b91e6e86b9cb934a66e39902"),
+    "twolayer": (2.9362e+09, 4.1680e+09,
+                 "46baf68b4ce8fcfee22fa6ef2a37eef1782decc73915691e4a1c21d650b3d157"),
+    "grid256": (3.3158e+11, 2.5609e+09,
+                "46baf68b4ce8fcfee22fa6ef2a37eef1782decc73915691e4a1c21d650b3d157"),
 }
-TRACE_SOURCES = ("rt_kernels.hip", "rt_device.hpp", "rt_params.hpp")
+TRACE_SOURCES = ("rt_kernels.hip", "rt_strat.hip", "rt_trace.hpp", "rt_device.hpp",
+                 "rt_params.hpp")
 
 
 def code_of(text):
@@ -82,6 +83,21 @@ def kernel_digest(sources=None):
             text = sources[f]
         h.update(code_of(text).encode())
     return h.hexdigest()
+
+
+# L2 hit fraction of the trace kernel's requests (rocprofv3 TCC_HIT_sum,
+# TCC_MISS_sum of one launch), valid for the listed code digest like TRAFFIC.
+L2_HIT = {  # workload -> (hits, misses, digest)
+    "grid256": (8.0602e+09, 2.6684e+09,
+                "46baf68b4ce8fcfee22fa6ef2a37eef1782decc73915691e4a1c21d650b3d157"),
+}
+
+
+def measured_l2_hit(workload):
+    t = L2_HIT.get(workload)
+    if t is None or t[2] != kernel_digest():
+        return None
+    return t[0] / (t[0] + t[1])
 
 
 def measured_traffic(workload):
@@ -461,6 +477,37 @@ def bench_copy(args, log):
     print(json.dumps(out), flush=True)
 
 
+def probe_levels(log, passes=20):
+    """Read bandwidth (GB/s) of float4 streams and gathers from buffers sized
+    for each XCD's L2 (2 MiB), the MALL (128 MiB, the size of the gridded
+    workload's node array) and HBM (4 GiB)."""
+    import torch
+    from paper_1810_01780_amd import binding
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+    for name, nbytes in (("l2", 2 << 20), ("mall", 128 << 20), ("hbm", 4 << 30)):
+        buf = torch.rand(nbytes // 4, dtype=torch.float32, device="cuda")
+        for pat, pname in ((binding.RT_PROBE_STREAM, "stream"), (binding.RT_PROBE_GATHER, "gather")):
+            gbs = binding.rt_probe_read_bandwidth(buf.data_ptr(), nbytes, pat, passes, stream)
+            out[f"{pname}_{name}"] = gbs
+            log(f"probe {pname} {name} ({nbytes >> 20} MiB): {gbs:.0f} GB/s")
+        del buf
+    return out
+
+
+def bench_probe(args, log):
+    """The read-bandwidth probe alone: one JSON line of GB/s per level and
+    pattern (value: the L2 gather rate)."""
+    t0 = time.perf_counter()
+    lv = probe_levels(log)
+    dt = time.perf_counter() - t0
+    out = {"metric": "float4 read bandwidth by serving level", "value": lv["gather_l2"],
+           "unit": "GB/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": dt * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": "probe", **lv}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -468,7 +515,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="twolayer",
                     choices=["twolayer", "grid256", "curved", "field3d", "fan1024", "solve",
-                             "surrogate", "copy"])
+                             "surrogate", "copy", "probe"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -492,6 +539,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "copy":
         return bench_copy(args, log)
+    if args.workload == "probe":
+        return bench_probe(args, log)
     if args.workload == "solve":
         return bench_solve(args, log)
     if args.workload == "surrogate":
@@ -534,9 +583,25 @@ def main():
 
     trials = st["accepted"] + st["rejected"] + st["relocation"]
     if args.workload == "grid256":
-        achieved = trials * BYTES_PER_TRIAL_GRID / kern_s / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(args.workload)}
+        # HBM: the measured traffic of the trace kernel (counter runs) over
+        # its time; the node data the trials request is mostly served by the
+        # L2 and the MALL, so it is set against those levels' measured peaks,
+        # mixed by the L2 hit fraction of the same kernel's requests
+        traffic = measured_traffic(args.workload)
+        hbm = traffic / kern_s / 1e9 if traffic else None
+        roof = {"bound": "hbm", "achieved": hbm, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": hbm / PEAK_HBM_GBS if hbm else None, "traffic": traffic}
+        req = trials * BYTES_PER_TRIAL_GRID / kern_s / 1e9
+        lv = probe_levels(log)
+        hit = measured_l2_hit(args.workload)
+        serving = {"requested_GBps": req, "bytes_per_trial": BYTES_PER_TRIAL_GRID,
+                   "peak_stream_l2": lv["stream_l2"], "peak_stream_mall": lv["stream_mall"],
+                   "peak_gather_l2": lv["gather_l2"], "peak_gather_mall": lv["gather_mall"],
+                   "l2_hit": hit}
+        if hit is not None:
+            mix = 1.0 / (hit / lv["stream_l2"] + (1.0 - hit) / lv["stream_mall"])
+            serving.update(peak_mix=mix, frac=req / mix)
+        roof["serving"] = serving
     else:
         achieved = trial_flops(scene, rec, trials) / kern_s / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,

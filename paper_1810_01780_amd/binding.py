@@ -227,6 +227,9 @@ def lib() -> C.CDLL:
                                              C.c_double, C.POINTER(rt_step_limits),
                                              C.POINTER(rt_outputs), C.c_void_p,
                                              C.POINTER(rt_tuning)]
+        L.rt_probe_read_bandwidth.restype = C.c_int
+        L.rt_probe_read_bandwidth.argtypes = [C.c_void_p, C.c_size_t, C.c_int32, C.c_int32,
+                                              C.c_void_p, C.POINTER(C.c_double)]
         L.rt_collect.restype = C.c_int
         L.rt_collect.argtypes = [C.POINTER(rt_stats), C.c_int64]
         L.rt_last_error.restype = C.c_char_p
@@ -332,6 +335,16 @@ def raytrace_launch_static(field, boundaries, sources, directions, tol, limits, 
 
 
 RT_STATIC_SCRATCH_BYTES = 64 << 20
+RT_PROBE_STREAM, RT_PROBE_GATHER = 0, 1
+
+
+def rt_probe_read_bandwidth(buffer, nbytes: int, pattern: int, passes: int, stream) -> float:
+    """GB/s of float4 reads served from a device buffer (see radiotrace_probe.h)."""
+    out = C.c_double()
+    st = lib().rt_probe_read_bandwidth(buffer, nbytes, pattern, passes, stream, C.byref(out))
+    if st != RT_OK:
+        raise RTError(st, rt_last_error())
+    return float(out.value)
 
 
 def rt_collect(stats, capacity: int) -> int:
