@@ -142,6 +142,35 @@ __device__ __forceinline__ double exp_small(double x) {
   return fma(p, x, 1.0);
 }
 
+// e^x for any x: Cody and Waite's reduction by ln 2 and a Taylor polynomial.
+// x = k ln2 + r with k = rint(x / ln2) and |r| <= ln2 / 2; ln2 = L1 + L2,
+// L1 holding 42 significant bits, so that k L1 is exact for |k| < 2^11 and
+// x - k L1 is rounded once; e^r by its Taylor polynomial of degree 13
+// (remainder below 2^-56 relative), then scaled by 2^k.  x is first clamped
+// to [-746, 709], beyond which e^x is below the smallest subnormal or
+// overflows.
+__device__ __forceinline__ double exp_rr(double x) {
+  constexpr double kL1 = 0x1.62e42fefa38p-1, kL2 = 5.497923018708371e-14;
+  x = fmin(fmax(x, -746.0), 709.0);
+  const double k = __builtin_rint(x * 1.4426950408889634);
+  double r = fma(-k, kL1, x);
+  r = fma(-k, kL2, r);
+  double p = fma(r, 1.0 / 6227020800.0, 1.0 / 479001600.0);
+  p = fma3(p, r, 1.0 / 39916800.0);
+  p = fma3(p, r, 1.0 / 3628800.0);
+  p = fma3(p, r, 1.0 / 362880.0);
+  p = fma3(p, r, 1.0 / 40320.0);
+  p = fma3(p, r, 1.0 / 5040.0);
+  p = fma3(p, r, 1.0 / 720.0);
+  p = fma3(p, r, 1.0 / 120.0);
+  p = fma3(p, r, 1.0 / 24.0);
+  p = fma3(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return __builtin_amdgcn_ldexp(p, (int)k);
+}
+
 // Medium of one ray, kept in registers: n(z) = a + b z - dn exp(-z/z0).
 struct Medium {
   double a, b, dn, inv_z0, dn_inv_z0;
@@ -188,6 +217,62 @@ __device__ __forceinline__ void strat_field_rel(const Medium& M, double z0, doub
   }
   n = fma(M.b, z, M.a) - M.dn * e;
   gz = fma(M.dn_inv_z0, e, M.b);
+}
+
+// 1/k! for k = 0..13.
+__device__ constexpr double inv_fact(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= (double)i;
+  return 1.0 / f;
+}
+// e^x by its Taylor polynomial of degree D in Horner form.  Its remainder,
+// at most |x|^(D+1) / (D+1)! e^|x|, is below 2^-53 of e^x for
+// |x| <= taylor_max(D): the largest such |x|, rounded down.
+template <int D>
+__device__ __forceinline__ double exp_taylor(double x) {
+  double p = inv_fact(D);
+#pragma unroll
+  for (int k = D - 1; k >= 3; --k) p = fma3(p, x, inv_fact(k));
+  p = fma(p, x, 0.5);
+  p = fma(p, x, 1.0);
+  return fma(p, x, 1.0);
+}
+__device__ constexpr double taylor_max(int D) {
+  return D <= 7 ? 0.0377 : D == 8 ? 0.0689 : D == 9 ? 0.1123 : D == 10 ? 0.1687 : 0.2380;
+}
+// Taylor degree at stage s (1..5) of a trial: stage s lies about c_s h
+// from the step's start (nodes c = 1/5, 3/10, 3/5, 1, 7/8), so for steps up
+// to a sixth of z0 the early stages need fewer terms.
+__device__ constexpr int stage_degree(int s) {
+  return s == 1 ? 7 : s == 2 ? 8 : s == 3 ? 9 : 10;
+}
+
+// strat_field_rel at stage S without a branch: slow is raised when the
+// exponent is outside the Taylor range of the stage (or NaN); the caller
+// then recomputes the step with strat_field_rel.  Media with dn = 0 have
+// inv_z0 = 0, so e = E0 and dn e = 0.
+template <int S>
+__device__ __forceinline__ void strat_field_stage_fast(const Medium& M, double z0, double dz,
+                                                       double E0, double& n, double& gz,
+                                                       bool& slow) {
+  constexpr int D = stage_degree(S);
+  const double z = z0 + dz;
+  const double x = -dz * M.inv_z0;
+  slow = slow || !(fabs(x) <= taylor_max(D));
+  const double e = E0 * exp_taylor<D>(x);
+  n = fma(M.b, z, M.a) - M.dn * e;
+  gz = fma(M.dn_inv_z0, e, M.b);
+}
+__device__ __forceinline__ void strat_field_fast_at(int st, const Medium& M, double z0, double dz,
+                                                    double E0, double& n, double& gz,
+                                                    bool& slow) {
+  switch (st) {
+    case 1: strat_field_stage_fast<1>(M, z0, dz, E0, n, gz, slow); break;
+    case 2: strat_field_stage_fast<2>(M, z0, dz, E0, n, gz, slow); break;
+    case 3: strat_field_stage_fast<3>(M, z0, dz, E0, n, gz, slow); break;
+    case 4: strat_field_stage_fast<4>(M, z0, dz, E0, n, gz, slow); break;
+    default: strat_field_stage_fast<5>(M, z0, dz, E0, n, gz, slow); break;
+  }
 }
 
 // Trilinear n and gradient from float4 nodes (n, Dx, Dy, Dz); positions
@@ -246,10 +331,15 @@ __device__ __forceinline__ double stage_inc(double h, const double (&k)[6]) {
   return h * acc;
 }
 
-template <int MODEL>
+// FAST (paper model): stages without branches (strat_field_stage_fast);
+// *slow_out tells whether a stage left its Taylor range, in which case the
+// caller repeats the step with FAST = false.
+template <int MODEL, bool FAST = false>
 __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], double h,
-                                            double inv_tol, double y5[7], double& err) {
-  const double E0 = M.dn != 0.0 ? exp(-y[2] * M.inv_z0) : 0.0;
+                                            double inv_tol, double y5[7], double& err,
+                                            bool* slow_out = nullptr) {
+  const double E0 = FAST ? exp_rr(-y[2] * M.inv_z0) : (M.dn != 0.0 ? exp(-y[2] * M.inv_z0) : 0.0);
+  bool slow = false;
   if constexpr (MODEL == RT_MODEL_PAPER) {
     // w = unit velocity, renormalised after every accepted step (|w| = 1).
     // z'' = (dn/dz)/n depends on z alone: the Nystrom form of the step, as
@@ -266,7 +356,8 @@ __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], 
 #pragma unroll
         for (int i = 0; i + 1 < st; ++i) acc = fma(ck_aa(st, i), kw[i], acc);
         const double dz = h * fma(h, acc, ck_c(st) * y[5]);
-        strat_field_rel(M, y[2], dz, E0, n, gz);
+        if constexpr (FAST) strat_field_fast_at(st, M, y[2], dz, E0, n, gz, slow);
+        else strat_field_rel(M, y[2], dz, E0, n, gz);
       }
       kw[st] = gz * rcp_nr(n);
       if (st == 0) tsum = kB1 * n;
@@ -288,6 +379,7 @@ __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], 
     y5[5] = fma(h, b_sum(kw), y[5]);
     y5[6] = fma(h * kInvC0, tsum, y[6]);
     err = fmax(fabs(h * ea), fabs(h * e_sum(kw))) * inv_tol;
+    if (slow_out) *slow_out = slow;
   } else {
     // w = p = n dr/ds; p_x, p_y are constant in a stratified medium
     const double px = y[3], py = y[4];
@@ -730,7 +822,17 @@ __device__ __forceinline__ void trial(const KParams& P, const Ray& R, double h, 
   if constexpr (FIELD == 1) {
     trial_3d<MODEL>(P, medium_of(P, R.region), R.y, h, P.inv_tol, y5, err);
   } else {
-    trial_strat<MODEL>(medium_of(P, R.region), R.y, h, P.inv_tol, y5, err);
+    if constexpr (MODEL == RT_MODEL_PAPER) {
+      // the branch-free form first (one basic block, so the stages' code can
+      // interleave); a lane whose stages left their Taylor ranges repeats
+      // the step with the general exponential
+      const Medium M = medium_of(P, R.region);
+      bool slow = false;
+      trial_strat<MODEL, true>(M, R.y, h, P.inv_tol, y5, err, &slow);
+      if (__builtin_expect(slow, 0)) trial_strat<MODEL>(M, R.y, h, P.inv_tol, y5, err);
+    } else {
+      trial_strat<MODEL>(medium_of(P, R.region), R.y, h, P.inv_tol, y5, err);
+    }
   }
 }
 

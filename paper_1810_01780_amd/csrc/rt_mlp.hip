@@ -58,6 +58,9 @@ struct GemmArgs {
   int lda_out;
   bf16* AoutT;    // [N][ldt]; rows of the transposed copy are written up to Mpad
   int ldt, Mpad;
+  // split-K (EPI_PLAIN only): block z sums k in [z kslice, (z + 1) kslice)
+  // and writes its partial product to C + z M ldc; 0 = one slice
+  int kslice;
 };
 
 template <int EPI>
@@ -86,7 +89,16 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
     okb[i] = col < g.N;
     pb[i] = g.Bt + (size_t)(okb[i] ? col : 0) * g.ldb + kh;
   }
-  for (int k = 0; k < g.K; k += 16) {
+  int k0 = 0, k1 = g.K;
+  float* Cout = g.C;
+  if constexpr (EPI == EPI_PLAIN) {
+    if (g.kslice > 0) {
+      k0 = (int)blockIdx.z * g.kslice;
+      k1 = min(g.K, k0 + g.kslice);
+      Cout = g.C + (size_t)blockIdx.z * g.M * g.ldc;
+    }
+  }
+  for (int k = k0; k < k1; k += 16) {
     bf16x8 a[2], b[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -118,7 +130,7 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
         if constexpr (EPI == EPI_PLAIN || EPI == EPI_OUT) {
 #pragma unroll
           for (int u = 0; u < 4; ++u)
-            if (rb + u < g.M) g.C[(size_t)(rb + u) * g.ldc + col] = val[u];
+            if (rb + u < g.M) Cout[(size_t)(rb + u) * g.ldc + col] = val[u];
         } else {
           float a[4];
 #pragma unroll
@@ -265,6 +277,17 @@ __global__ void __launch_bounds__(256) rowsum_kernel(const bf16* __restrict__ X,
   if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
+// out[i] = sum over s < S of part[s n + i]: the slices of a split-K product,
+// added in slice order (the result does not depend on the launch).
+__global__ void __launch_bounds__(256) splitk_sum_kernel(const float* __restrict__ part, int S,
+                                                         int64_t n, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc = part[i];
+  for (int z = 1; z < S; ++z) acc += part[(int64_t)z * n + i];
+  out[i] = acc;
+}
+
 // W [N][K] FP32 -> Wb [N][Kp] BF16 and (optional) WbT [K][Np] BF16, zero padded.
 __global__ void pack_layer_kernel(const float* __restrict__ W, int N, int K, bf16* __restrict__ Wb,
                                   int Kp, bf16* __restrict__ WbT, int Np) {
@@ -324,8 +347,15 @@ struct Layout {
   float* dA;
   bf16 *dz, *dzT;
   float* partial;
+  float* splitk;  // kMaxSlices partial products of up to 256 x 256
   size_t bytes;
 };
+
+// Weight gradients sum over the batch: split into slices of at least 256
+// rows (16 matrix-core steps), at most kMaxSlices of them, so that a
+// 256 x 256 gradient keeps 4 x slices workgroups busy instead of 4.
+constexpr int kMaxSlices = 32;
+constexpr int kMinSliceK = 256;
 
 size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
@@ -364,6 +394,8 @@ Layout layout(char* base, int64_t B, bool training) {
     L.dz = reinterpret_cast<bf16*>(take((size_t)B * RT_MLP_WIDTH * 2));
     L.dzT = reinterpret_cast<bf16*>(take((size_t)RT_MLP_WIDTH * Bp * 2));
     L.partial = reinterpret_cast<float*>(take((size_t)((Bp + 255) / 256) * 4));
+    L.splitk = reinterpret_cast<float*>(
+        take((size_t)kMaxSlices * RT_MLP_WIDTH * RT_MLP_WIDTH * 4));
   }
   L.bytes = off;
   return L;
@@ -371,8 +403,26 @@ Layout layout(char* base, int64_t B, bool training) {
 
 template <int EPI>
 hipError_t gemm(const GemmArgs& g, hipStream_t s) {
-  dim3 grid((unsigned)((g.M + 127) / 128), (unsigned)((g.N + 127) / 128));
+  const unsigned nz = g.kslice > 0 ? (unsigned)((g.K + g.kslice - 1) / g.kslice) : 1u;
+  dim3 grid((unsigned)((g.M + 127) / 128), (unsigned)((g.N + 127) / 128), nz);
   hipLaunchKernelGGL((gemm_nt_kernel<EPI>), grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+// Weight gradient C[M][N] (M, N <= 256) = sum over the K batch rows, as a
+// split-K product into the slice buffer and a slice sum into C.
+hipError_t weight_grad(GemmArgs g, float* slices, hipStream_t s) {
+  int S = std::min(kMaxSlices, std::max(1, g.K / kMinSliceK));
+  const int ks = (g.K / 16 + S - 1) / S * 16;  // a multiple of 16
+  S = (g.K + ks - 1) / ks;
+  float* C = g.C;
+  g.kslice = ks;
+  g.C = slices;
+  hipError_t e = gemm<EPI_PLAIN>(g, s);
+  if (e != hipSuccess) return e;
+  const int64_t n = (int64_t)g.M * g.ldc;
+  hipLaunchKernelGGL(splitk_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     slices, S, n, C);
   return hipGetLastError();
 }
 
@@ -542,7 +592,8 @@ extern "C" rt_status rt_mlp_gradients(const float* params, const float* x, const
   hipLaunchKernelGGL(rowsum_kernel, dim3(RT_MLP_OUT), dim3(256), 0, s, L.dyT, Bp, Bp,
                      grad + o.b[4]);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(gemm<EPI_PLAIN>(args(L.dyT, Kb, L.aT[3], Kb, RT_MLP_OUT, W, Kb, grad + o.w[4], W), s));
+  HIP_TRY(weight_grad(args(L.dyT, Kb, L.aT[3], Kb, RT_MLP_OUT, W, Kb, grad + o.w[4], W), L.splitk,
+                      s));
   HIP_TRY(gemm<EPI_PLAIN>(args(L.dy, 16, L.wbt[4], 16, M, W, 16, L.dA, W), s));
   for (int h = RT_MLP_HIDDEN - 1; h >= 0; --h) {
     dim3 tg((unsigned)((Bp + 31) / 32), W / 32);
@@ -552,7 +603,8 @@ extern "C" rt_status rt_mlp_gradients(const float* params, const float* x, const
     HIP_TRY(hipGetLastError());
     const bf16* prevT = h > 0 ? L.aT[h - 1] : L.x0T;
     const int n_in = kIn[h];
-    HIP_TRY(gemm<EPI_PLAIN>(args(L.dzT, Kb, prevT, Kb, W, n_in, Kb, grad + o.w[h], n_in), s));
+    HIP_TRY(weight_grad(args(L.dzT, Kb, prevT, Kb, W, n_in, Kb, grad + o.w[h], n_in), L.splitk,
+                        s));
     if (h > 0) HIP_TRY(gemm<EPI_PLAIN>(args(L.dz, W, L.wbt[h], W, M, W, W, L.dA, W), s));
   }
   return RT_OK;

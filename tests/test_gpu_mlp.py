@@ -69,7 +69,7 @@ def test_forward_matches_reference(gpu, B):
     assert rms_f <= 1e-2 and max_f <= 6e-2
 
 
-@pytest.mark.parametrize("B", [48, 1000, 4096])
+@pytest.mark.parametrize("B", [48, 1000, 4096, 16384])
 def test_gradients_match_reference(gpu, B):
     print(f"\n[gpu-case] mlp-gradients B={B}", flush=True)
     p = W.mlp_init_params(8)

@@ -234,3 +234,36 @@ def test_seeded_secant(oracle_lib):
         # the miss of a straight line is D cot(theta) - (zs - zr) shifted: angle error ~ miss / L
         assert r["theta"][i, 0] == pytest.approx(th[i], abs=2e-3 / L[i])
         assert r["t"][i, 0] * C0 == pytest.approx(n * L[i], abs=n * 2e-3)
+
+
+def test_scan_completeness_against_dense_scan(oracle_lib):
+    """How many solutions the 64-angle scan misses: the same solves with a
+    scan of 1,024 angles and 16 brackets per family, on 512 pairs spread over
+    the two-layer workload.  Every solution of the 64-angle scan is one of
+    the dense scan's (same entries, same or later arrival); the dense scan
+    finds 1.6 % more (measured 21 of 1,299 entries on 1,024 pairs).  The
+    missed roots are of two kinds: launches closer to the vertical than the
+    first scan angle (pi/128; short horizontal distances), which no scan
+    interval brackets, and two roots of the direct family inside one scan
+    interval (misses of the same sign at both ends).  The 64-angle scan
+    reports a later arrival than the dense one for 0.15 % of its entries.
+    The bars are those rates with room for the sample: a scan that lost
+    brackets or an arrival rule that picked the wrong root would exceed
+    them."""
+    sp = W.solve_pairs(65536)
+    idx = np.arange(0, 65536, 128)
+    zs, zr, D = sp.zs[idx], sp.zr[idx], sp.dist[idx]
+    a = oracle_lib.solve(sp.scene, zs, zr, D)
+    b = oracle_lib.solve(sp.scene, zs, zr, D, n_scan=1024, max_brackets=16)
+    fa, fb = a["found"] == 1, b["found"] == 1
+    both = fa & fb
+    dt = a["t"] - b["t"]
+    missed = int((fb & ~fa).sum())
+    later = int((both & (dt > 1e-10)).sum())
+    print(f"scan completeness: 64 angles {fa.sum()}, 1024 angles {fb.sum()} of {fa.size}; "
+          f"missed {missed}, later arrival {later}")
+    assert not np.any(fa & ~fb)
+    assert np.all(dt[both] >= -1e-12)
+    assert fb.sum() > 0.5 * fb.size
+    assert missed <= 0.03 * fb.sum()
+    assert later <= 0.005 * both.sum()
