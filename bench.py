@@ -12,7 +12,11 @@ the full batch, with inputs already resident in device memory.  The headline
 value is accepted Runge-Kutta steps per second over primaries and
 secondaries.  The trace kernel's own duration is measured with HIP events
 recorded on the launch stream, and the CPU oracle is timed on a bounded
-sample of the same workload.  Prints one JSON line.
+sample of the same workload.  The default line also carries the metric's
+second part under "solves": emitter -> receiver solves/s of the
+surrogate-seeded path and of the tracer alone on one batch of 1,048,576
+pairs (network trained first, not timed; see surrogate_run).  Prints one
+JSON line.
 """
 import argparse
 import ctypes
@@ -109,6 +113,7 @@ def measured_traffic(workload):
 
 PEAK_FP64_VECTOR_TFLOPS = 78.6   # MI355X: 256 CU x 128 FLOP/clk x 2.4 GHz
 PEAK_HBM_GBS = 8000.0            # MI355X HBM3E
+PEAK_BF16_TFLOPS = 2500.0        # MI355X dense BF16 matrix cores
 
 
 def _hip():
@@ -279,18 +284,18 @@ def bench_solve(args, log):
                accept_tol_m=prm.accept_tol, slope_max_m_per_rad=prm.slope_max,
                tol=sp.scene.limits.tol, model="paper")
     log(f"workload solve65536: {sp.n} pairs")
-    if args.block or args.refill:
-        tun = binding.rt_tuning(args.block, 0, args.refill, None, None)
+    if args.block or args.refill or args.scan_chunk:
+        tun = binding.rt_tuning(args.block, 0, args.refill, None, None, 0, args.scan_chunk)
         cfg["tuning"] = "fixed"
     else:
         m = 16384
         sample = binding.DeviceSolve(sp.scene, sp.zs[:m], sp.zr[:m], sp.dist[:m], prm)
         tun, ms = sample.autotune()
         log(f"autotune on {m} pairs: block {tun.block_size} refill {tun.refill_threshold} "
-            f"({ms:.2f} ms)")
+            f"scan chunk {tun.scan_chunk} ({ms:.2f} ms)")
         cfg["tuning"] = "autotuned"
         del sample
-    cfg.update(block=tun.block_size, refill=tun.refill_threshold)
+    cfg.update(block=tun.block_size, refill=tun.refill_threshold, scan_chunk=tun.scan_chunk)
     ds = binding.DeviceSolve(sp.scene, sp.zs, sp.zr, sp.dist, prm)
     hip = _hip()
 
@@ -308,7 +313,8 @@ def bench_solve(args, log):
     kern = []
     for i in range(args.warmup + 1):
         b, e = event(), event()
-        ds.launch(tuning=binding.rt_tuning(tun.block_size, 0, tun.refill_threshold, b, e))
+        ds.launch(tuning=binding.rt_tuning(tun.block_size, 0, tun.refill_threshold, b, e, 0,
+                                           tun.scan_chunk))
         res, st = ds.collect()
         if i >= args.warmup:
             kern.append(elapsed(b, e))
@@ -354,22 +360,29 @@ def bench_solve(args, log):
     print(json.dumps(out), flush=True)
 
 
-def bench_surrogate(args, log):
-    """Surrogate-seeded solves of the 65,536-pair workload: the network is
-    trained first on the GPU (tracer solves of 128 profiles x 8,192 pairs,
-    6,000 Adam steps; not timed), then a step is one replay of the captured
-    raytrace_solve_surrogate graph (network, seeded secant with shot
-    verification, tracer fallback).  The tracer's own graph is timed beside
-    it on the same pairs."""
+def surrogate_run(n_pairs, steps, warmup, log, net=None):
+    """Surrogate-seeded solves against the tracer alone on the same GPU.
+
+    The network is trained first (the default recipe: tracer solves of
+    2,048 seeded profiles x 8,192 pairs, 8,000 Adam steps of 16,384 rows; not
+    timed) unless given.  Then n_pairs seeded pairs of the two-layer workload
+    are solved as one batch, by the captured raytrace_solve_surrogate graph
+    (network inference on the whole batch, seeded secant with shot
+    verification, tracer for every other entry) and by the tracer's captured
+    raytrace_solve graph; each is replayed warmup + steps times, the steps
+    timed.  Returns the measured figures and the entry classification."""
+    import numpy as np
     import torch
     from paper_1810_01780_amd import binding
     from paper_1810_01780_amd import surrogate
     from paper_1810_01780_amd import workloads as W
-    t0 = time.perf_counter()
-    net, losses = surrogate.default_model(seed=0, n_profiles=128, pairs_per_profile=8192,
-                                          steps=6000, log=log)
-    train_s = time.perf_counter() - t0
-    sp = W.solve_pairs()
+    out = {}
+    if net is None:
+        t0 = time.perf_counter()
+        net, losses = surrogate.default_model(seed=0, log=log)
+        out.update(training_pairs=2048 * 8192, training_steps=8000, training_batch=16384,
+                   training_s=round(time.perf_counter() - t0, 1), final_loss=losses[-1][1])
+    sp = W.solve_pairs(n_pairs)
     prm = binding.solve_params()
     spar = binding.surrogate_params(z0=75.0, dn=0.43)
     ds = binding.DeviceSurrogateSolve(sp.scene, sp.zs, sp.zr, sp.dist, spar, prm)
@@ -391,29 +404,30 @@ def bench_surrogate(args, log):
     g_tr = graph_of(lambda s: tr.launch(stream=s))
 
     def timed(g):
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             g.replay()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             g.replay()
         torch.cuda.synchronize()
-        return (time.perf_counter() - t) / args.steps
+        return (time.perf_counter() - t) / steps
     t_su = timed(g_su)
     t_tr = timed(g_tr)
     res, st = ds.collect()
     rres, rst = tr.collect()
     path = res["path"]
-    found_s, found_t = int(res["found"].sum()), int(rres["found"].sum())
-    false_absent = int(((path == binding.RT_PATH_ABSENT) & (rres["found"] == 1)).sum())
-    # network forward alone (events on the stream), for its matrix-core rate
+    sur = path == binding.RT_PATH_SURROGATE
+    both = sur & (rres["found"] == 1)
+    dt = res["t"][both] - rres["t"][both]
+    # network forward alone on the whole batch (events on the stream)
     hip = _hip()
     e0, e1 = ctypes.c_void_p(), ctypes.c_void_p()
     hip.hipEventCreate(ctypes.byref(e0))
     hip.hipEventCreate(ctypes.byref(e1))
     inf = binding.DeviceMLP(net.params.cpu().numpy(), max_batch=sp.n, training=False)
     x = torch.randn((sp.n, 5), device="cuda")
-    y = torch.empty((sp.n, 10), device="cuda")
+    y = torch.empty((sp.n, 12), device="cuda")
     inf.forward(x, y)
     stream = torch.cuda.current_stream().cuda_stream
     hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -425,28 +439,43 @@ def bench_surrogate(args, log):
     ms = ctypes.c_float()
     hip.hipEventElapsedTime(ctypes.byref(ms), e0, e1)
     mlp_s = ms.value / 10 / 1e3
-    mlp_flop = 2.0 * sp.n * (5 * 256 + 3 * 256 * 256 + 256 * 10)
-    trials = st["accepted"] + st["rejected"] + st["relocation"]
-    achieved = trials * FLOP_PER_TRIAL[0] / t_su / 1e12
-    cfg = dict(workload="solve65536-surrogate", pairs=sp.n, network="5-256x4-10 SiLU, BF16 MFMA",
-               training_pairs=128 * 8192, training_steps=6000, training_s=round(train_s, 1),
-               final_loss=losses[-1][1], verify_tol_m=spar.verify_tol, max_shots=spar.max_shots,
-               absent_logit=spar.absent_logit, fallback_pairs=st["fallback_pairs"],
-               found=found_s, tracer_found=found_t, false_absent=false_absent,
-               shots=st["shots"], tracer_shots=rst["shots"],
+    mlp_flop = 2.0 * sp.n * (5 * 256 + 3 * 256 * 256 + 256 * 12)
+    out.update(pairs=sp.n, network="5-256x4-12 SiLU, BF16 MFMA", verify_tol_m=spar.verify_tol,
+               max_shots=spar.max_shots, absent_logit=spar.absent_logit,
+               multi_logit=spar.multi_logit, surrogate_solves_per_s=sp.n / t_su,
                tracer_solves_per_s=sp.n / t_tr, gain_vs_tracer=t_tr / t_su,
-               mlp_forward_ms=mlp_s * 1e3, mlp_tflops=mlp_flop / mlp_s / 1e12)
+               surrogate_ms=t_su * 1e3, tracer_ms=t_tr * 1e3,
+               surrogate_entries=int(sur.sum()), tracer_entries=int((~sur).sum()),
+               fallback_pairs=st["fallback_pairs"], found=int(res["found"].sum()),
+               tracer_found=int(rres["found"].sum()),
+               tracer_found_missed=int(((rres["found"] == 1) & (res["found"] == 0)).sum()),
+               later_than_tracer=int((dt > 1e-10).sum()),
+               earlier_than_tracer=int((dt < -1e-10).sum()),
+               shots=st["shots"], tracer_shots=rst["shots"],
+               trial_steps=st["accepted"] + st["rejected"] + st["relocation"],
+               mlp_forward_ms=mlp_s * 1e3, mlp_tflops=mlp_flop / mlp_s / 1e12,
+               mlp_bf16_frac=mlp_flop / mlp_s / 1e12 / PEAK_BF16_TFLOPS)
+    log(f"surrogate {t_su * 1e3:.2f} ms vs tracer {t_tr * 1e3:.2f} ms per {sp.n} pairs; "
+        f"{st['fallback_pairs']} pairs with tracer entries")
+    return out, net, sp
+
+
+def bench_surrogate(args, log):
+    """Surrogate-seeded solves of a 1,048,576-pair batch (surrogate_run); the
+    JSON line carries the tracer's rate on the same pairs and GPU."""
+    r, _, sp = surrogate_run(1 << 20, args.steps, args.warmup, log)
+    t_su = r["surrogate_ms"] / 1e3
+    achieved = r["trial_steps"] * FLOP_PER_TRIAL[0] / t_su / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
-            "kernel": "shot_kernel (seeded + fallback), whole-launch time",
+            "kernel": "shot_kernel (seeded + tracer entries), whole-launch time",
             "kernel_ms": t_su * 1e3}
-    log(f"surrogate {t_su * 1e3:.2f} ms vs tracer {t_tr * 1e3:.2f} ms per 65,536 pairs; "
-        f"{st['fallback_pairs']} fallback pairs")
     out = {"metric": "emitter->receiver solves/s (surrogate-seeded, shot-verified)",
-           "value": sp.n / t_su, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": t_su * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64+bf16", "data": "synthetic",
-           "config": cfg, "roofline": roof}
+           "value": r["surrogate_solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_su * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64+bf16", "data": "synthetic",
+           "config": dict(workload="solve1M-surrogate", **r), "roofline": roof}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_solve_baseline(sp, args.cpu_seconds,
                                                  min(args.cpu_threads, host_cpu()[0]), log)
@@ -518,12 +547,16 @@ def main():
                              "surrogate", "copy", "probe"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--refill", type=int, default=0)
+    ap.add_argument("--scan-chunk", type=int, default=0,
+                    help="solve: entries whose angle scans interleave (0 = autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--cpu-threads", type=int, default=16,
                     help="at most this many oracle threads (one GPU's share of a box's CPUs)")
     ap.add_argument("--ev-capacity", type=int, default=0,
                     help="record Fresnel events too (rt_event array of this many entries)")
+    ap.add_argument("--no-solves", action="store_true",
+                    help="twolayer: leave out the solves figures (surrogate vs tracer)")
     args = ap.parse_args()
     log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
 
@@ -620,6 +653,16 @@ def main():
            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": cfg,
            "roofline": roof}
+    if args.workload == "twolayer" and not args.no_solves:
+        # the metric's second part: emitter -> receiver solves/s of the
+        # surrogate path and of the tracer alone, on a 1,048,576-pair batch
+        del ds
+        torch.cuda.empty_cache()
+        try:
+            r, _, _ = surrogate_run(1 << 20, 3, 1, log)
+            out["solves"] = dict(workload="solve1M two-layer", **r)
+        except Exception as e:  # the trace figures stand on their own
+            out["solves"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, args.cpu_seconds, args.cpu_threads, log)
     print(json.dumps(out), flush=True)

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define RT_ABI_VERSION 6
+#define RT_ABI_VERSION 7
 #define RT_MAX_REGIONS 8
 #define RT_MAX_PLANES 16
 #define RT_MAX_ANOMALIES 8
@@ -218,6 +218,8 @@ typedef struct {
   int64_t spilled;    /* secondaries handed to other waves (global queue) */
   int64_t interrupted; /* 1: this launch stopped at max_steps_per_launch */
   int64_t events_lost; /* event records that did not fit out->ev_capacity */
+  int64_t max_queue;  /* largest backlog of secondaries waiting on one wave's
+                         own queue (at most the local queue length) */
 } rt_stats;
 
 /* Outcome of a Fresnel event for its transmitted branch. */
@@ -295,6 +297,12 @@ typedef struct {
   int32_t local_queue;      /* secondaries a wave keeps for itself before it
                                hands further ones to other waves: 0 = 256,
                                -1 = none, else 1..1024 */
+  int32_t scan_chunk;       /* solves: entries (pair, family) whose angle
+                               scans are interleaved in the task order, so
+                               that consecutive tasks shoot one angle for
+                               scan_chunk entries (1..4096); 0 = 1: each
+                               entry's angles consecutively.  Traces ignore it.
+                               Results do not depend on it. */
 } rt_tuning;
 
 /* ABI version (RT_ABI_VERSION of the built library).  Plumbing: no

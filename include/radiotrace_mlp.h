@@ -3,7 +3,8 @@
  *
  * A multilayer perceptron maps a source/receiver pair and the firn profile
  * to the launch angles, travel times, path lengths and amplitudes of its
- * direct and surface-reflected rays, plus whether each exists.  It is
+ * direct and surface-reflected rays, plus whether each exists and whether
+ * its family has more than one ray to the receiver.  It is
  * trained on solutions of the tracer (radiotrace_solve.h) and used only as a
  * seed: every prediction is verified by shooting (raytrace_solve_seeded),
  * and the tracer's full solve is the fallback.  The paper has no surrogate;
@@ -12,22 +13,23 @@
  *
  * Network (fixed): inputs x (RT_MLP_IN = 5 features) -> 4 hidden layers of
  * RT_MLP_WIDTH = 256 units with SiLU, s(z) = z / (1 + exp(-z)) -> RT_MLP_OUT
- * = 10 outputs.  Layer l computes z = W_l a + b_l with W_l of shape
+ * = 12 outputs.  Layer l computes z = W_l a + b_l with W_l of shape
  * [n_out][n_in] (row-major).  Arithmetic: BF16 operands (weights and
  * activations rounded to nearest even), FP32 accumulation on the matrix
  * cores, FP32 bias, activation, loss and optimiser.
  *
  * Parameters are one FP32 device array of rt_mlp_param_count() values:
  * for l = 0..4, W_l (n_out * n_in values) then b_l (n_out values), with
- * (n_in, n_out) = (5, 256), (256, 256) x 3, (256, 10).
+ * (n_in, n_out) = (5, 256), (256, 256) x 3, (256, 12).
  *
  * Features, targets and the loss are defined by the caller's normalisation
  * (the Python surrogate module documents the one it uses).  The loss is
  *   L = 1/B sum_b [ sum_f m_bf sum_q (y_b,4f+q - t_b,4f+q)^2
- *                   + sum_f BCE(y_b,8+f ; m_bf) ]
+ *                   + sum_f BCE(y_b,8+f ; m_bf) + sum_f BCE(y_b,10+f ; r_bf) ]
  * over a batch of B rows, families f = 0, 1, regression outputs q = 0..3,
- * targets t (8 per row), masks m (2 per row, 0 or 1), and
- * BCE(y; m) = log(1 + exp(y)) - m y (outputs 8, 9 are logits).
+ * targets t (8 per row), labels (4 per row, 0 or 1: m_b0, m_b1, r_b0,
+ * r_b1), and BCE(y; m) = log(1 + exp(y)) - m y (outputs 8 .. 11 are
+ * logits).
  *
  * Conventions of radiotrace.h hold: device arrays owned by the caller,
  * asynchronous on 'stream', no allocation (scratch = caller workspace),
@@ -46,13 +48,14 @@ extern "C" {
 #define RT_MLP_IN 5
 #define RT_MLP_WIDTH 256
 #define RT_MLP_HIDDEN 4
-#define RT_MLP_OUT 10
+#define RT_MLP_OUT 12
 #define RT_MLP_TARGETS 8
+#define RT_MLP_LABELS 4
 
 /* The surrogate network has no counterpart in the paper: it accelerates the
  * receiver/emitter set-ups of section 2 by seeding the shooting solver, and
  * every solution it seeds is verified by a trace (or solved by the tracer).
- * Number of FP32 parameters (201,482). */
+ * Number of FP32 parameters (201,996). */
 int64_t rt_mlp_param_count(void);
 
 /* Workspace bytes for batches of up to 'batch' rows; training != 0 adds the
@@ -64,16 +67,16 @@ rt_status rt_mlp_workspace_bytes(int64_t batch, int32_t training, size_t* bytes)
 rt_status rt_mlp_pack(const float* params, void* workspace, size_t workspace_bytes,
                       void* stream);
 
-/* y[B][10] = network(x[B][5]) with the packed weights; biases are read from
+/* y[B][12] = network(x[B][5]) with the packed weights; biases are read from
  * 'params'.  1 <= batch <= the workspace's batch. */
 rt_status rt_mlp_forward(const float* params, const float* x, int64_t batch, float* y,
                          void* workspace, size_t workspace_bytes, void* stream);
 
 /* Forward and backward pass of the loss above: grad[rt_mlp_param_count()]
  * receives dL/dparams (overwritten), *loss (device, one float) the loss.
- * targets [B][8], mask [B][2].  Needs a training workspace. */
+ * targets [B][8], labels [B][4].  Needs a training workspace. */
 rt_status rt_mlp_gradients(const float* params, const float* x, const float* targets,
-                           const float* mask, int64_t batch, float* grad, float* loss,
+                           const float* labels, int64_t batch, float* grad, float* loss,
                            void* workspace, size_t workspace_bytes, void* stream);
 
 typedef struct {
@@ -101,8 +104,10 @@ rt_status rt_mlp_adam(float* params, float* m, float* v, const float* grad, int6
  *   targets   per family f (outputs 4f .. 4f+3):
  *             theta / (pi/2) - 1, c0 t / 3000 m - 1, s / 3000 m - 1,
  *             2 A - 1 with A = sqrt((|A_s|^2 + |A_p|^2) / 2);
- *             mask m_f = 1 where the tracer found the solution
- *   logits    outputs 8 + f: existence of family f's solution.
+ *   labels    m_f = 1 where the tracer found the solution, r_f = 1 where it
+ *             found more than one root (roots >= 2)
+ *   logits    outputs 8 + f: existence of family f's solution;
+ *             outputs 10 + f: more than one root in family f.
  *
  * Seeded secant of one (pair, family) entry: shot at the seed theta0, then
  * at theta0 + dseed (theta0 - dseed if that leaves (0, pi)), then secant
@@ -116,15 +121,16 @@ typedef struct {
   double verify_tol;   /* |miss| of the verifying shot (m), > 0 */
   double dseed;        /* second shot offset (rad), > 0 */
   int32_t max_shots;   /* shots per seeded entry, 2..64 */
-  float absent_logit;  /* existence logit at or below which an entry is
-                          declared absent without tracing */
+  float absent_logit;  /* existence logit at or below which an entry is not
+                          seeded (the tracer solves it) */
+  float multi_logit;   /* several-roots logit above which an entry is not
+                          seeded (the tracer picks its first arrival) */
 } rt_surrogate_params;
 
 /* How each entry [2 pair + family] of a surrogate solve was decided. */
 enum {
   RT_PATH_SURROGATE = 0, /* network seed, verified by a shot */
-  RT_PATH_TRACER = 1,    /* the pair went to the tracer's full solve */
-  RT_PATH_ABSENT = 2     /* declared absent by the network (not traced) */
+  RT_PATH_TRACER = 1     /* the tracer's full solve of the entry's family */
 };
 
 /* Seeded secant (above) of every entry [2 n] with seed_try != 0: results
@@ -142,23 +148,25 @@ rt_status raytrace_solve_seeded(const rt_field* field, const rt_boundaries* boun
 rt_status rt_surrogate_features(const rt_pairs* pairs, double z0, double dn, float* x,
                                 void* stream);
 
-/* Training targets [n][8] and masks [n][2] (FP32) from solve results. */
+/* Training targets [n][8] and labels [n][4] (FP32) from solve results. */
 rt_status rt_surrogate_targets(const rt_solve_outputs* solved, int64_t n, float* targets,
-                               float* mask, void* stream);
+                               float* labels, void* stream);
 
 /* Workspace bytes of raytrace_solve_surrogate for n_pairs pairs. */
 rt_status rt_surrogate_workspace_bytes(const rt_field* field, int64_t n_pairs,
                                        const rt_solve_params* fallback, size_t* bytes);
 
 /* Solve every pair with the network as seed: features -> network
- * (mlp_params, FP32 device array) -> per entry either declared absent
- * (logit <= absent_logit) or tried by the seeded secant; a pair with an
- * entry that was tried and not verified is solved again, both families, by
- * the tracer's full solve (raytrace_solve with 'fallback'), on the device
- * (no host synchronisation).  Results in out as for raytrace_solve; path
- * [2 n] (device) receives RT_PATH_*; *fallback_pairs (device, one int64)
- * the number of pairs solved by the tracer; out->stats the shots and steps
- * of the seeded phase plus the fallback solve. */
+ * (mlp_params, FP32 device array) -> per entry, the seeded secant when the
+ * network predicts one root (existence logit > absent_logit, several-roots
+ * logit <= multi_logit); every entry that is not seeded or whose seed is not
+ * verified is solved by the tracer's full solve of its family (raytrace_solve
+ * with 'fallback'), so the network never decides that an entry has no
+ * solution.  On the device (no host synchronisation).  Results in out as
+ * for raytrace_solve; path [2 n] (device) receives RT_PATH_*;
+ * *fallback_pairs (device, one int64) the number of pairs with an entry
+ * solved by the tracer; out->stats the shots and steps of the seeded phase
+ * plus the fallback solve. */
 rt_status raytrace_solve_surrogate(const rt_field* field, const rt_boundaries* boundaries,
                                    double tol, const rt_step_limits* limits,
                                    const rt_pairs* pairs, const rt_solve_params* fallback,

@@ -112,9 +112,12 @@ typedef struct {
  * bracket there; the device scans all n_scan angles in parallel and counts
  * its actual work in stats.shots).  theta: launch angle; miss: depth at the
  * receiver plane minus zr; t: travel time; s: path length; as_*, ap_*:
- * complex s/p amplitude factors (start 1 + 0i). */
+ * complex s/p amplitude factors (start 1 + 0i).  roots: refined brackets
+ * whose last shot met the receiver plane within accept_tol (the solution is
+ * the first arrival among them; 1 for an entry verified by the seeded
+ * secant, 0 without a solution). */
 typedef struct {
-  int32_t *found, *shots;
+  int32_t *found, *shots, *roots;
   double *theta, *miss, *t, *s, *as_re, *as_im, *ap_re, *ap_im;
   rt_solve_stats* stats; /* device, one struct; overwritten by each call */
 } rt_solve_outputs;
@@ -184,6 +187,7 @@ rt_status raytrace_shoot(const rt_field* field, const rt_boundaries* boundaries,
 /* Plumbing, no counterpart in the paper.  Pick launch tuning for
  * raytrace_solve by measurement: every combination of
  * block_size in {64, 128, 192, 256} and refill_threshold in {4, 16, 32, 64}
+ * (scan_chunk 1), then scan_chunk in {4, 16, 64} at the best of those, each
  * runs raytrace_solve once on 'pairs' (a representative sample; its results
  * land in 'out' and are overwritten by each candidate) after one untimed
  * call, timed with HIP events on 'stream'; the fastest is written to *best

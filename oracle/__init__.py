@@ -326,7 +326,7 @@ class SolveSpec(C.Structure):
                 ("slope_max", C.c_double)]
 
 
-SOLVE_I32 = ["found", "shots"]
+SOLVE_I32 = ["found", "shots", "roots"]
 SOLVE_F64 = ["theta", "miss", "t", "s", "as_re", "as_im", "ap_re", "ap_im"]
 
 

@@ -3,8 +3,9 @@
 Plain numpy, one layer at a time: z = W a + b, a' = SiLU(z) = z / (1 + e^-z)
 for the four hidden layers, a linear output layer; the loss of the C header
 (masked squared error of 8 regression outputs plus the binary cross-entropy of
-2 existence logits, averaged over the batch); backpropagation written out by
-the chain rule; Adam (Kingma & Ba 2015) with bias correction.
+2 existence and 2 several-roots logits, averaged over the batch);
+backpropagation written out by the chain rule; Adam (Kingma & Ba 2015) with
+bias correction.
 
 The GPU computes its matrix products from BF16-rounded weights and inputs;
 ``forward``/``gradients`` take ``bf16=True`` to evaluate the network at those
@@ -16,7 +17,7 @@ from __future__ import annotations
 
 import numpy as np
 
-N_IN, WIDTH, HIDDEN, N_OUT, N_TGT = 5, 256, 4, 10, 8
+N_IN, WIDTH, HIDDEN, N_OUT, N_TGT, N_LAB = 5, 256, 4, 12, 8, 4
 DIMS = [(N_IN, WIDTH)] + [(WIDTH, WIDTH)] * (HIDDEN - 1) + [(WIDTH, N_OUT)]
 
 
@@ -56,7 +57,7 @@ def silu_grad(z):
 
 
 def forward(params, x, bf16=True, act_bf16=False):
-    """Outputs [B][10] and the cache for backpropagation.  act_bf16 rounds
+    """Outputs [B][12] and the cache for backpropagation.  act_bf16 rounds
     the hidden activations to BF16 as the GPU stores them between layers."""
     layers = unpack(np.asarray(params, dtype=np.float64) if not bf16 else
                     np.asarray(params, dtype=np.float32))
@@ -75,7 +76,8 @@ def forward(params, x, bf16=True, act_bf16=False):
 
 
 def loss(y, t, m):
-    """Loss of the C header for outputs y [B][10], targets t [B][8], masks m [B][2]."""
+    """Loss of the C header for outputs y [B][12], targets t [B][8] and
+    labels m [B][4] (existence of families 0, 1; several roots in 0, 1)."""
     B = y.shape[0]
     L = 0.0
     for f in range(2):
@@ -83,6 +85,8 @@ def loss(y, t, m):
         L += np.sum(m[:, f:f + 1] * e * e)
         z = y[:, 8 + f]
         L += np.sum(np.logaddexp(0.0, z) - m[:, f] * z)
+        z = y[:, 10 + f]
+        L += np.sum(np.logaddexp(0.0, z) - m[:, 2 + f] * z)
     return L / B
 
 
@@ -93,6 +97,7 @@ def loss_grad_y(y, t, m):
         e = y[:, 4 * f:4 * f + 4] - t[:, 4 * f:4 * f + 4]
         d[:, 4 * f:4 * f + 4] = 2.0 * m[:, f:f + 1] * e / B
         d[:, 8 + f] = (1.0 / (1.0 + np.exp(-y[:, 8 + f])) - m[:, f]) / B
+        d[:, 10 + f] = (1.0 / (1.0 + np.exp(-y[:, 10 + f])) - m[:, 2 + f]) / B
     return d
 
 

@@ -169,9 +169,11 @@ typedef struct {
                            width (m/rad) hold no root; 0 = off */
 } orc_solve_spec;
 
-/* Outputs indexed [2 * pair + family]. */
+/* Outputs indexed [2 * pair + family].  roots: refined brackets whose last
+ * shot met the receiver plane within accept_tol (the solution is the first
+ * arrival among them); the seeded secant reports 1 for a verified entry. */
 typedef struct {
-  int32_t *found, *shots;
+  int32_t *found, *shots, *roots;
   double *theta, *miss, *t, *s, *as_re, *as_im, *ap_re, *ap_im;
 } orc_solve_out;
 

@@ -1160,7 +1160,7 @@ static void solve_one(worker_t* W, const scene_t* base, const orc_solve_spec* sp
   if (!pair_ok(base, zs, zr, D)) {
     for (int family = 0; family < 2; ++family) {
       const int64_t o = 2 * i + family;
-      out->found[o] = out->shots[o] = 0;
+      out->found[o] = out->shots[o] = out->roots[o] = 0;
       out->theta[o] = out->miss[o] = out->t[o] = out->s[o] = 0.0;
       out->as_re[o] = out->as_im[o] = out->ap_re[o] = out->ap_im[o] = 0.0;
     }
@@ -1172,7 +1172,7 @@ static void solve_one(worker_t* W, const scene_t* base, const orc_solve_spec* sp
   W->S = &S;
   for (int family = 0; family < 2; ++family) {
     const int64_t o = 2 * i + family;
-    int shots = 0, found = 0, brackets = 0;
+    int shots = 0, found = 0, brackets = 0, roots = 0;
     double best_theta = 0.0;
     shot_t best;
     memset(&best, 0, sizeof best);
@@ -1186,8 +1186,9 @@ static void solve_one(worker_t* W, const scene_t* base, const orc_solve_spec* sp
         double root;
         shot_t rs = refine(W, &S, sp, zs, zr, D, family, th_prev, prev.miss, th, sh.miss, &root,
                            &shots);
-        if (rs.status == SHOT_RECV && fabs(rs.miss) <= sp->accept_tol &&
-            (!found || rs.t < best.t)) {
+        const int admissible = rs.status == SHOT_RECV && fabs(rs.miss) <= sp->accept_tol;
+        roots += admissible;
+        if (admissible && (!found || rs.t < best.t)) {
           best = rs;
           best_theta = root;
           found = 1;
@@ -1199,6 +1200,7 @@ static void solve_one(worker_t* W, const scene_t* base, const orc_solve_spec* sp
     }
     out->found[o] = found;
     out->shots[o] = shots;
+    out->roots[o] = roots;
     out->theta[o] = found ? best_theta : 0.0;
     out->miss[o] = best.miss;
     out->t[o] = best.t;
@@ -1337,6 +1339,7 @@ static void seeded_one(worker_t* W, const scene_t* base, const double* zs_, cons
   }
   out->found[e] = success;
   out->shots[e] = shots;
+  out->roots[e] = success;
   out->theta[e] = success ? c : 0.0;
   out->miss[e] = success ? sh.miss : 0.0;
   out->t[e] = success ? sh.t : 0.0;

@@ -82,7 +82,7 @@ class rt_step_limits(C.Structure):
 STAT_FIELDS = ["accepted", "rejected", "relocation", "forced", "events", "spawned",
                "suppressed_gen", "suppressed_amp", "records", "needed", "nonfinite",
                "max_gen", "invalid", "refills", "sched_errors", "spilled", "interrupted",
-               "events_lost"]
+               "events_lost", "max_queue"]
 
 
 class rt_stats(C.Structure):
@@ -126,7 +126,8 @@ EVENT_DTYPE = np.dtype([("key", np.uint64), ("ordinal", np.int32), ("boundary", 
 class rt_tuning(C.Structure):
     _fields_ = [("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("refill_threshold", C.c_int32), ("ev_trace_begin", C.c_void_p),
-                ("ev_trace_end", C.c_void_p), ("local_queue", C.c_int32)]
+                ("ev_trace_end", C.c_void_p), ("local_queue", C.c_int32),
+                ("scan_chunk", C.c_int32)]
 
 
 # --- emitter -> receiver solves (include/radiotrace_solve.h) -----------------
@@ -152,7 +153,7 @@ class rt_solve_stats(C.Structure):
     _fields_ = [(f, C.c_int64) for f in SOLVE_STAT_FIELDS]
 
 
-SOLVE_I32 = ["found", "shots"]
+SOLVE_I32 = ["found", "shots", "roots"]
 SOLVE_F64 = ["theta", "miss", "t", "s", "as_re", "as_im", "ap_re", "ap_im"]
 
 
@@ -182,12 +183,13 @@ class rt_adam(C.Structure):
                 ("eps", C.c_float)]
 
 
-RT_PATH_SURROGATE, RT_PATH_TRACER, RT_PATH_ABSENT = 0, 1, 2
+RT_PATH_SURROGATE, RT_PATH_TRACER = 0, 1
 
 
 class rt_surrogate_params(C.Structure):
     _fields_ = [("z0", C.c_double), ("dn", C.c_double), ("verify_tol", C.c_double),
-                ("dseed", C.c_double), ("max_shots", C.c_int32), ("absent_logit", C.c_float)]
+                ("dseed", C.c_double), ("max_shots", C.c_int32), ("absent_logit", C.c_float),
+                ("multi_logit", C.c_float)]
 
 
 _lib = None
@@ -773,8 +775,8 @@ class DeviceMLP:
 
 # --- surrogate-seeded solves ----------------------------------------------------
 def surrogate_params(z0=75.0, dn=0.43, verify_tol=0.01, dseed=1e-4, max_shots=8,
-                     absent_logit=-2.0):
-    return rt_surrogate_params(z0, dn, verify_tol, dseed, max_shots, absent_logit)
+                     absent_logit=-2.0, multi_logit=-3.0):
+    return rt_surrogate_params(z0, dn, verify_tol, dseed, max_shots, absent_logit, multi_logit)
 
 
 def raytrace_solve_seeded(field, boundaries, tol, limits, pairs, seed, seed_try, sp, outputs,

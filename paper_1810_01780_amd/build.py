@@ -52,8 +52,9 @@ def build(verbose: bool = False) -> str:
             for (src, extra), obj in zip(jobs, objs)]
     with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
         list(ex.map(lambda c: _run(c, verbose), cmds))
-    _run([hipcc(), "--offload-arch=gfx950", "-fPIC", "-shared", "-o", LIB + ".tmp", *objs],
-         verbose)
+    # ROCTx (the rocprofiler-sdk marker library) for the host ranges
+    _run([hipcc(), "--offload-arch=gfx950", "-fPIC", "-shared", "-o", LIB + ".tmp", *objs,
+          "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"], verbose)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

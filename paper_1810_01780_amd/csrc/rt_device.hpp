@@ -249,41 +249,49 @@ __device__ constexpr int stage_degree(int s) {
 
 // strat_field_rel at stage S without a branch: slow is raised when the
 // exponent is outside the Taylor range of the stage (or NaN); the caller
-// then recomputes the step with strat_field_rel.  Media with dn = 0 have
-// inv_z0 = 0, so e = E0 and dn e = 0.
+// then recomputes the step with strat_field_rel.  dnE0 = dn E0 and
+// gE0 = (dn / z0) E0 are the step's factors of exp(-dz / z0) in n and dn/dz.
+// Media with dn = 0 have inv_z0 = 0 and both factors 0.
 template <int S>
 __device__ __forceinline__ void strat_field_stage_fast(const Medium& M, double z0, double dz,
-                                                       double E0, double& n, double& gz,
-                                                       bool& slow) {
+                                                       double dnE0, double gE0, double& n,
+                                                       double& gz, bool& slow) {
   constexpr int D = stage_degree(S);
   const double z = z0 + dz;
   const double x = -dz * M.inv_z0;
   slow = slow || !(fabs(x) <= taylor_max(D));
-  const double e = E0 * exp_taylor<D>(x);
-  n = fma(M.b, z, M.a) - M.dn * e;
-  gz = fma(M.dn_inv_z0, e, M.b);
+  const double p = exp_taylor<D>(x);
+  n = fma(-dnE0, p, fma(M.b, z, M.a));
+  gz = fma(gE0, p, M.b);
 }
 __device__ __forceinline__ void strat_field_fast_at(int st, const Medium& M, double z0, double dz,
-                                                    double E0, double& n, double& gz,
-                                                    bool& slow) {
+                                                    double dnE0, double gE0, double& n,
+                                                    double& gz, bool& slow) {
   switch (st) {
-    case 1: strat_field_stage_fast<1>(M, z0, dz, E0, n, gz, slow); break;
-    case 2: strat_field_stage_fast<2>(M, z0, dz, E0, n, gz, slow); break;
-    case 3: strat_field_stage_fast<3>(M, z0, dz, E0, n, gz, slow); break;
-    case 4: strat_field_stage_fast<4>(M, z0, dz, E0, n, gz, slow); break;
-    default: strat_field_stage_fast<5>(M, z0, dz, E0, n, gz, slow); break;
+    case 1: strat_field_stage_fast<1>(M, z0, dz, dnE0, gE0, n, gz, slow); break;
+    case 2: strat_field_stage_fast<2>(M, z0, dz, dnE0, gE0, n, gz, slow); break;
+    case 3: strat_field_stage_fast<3>(M, z0, dz, dnE0, gE0, n, gz, slow); break;
+    case 4: strat_field_stage_fast<4>(M, z0, dz, dnE0, gE0, n, gz, slow); break;
+    default: strat_field_stage_fast<5>(M, z0, dz, dnE0, gE0, n, gz, slow); break;
   }
 }
 
 // Trilinear n and gradient from float4 nodes (n, Dx, Dy, Dz); positions
-// outside the grid are clamped onto it; grad n = D / (2 spacing).
-__device__ __forceinline__ void grid_field(const KParams& P, double x, double y, double z,
-                                           double& n, double g[3]) {
+// outside the grid are clamped onto it; grad n = D / (2 spacing).  In two
+// parts, so that a caller can issue the eight corner loads of one
+// evaluation before it blends those of another: grid_fetch (cell, fractions
+// and the corner loads), grid_blend (weights and sums).
+struct GridFetch {
+  float4 c[8];
+  double t[3];
+};
+
+__device__ __forceinline__ void grid_fetch(const KParams& P, double x, double y, double z,
+                                           GridFetch& F) {
   const float4* __restrict__ nodes = static_cast<const float4*>(P.nodes);
   double f[3] = {(x - P.gorg[0]) * P.ginv[0], (y - P.gorg[1]) * P.ginv[1],
                  (z - P.gorg[2]) * P.ginv[2]};
   int i0[3];
-  double t[3];
   const int dims[3] = {P.gnx, P.gny, P.gnz};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -291,28 +299,38 @@ __device__ __forceinline__ void grid_field(const KParams& P, double x, double y,
     int i = (int)floor(v);
     i = min(i, dims[a] - 2);
     i0[a] = i;
-    t[a] = v - (double)i;
+    F.t[a] = v - (double)i;
   }
   const size_t sx = 1, sy = (size_t)P.gnx, sz = (size_t)P.gnx * P.gny;
   const size_t base = (size_t)i0[2] * sz + (size_t)i0[1] * sy + (size_t)i0[0];
-  float4 c[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q)
-    c[q] = nodes[base + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0)];
+    F.c[q] = nodes[base + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0)];
+}
+
+__device__ __forceinline__ void grid_blend(const KParams& P, const GridFetch& F, double& n,
+                                           double g[3]) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    double w = ((q & 1) ? t[0] : 1.0 - t[0]) * ((q & 2) ? t[1] : 1.0 - t[1]) *
-               ((q & 4) ? t[2] : 1.0 - t[2]);
-    acc[0] = fma(w, (double)c[q].x, acc[0]);
-    acc[1] = fma(w, (double)c[q].y, acc[1]);
-    acc[2] = fma(w, (double)c[q].z, acc[2]);
-    acc[3] = fma(w, (double)c[q].w, acc[3]);
+    double w = ((q & 1) ? F.t[0] : 1.0 - F.t[0]) * ((q & 2) ? F.t[1] : 1.0 - F.t[1]) *
+               ((q & 4) ? F.t[2] : 1.0 - F.t[2]);
+    acc[0] = fma(w, (double)F.c[q].x, acc[0]);
+    acc[1] = fma(w, (double)F.c[q].y, acc[1]);
+    acc[2] = fma(w, (double)F.c[q].z, acc[2]);
+    acc[3] = fma(w, (double)F.c[q].w, acc[3]);
   }
   n = acc[0];
   g[0] = acc[1] * P.ghalf[0];
   g[1] = acc[2] * P.ghalf[1];
   g[2] = acc[3] * P.ghalf[2];
+}
+
+__device__ __forceinline__ void grid_field(const KParams& P, double x, double y, double z,
+                                           double& n, double g[3]) {
+  GridFetch F;
+  grid_fetch(P, x, y, z, F);
+  grid_blend(P, F, n, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -339,6 +357,7 @@ __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], 
                                             double inv_tol, double y5[7], double& err,
                                             bool* slow_out = nullptr) {
   const double E0 = FAST ? exp_rr(-y[2] * M.inv_z0) : (M.dn != 0.0 ? exp(-y[2] * M.inv_z0) : 0.0);
+  const double dnE0 = M.dn * E0, gE0 = M.dn_inv_z0 * E0;
   bool slow = false;
   if constexpr (MODEL == RT_MODEL_PAPER) {
     // w = unit velocity, renormalised after every accepted step (|w| = 1).
@@ -356,7 +375,7 @@ __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], 
 #pragma unroll
         for (int i = 0; i + 1 < st; ++i) acc = fma(ck_aa(st, i), kw[i], acc);
         const double dz = h * fma(h, acc, ck_c(st) * y[5]);
-        if constexpr (FAST) strat_field_fast_at(st, M, y[2], dz, E0, n, gz, slow);
+        if constexpr (FAST) strat_field_fast_at(st, M, y[2], dz, dnE0, gE0, n, gz, slow);
         else strat_field_rel(M, y[2], dz, E0, n, gz);
       }
       kw[st] = gz * rcp_nr(n);
@@ -458,6 +477,66 @@ __device__ __forceinline__ void stage_vec(const double y[7], double h, const dou
     for (int j = 0; j < 6; ++j) kc[j] = k[c][j];
     ys[c] = stage_in<S>(y[c], h, kc);
   }
+}
+
+// Paper-model trial in a gridded medium without anomalies (trial_3d's
+// Nystrom form, same arithmetic): stage s's position needs the derivatives
+// of stages 0 .. s-2 only ((A^2)_s,s-1 = 0), so the corner loads of stage
+// s + 1 are issued before stage s is blended, and two stages' gathers are
+// in flight at a time.
+__device__ __forceinline__ void trial_grid_paper(const KParams& P, const double y[7], double h,
+                                                 double inv_tol, double y5[7], double& err) {
+  double kw[3][6];
+  double tsum = 0.0;
+  GridFetch F[2];
+  grid_fetch(P, y[0], y[1], y[2], F[0]);
+  {
+    const double c1h = ck_c(1) * h;
+    grid_fetch(P, fma(c1h, y[3], y[0]), fma(c1h, y[4], y[1]), fma(c1h, y[5], y[2]), F[1]);
+  }
+#pragma unroll
+  for (int st = 0; st < 6; ++st) {
+    double n, g[3];
+    grid_blend(P, F[st & 1], n, g);
+    const double in = rcp_nr(n);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) kw[c][st] = g[c] * in;
+    if (st == 0) tsum = kB1 * n;
+    if (st == 2) tsum = fma(kB3, n, tsum);
+    if (st == 3) tsum = fma(kB4, n, tsum);
+    if (st == 5) tsum = fma(kB6, n, tsum);
+    const int nx = st + 2;  // the stage whose loads go out now
+    if (nx < 6) {
+      double rs[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i + 1 < nx; ++i) acc = fma(ck_aa(nx, i), kw[c][i], acc);
+        rs[c] = fma(h, fma(h, acc, ck_c(nx) * y[3 + c]), y[c]);
+      }
+      grid_fetch(P, rs[0], rs[1], rs[2], F[st & 1]);
+    }
+  }
+  double dr[3], dw[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double ba = 0.0, ea = 0.0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      ba = fma(ck_ba(i), kw[c][i], ba);
+      ea = fma(ck_ea(i), kw[c][i], ea);
+    }
+    y5[c] = fma(h, fma(h, ba, y[3 + c]), y[c]);
+    y5[3 + c] = fma(h, b_sum(kw[c]), y[3 + c]);
+    dr[c] = h * ea;
+    dw[c] = e_sum(kw[c]);
+  }
+  y5[6] = fma(h * kInvC0, tsum, y[6]);
+  const double dr_h = sqrt(fma(dr[0], dr[0], fma(dr[1], dr[1], dr[2] * dr[2])));
+  const double dw_h = sqrt(fma(dw[0], dw[0], fma(dw[1], dw[1], dw[2] * dw[2])));
+  const double iw0 = rsqrt_nr(fma(y[3], y[3], fma(y[4], y[4], y[5] * y[5])));
+  err = fmax(dr_h, h * dw_h * iw0) * inv_tol;
 }
 
 template <int MODEL>
@@ -820,7 +899,11 @@ template <int MODEL, int FIELD>
 __device__ __forceinline__ void trial(const KParams& P, const Ray& R, double h, double y5[7],
                                       double& err) {
   if constexpr (FIELD == 1) {
-    trial_3d<MODEL>(P, medium_of(P, R.region), R.y, h, P.inv_tol, y5, err);
+    const Medium M = medium_of(P, R.region);
+    if (MODEL == RT_MODEL_PAPER && M.use_grid && P.n_anom == 0)
+      trial_grid_paper(P, R.y, h, P.inv_tol, y5, err);
+    else
+      trial_3d<MODEL>(P, M, R.y, h, P.inv_tol, y5, err);
   } else {
     if constexpr (MODEL == RT_MODEL_PAPER) {
       // the branch-free form first (one basic block, so the stages' code can

@@ -5,6 +5,8 @@
 #include <cstdio>
 #include <cstring>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "radiotrace_mlp.h"
 #include "radiotrace_solve.h"
 #include "rt_params.hpp"
@@ -13,6 +15,9 @@
 namespace rt {
 
 static thread_local char g_err[512];
+
+Range::Range(const char* name) { roctxRangePushA(name); }
+Range::~Range() { roctxRangePop(); }
 
 void set_last_error(const char* fmt, ...) {
   va_list ap;
@@ -149,8 +154,9 @@ rt_status check_surrogate_params(const rt_surrogate_params* sp) {
     FAIL(RT_ERR_INVALID_ARG, "verify_tol must be > 0");
   if (!(sp->dseed > 0.0) || !(sp->dseed < 0.5)) FAIL(RT_ERR_INVALID_ARG, "need 0 < dseed < 0.5");
   if (sp->max_shots < 2 || sp->max_shots > 64) FAIL(RT_ERR_INVALID_ARG, "max_shots must be 2..64");
-  if (!std::isfinite(sp->z0) || !std::isfinite(sp->dn) || std::isnan(sp->absent_logit))
-    FAIL(RT_ERR_INVALID_ARG, "non-finite profile features or logit threshold");
+  if (!std::isfinite(sp->z0) || !std::isfinite(sp->dn) || std::isnan(sp->absent_logit) ||
+      std::isnan(sp->multi_logit))
+    FAIL(RT_ERR_INVALID_ARG, "non-finite profile features or NaN logit threshold");
   return RT_OK;
 }
 
@@ -191,6 +197,7 @@ rt_status rt_workspace_bytes(const rt_field* field, int64_t capacity, size_t* by
 }
 
 rt_status rt_collect(const rt_stats* s, int64_t capacity) {
+  rt::Range range("rt_collect");
   if (!s) {
     rt::set_last_error("null stats");
     return RT_ERR_INVALID_ARG;

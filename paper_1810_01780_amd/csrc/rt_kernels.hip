@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <optional>
 
 #include "rt_trace.hpp"
 
@@ -610,6 +611,8 @@ rt_status launch_trace(const rt_field* field, const rt_boundaries* bnd, const rt
   }
 
   const unsigned cap_blocks = (unsigned)((out->capacity + 255) / 256);
+  std::optional<Range> range;  // the enqueue phases, for a profiler's timeline
+  range.emplace("raytrace_launch: reset, init, order");
   if (L->resume) {
     hipLaunchKernelGGL(resume_reset_kernel, dim3(1), dim3(64), 0, s, P);
     HIP_TRY(hipGetLastError());
@@ -664,6 +667,8 @@ rt_status launch_trace(const rt_field* field, const rt_boundaries* bnd, const rt
   P.chunk_limit = chunked ? (uint64_t)(out->capacity - reserve) : 0;
   P.reserve = chunked ? (uint64_t)reserve : 0;
 
+  range.reset();
+  range.emplace("raytrace_launch: trace, compaction");
   if (tuning && tuning->ev_trace_begin)
     HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(tuning->ev_trace_begin), s));
   hipError_t e;

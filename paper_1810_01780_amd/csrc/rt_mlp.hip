@@ -27,6 +27,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 constexpr int kLayers = RT_MLP_HIDDEN + 1;
+static_assert(RT_MLP_OUT <= 16, "the output gradients are held 16 wide");
 constexpr int kIn[kLayers] = {RT_MLP_IN, RT_MLP_WIDTH, RT_MLP_WIDTH, RT_MLP_WIDTH, RT_MLP_WIDTH};
 constexpr int kOut[kLayers] = {RT_MLP_WIDTH, RT_MLP_WIDTH, RT_MLP_WIDTH, RT_MLP_WIDTH,
                                RT_MLP_OUT};
@@ -174,6 +175,7 @@ __global__ void features_kernel(const float* __restrict__ x, int64_t B, int64_t 
 
 // Loss of the header and its gradient w.r.t. the outputs; dY [B][16] and
 // dYT [16][Bp] in BF16 (zero padding), per-block partial sums of the loss.
+// Labels per row: existence of families 0, 1, then several roots in 0, 1.
 __global__ void __launch_bounds__(256) loss_kernel(const float* __restrict__ y,
                                                    const float* __restrict__ t,
                                                    const float* __restrict__ m, int64_t B,
@@ -190,7 +192,7 @@ __global__ void __launch_bounds__(256) loss_kernel(const float* __restrict__ y,
       const float invB = 1.0f / (float)B;
 #pragma unroll
       for (int f = 0; f < 2; ++f) {
-        const float mf = m[b * 2 + f];
+        const float mf = m[b * RT_MLP_LABELS + f];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const float e = y[b * RT_MLP_OUT + 4 * f + q] - t[b * RT_MLP_TARGETS + 4 * f + q];
@@ -201,6 +203,10 @@ __global__ void __launch_bounds__(256) loss_kernel(const float* __restrict__ y,
         // log(1 + e^z) - m z, evaluated without overflow
         l += fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))) - mf * z;
         d[8 + f] = (1.0f / (1.0f + expf(-z)) - mf) * invB;
+        const float rf = m[b * RT_MLP_LABELS + 2 + f];
+        const float zr = y[b * RT_MLP_OUT + 10 + f];
+        l += fmaxf(zr, 0.0f) + log1pf(expf(-fabsf(zr))) - rf * zr;
+        d[10 + f] = (1.0f / (1.0f + expf(-zr)) - rf) * invB;
       }
 #pragma unroll
       for (int q = 0; q < 16; ++q) dY[b * 16 + q] = (bf16)d[q];

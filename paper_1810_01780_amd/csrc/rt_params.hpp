@@ -92,6 +92,15 @@ struct KParams {
   rt_stats* stats;
 };
 
+// A ROCTx range over a host scope (rocprofv3 --marker-trace shows it on the
+// calling thread's timeline): the enqueue phases of the entry points.
+struct Range {
+  explicit Range(const char* name);
+  ~Range();
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+
 // Host helpers shared by the launcher (rt_launch.hip) and rt_host.cpp.
 void set_last_error(const char* fmt, ...);
 rt_status validate(const rt_field* field, const rt_boundaries* boundaries,

@@ -61,6 +61,7 @@ struct KSolve {
   int64_t n;                     // pairs or shots
   int64_t n_tasks;
   int32_t n_scan, max_iter, max_brackets, refill;
+  int32_t scan_chunk;            // scan: entries whose angles interleave
   double miss_tol, accept_tol, slope_max, dtheta;
   uint64_t* tickets;  // one counter per phase
   double* scan_miss;  // [2 n][n_scan]
@@ -80,6 +81,9 @@ struct KSolve {
   int32_t* verify;
   double verify_tol, dseed;
   int32_t max_shots;
+  // scan and refine: per pair, bit f set = solve family f; NULL = both
+  // (the other family's entries are left as no solution)
+  const uint8_t* fam_mask;
 };
 
 // A pair can be shot if its values are finite, the distance is positive and
@@ -347,6 +351,7 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
           const rt_solve_outputs& O = V.so;
           O.found[t] = success ? 1 : 0;
           O.shots[t] = shots;
+          O.roots[t] = success ? 1 : 0;
           O.theta[t] = success ? c : 0.0;
           O.miss[t] = success ? fin.miss : 0.0;
           O.t[t] = success ? R.y[6] : 0.0;
@@ -439,7 +444,7 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
         if (base + nidle >= (uint64_t)n_tasks) exhausted = true;
         const uint64_t task = base + (uint64_t)__popcll(idle & lanemask_lt());
         if (lane_idle && task < (uint64_t)n_tasks) {
-          const int64_t t = (int64_t)task;
+          int64_t t = (int64_t)task;
           double zs = 0.0, zr = 0.0, theta = 0.0;
           bool go = false;
           if constexpr (PHASE == PH_LIST) {
@@ -460,15 +465,23 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
               C.bump(V_INVALID);
             }
           } else if constexpr (PHASE == PH_SCAN) {
-            const int64_t pf = t / V.n_scan;
-            const int k = (int)(t - pf * V.n_scan);
+            // tasks in chunks of scan_chunk entries: within a chunk the
+            // angle varies slowest, so consecutive lanes shoot one angle for
+            // neighbouring entries (the last chunk may be short)
+            const int64_t C = V.scan_chunk, n2 = 2 * n_pairs;
+            const int64_t ch = t / (C * V.n_scan), r = t - ch * C * V.n_scan;
+            const int64_t ne = min(C, n2 - ch * C);
+            const int64_t pf = ch * C + r % ne;
+            const int k = (int)(r / ne);
+            t = pf * V.n_scan + k;  // the scan's miss array is [entry][angle]
             S.pair = (int32_t)(pf >> 1);
             S.fam = (int32_t)(pf & 1);
             S.D = V.dist[S.pair];
             zs = V.zs[S.pair];
             zr = V.zr[S.pair];
             theta = ((double)k + 0.5) * V.dtheta;
-            go = pair_ok(P, zs, zr, S.D);
+            go = pair_ok(P, zs, zr, S.D) &&
+                 (!V.fam_mask || ((V.fam_mask[S.pair] >> S.fam) & 1));
             if (!go) V.scan_miss[t] = 0.0;  // no sign change: no bracket
           } else if constexpr (PHASE == PH_SEEDED) {
             S.pair = (int32_t)(t >> 1);
@@ -486,6 +499,7 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
                 const rt_solve_outputs& O = V.so;
                 O.found[t] = 0;
                 O.shots[t] = 0;
+                O.roots[t] = 0;
                 O.theta[t] = O.miss[t] = O.t[t] = O.s[t] = 0.0;
                 O.as_re[t] = O.as_im[t] = O.ap_re[t] = O.ap_im[t] = 0.0;
                 V.verify[t] = 0;
@@ -732,7 +746,7 @@ __global__ void select_kernel(KParams P, KSolve V) {
   const rt_solve_outputs& O = V.so;
   const int32_t pair = (int32_t)(pf >> 1);
   const int64_t n2 = 2 * n;
-  int best = -1, nb = 0, last_k = -1, refine_shots = 0;
+  int best = -1, nb = 0, last_k = -1, refine_shots = 0, roots = 0;
   double best_t = 0.0;
   const bool ok = pair_ok(P, V.zs[pair], V.zr[pair], V.dist[pair]);
   if (ok) {
@@ -743,8 +757,9 @@ __global__ void select_kernel(KParams P, KSolve V) {
       ++nb;
       last_k = V.b_k[i];
       refine_shots += V.b_shots[i];
-      if (st == RT_SHOT_RECEIVER && fabs(V.b_miss[i]) <= V.accept_tol &&
-          (best < 0 || V.b_t[i] < best_t)) {
+      const bool admissible = st == RT_SHOT_RECEIVER && fabs(V.b_miss[i]) <= V.accept_tol;
+      roots += admissible ? 1 : 0;
+      if (admissible && (best < 0 || V.b_t[i] < best_t)) {
         best = b;
         best_t = V.b_t[i];
       }
@@ -756,6 +771,7 @@ __global__ void select_kernel(KParams P, KSolve V) {
   // reaches max_brackets
   const int scan_shots = nb >= V.max_brackets ? last_k + 1 : V.n_scan;
   O.shots[pf] = ok ? scan_shots + refine_shots : 0;
+  O.roots[pf] = roots;
   O.found[pf] = best >= 0;
   if (best >= 0) {
     const int64_t i = (int64_t)best * n2 + pf;
@@ -893,15 +909,16 @@ rt_status check_pairs_outputs(const rt_pairs* pairs, const rt_solve_outputs* out
     set_last_error("null pair array");
     return RT_ERR_INVALID_ARG;
   }
-  if (pairs->n > 0 && (!out->found || !out->shots || !out->theta || !out->miss || !out->t ||
-                       !out->s || !out->as_re || !out->as_im || !out->ap_re || !out->ap_im)) {
+  if (pairs->n > 0 && (!out->found || !out->shots || !out->roots || !out->theta || !out->miss ||
+                       !out->t || !out->s || !out->as_re || !out->as_im || !out->ap_re ||
+                       !out->ap_im)) {
     set_last_error("null output array");
     return RT_ERR_INVALID_ARG;
   }
   return RT_OK;
 }
 
-rt_status tuning_of(const rt_tuning* tuning, int& block, int& refill) {
+rt_status tuning_of(const rt_tuning* tuning, int& block, int& refill, int& chunk) {
   block = tuning && tuning->block_size ? tuning->block_size : 256;
   if (block < 64 || block > 256 || block % 64) {
     set_last_error("block_size must be 64, 128, 192 or 256");
@@ -910,6 +927,11 @@ rt_status tuning_of(const rt_tuning* tuning, int& block, int& refill) {
   refill = tuning && tuning->refill_threshold ? tuning->refill_threshold : 16;
   if (refill < 1 || refill > 64) {
     set_last_error("refill_threshold must be 1..64");
+    return RT_ERR_INVALID_ARG;
+  }
+  chunk = tuning && tuning->scan_chunk ? tuning->scan_chunk : 1;
+  if (chunk < 1 || chunk > 4096) {
+    set_last_error("scan_chunk must be 1..4096");
     return RT_ERR_INVALID_ARG;
   }
   return RT_OK;
@@ -933,17 +955,23 @@ namespace rt {
 // *n_dev when n_dev is not NULL); arguments already validated.
 rt_status solve_enqueue(const rt_field* field, const rt_boundaries* bnd, double tol,
                         const rt_step_limits* L, const rt_pairs* pairs, int64_t n_cap,
-                        const int64_t* n_dev, const rt_solve_params* prm,
-                        const rt_solve_outputs* out, void* workspace, void* stream,
-                        const rt_tuning* tuning) {
+                        const int64_t* n_dev, const uint8_t* fam_mask,
+                        const rt_solve_params* prm, const rt_solve_outputs* out, void* workspace,
+                        void* stream, const rt_tuning* tuning) {
   rt_status st;
-  int block = 0, refill = 0, n_cu = 0;
-  if ((st = tuning_of(tuning, block, refill)) != RT_OK) return st;
+  int block = 0, refill = 0, chunk = 0, n_cu = 0;
+  if ((st = tuning_of(tuning, block, refill, chunk)) != RT_OK) return st;
   KParams P;
   if ((st = pack_params(field, bnd, tol, L, P)) != RT_OK) return st;
   if ((st = device_cus(n_cu)) != RT_OK) return st;
 
   const int64_t n = n_cap, K = prm->n_scan, B = prm->max_brackets;
+  // a lane holds its task index in 32 bits
+  if (2 * n * std::max(K, B) > (int64_t)0x7fffffff) {
+    set_last_error("pairs x 2 x max(n_scan, max_brackets) = %lld exceeds 2^31 - 1 tasks",
+                   (long long)(2 * n * std::max(K, B)));
+    return RT_ERR_UNSUPPORTED;
+  }
   KSolve V;
   memset(&V, 0, sizeof V);
   V.zs = pairs->zs;
@@ -951,6 +979,8 @@ rt_status solve_enqueue(const rt_field* field, const rt_boundaries* bnd, double 
   V.dist = pairs->dist;
   V.n = n;
   V.n_dev = n_dev;
+  V.fam_mask = fam_mask;
+  V.scan_chunk = chunk;
   V.n_scan = prm->n_scan;
   V.max_iter = prm->max_iter;
   V.max_brackets = prm->max_brackets;
@@ -980,6 +1010,7 @@ rt_status solve_enqueue(const rt_field* field, const rt_boundaries* bnd, double 
   V.so = *out;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
+  Range range("raytrace_solve: scan, refine, select");
   hipLaunchKernelGGL(solve_reset_kernel, dim3(1), dim3(64), 0, s, V);
   HIP_TRY(hipGetLastError());
   if (n == 0) return RT_OK;
@@ -1006,8 +1037,8 @@ rt_status seeded_enqueue(const rt_field* field, const rt_boundaries* bnd, double
                          const rt_solve_outputs* out, int32_t* verify, void* workspace,
                          void* stream, const rt_tuning* tuning) {
   rt_status st;
-  int block = 0, refill = 0, n_cu = 0;
-  if ((st = tuning_of(tuning, block, refill)) != RT_OK) return st;
+  int block = 0, refill = 0, chunk = 0, n_cu = 0;
+  if ((st = tuning_of(tuning, block, refill, chunk)) != RT_OK) return st;
   KParams P;
   if ((st = pack_params(field, bnd, tol, L, P)) != RT_OK) return st;
   if ((st = device_cus(n_cu)) != RT_OK) return st;
@@ -1029,6 +1060,7 @@ rt_status seeded_enqueue(const rt_field* field, const rt_boundaries* bnd, double
   V.dseed = sp->dseed;
   V.max_shots = sp->max_shots;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  Range range("raytrace_solve_seeded: seeded secant");
   hipLaunchKernelGGL(solve_reset_kernel, dim3(1), dim3(64), 0, s, V);
   HIP_TRY(hipGetLastError());
   HIP_TRY(launch_shots<PH_SEEDED>(P, V, n_cu, block, s));
@@ -1057,8 +1089,8 @@ extern "C" rt_status raytrace_solve(const rt_field* field, const rt_boundaries* 
     set_last_error("workspace of %zu bytes < %zu needed", workspace_bytes, need);
     return RT_ERR_INVALID_ARG;
   }
-  return solve_enqueue(field, bnd, tol, L, pairs, pairs->n, nullptr, prm, out, workspace,
-                       stream, tuning);
+  return solve_enqueue(field, bnd, tol, L, pairs, pairs->n, nullptr, nullptr, prm, out,
+                       workspace, stream, tuning);
 }
 
 extern "C" rt_status raytrace_solve_seeded(const rt_field* field, const rt_boundaries* bnd,
@@ -1120,8 +1152,8 @@ extern "C" rt_status raytrace_shoot(const rt_field* field, const rt_boundaries* 
     set_last_error("workspace of %zu bytes < %zu needed", workspace_bytes, need);
     return RT_ERR_INVALID_ARG;
   }
-  int block = 0, refill = 0, n_cu = 0;
-  if ((st = tuning_of(tuning, block, refill)) != RT_OK) return st;
+  int block = 0, refill = 0, chunk = 0, n_cu = 0;
+  if ((st = tuning_of(tuning, block, refill, chunk)) != RT_OK) return st;
   KParams P;
   if ((st = pack_params(field, bnd, tol, L, P)) != RT_OK) return st;
   if ((st = device_cus(n_cu)) != RT_OK) return st;
@@ -1171,6 +1203,7 @@ extern "C" rt_status rt_solve_autotune(const rt_field* field, const rt_boundarie
   }
   static const int kBlocks[] = {64, 128, 192, 256};
   static const int kRefill[] = {4, 16, 32, 64};
+  static const int kChunks[] = {1, 4, 16, 64};
   rt_status st = RT_OK;
   float best_t = -1.0f;
   rt_tuning cand;
@@ -1178,30 +1211,41 @@ extern "C" rt_status rt_solve_autotune(const rt_field* field, const rt_boundarie
   // one untimed call first (code load, caches)
   cand.block_size = 256;
   cand.refill_threshold = 16;
+  cand.scan_chunk = 1;
   st = raytrace_solve(field, bnd, tol, L, pairs, prm, out, workspace, workspace_bytes, stream,
                       &cand);
+  auto trial = [&](const rt_tuning& c) {
+    hipError_t e = hipEventRecord(e0, s);
+    if (e == hipSuccess)
+      st = raytrace_solve(field, bnd, tol, L, pairs, prm, out, workspace, workspace_bytes,
+                          stream, &c);
+    if (e == hipSuccess && st == RT_OK) e = hipEventRecord(e1, s);
+    if (e == hipSuccess && st == RT_OK) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess && st == RT_OK) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      set_last_error("autotune timing: %s", hipGetErrorString(e));
+      st = RT_ERR_DEVICE;
+      return;
+    }
+    if (st == RT_OK && (best_t < 0.0f || ms < best_t)) {
+      best_t = ms;
+      *best = c;
+    }
+  };
+  // block size x refill threshold with each entry's scan in one piece, then
+  // the scan interleave at the best of those
   for (int bi = 0; st == RT_OK && bi < 4; ++bi)
     for (int ri = 0; st == RT_OK && ri < 4; ++ri) {
       cand.block_size = kBlocks[bi];
       cand.refill_threshold = kRefill[ri];
-      hipError_t e = hipEventRecord(e0, s);
-      if (e == hipSuccess)
-        st = raytrace_solve(field, bnd, tol, L, pairs, prm, out, workspace, workspace_bytes,
-                            stream, &cand);
-      if (e == hipSuccess && st == RT_OK) e = hipEventRecord(e1, s);
-      if (e == hipSuccess && st == RT_OK) e = hipEventSynchronize(e1);
-      float ms = 0.0f;
-      if (e == hipSuccess && st == RT_OK) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        set_last_error("autotune timing: %s", hipGetErrorString(e));
-        st = RT_ERR_DEVICE;
-        break;
-      }
-      if (st == RT_OK && (best_t < 0.0f || ms < best_t)) {
-        best_t = ms;
-        *best = cand;
-      }
+      trial(cand);
     }
+  for (int ci = 1; st == RT_OK && ci < 4; ++ci) {
+    cand = *best;
+    cand.scan_chunk = kChunks[ci];
+    trial(cand);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st == RT_OK && best_ms) *best_ms = best_t;

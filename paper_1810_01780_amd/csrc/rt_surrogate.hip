@@ -50,7 +50,8 @@ __global__ void targets_kernel(rt_solve_outputs S, int64_t n, float* __restrict_
     o[1] = ok ? (float)(kC0 * S.t[e] / 3000.0 - 1.0) : 0.0f;
     o[2] = ok ? (float)(S.s[e] / 3000.0 - 1.0) : 0.0f;
     o[3] = ok ? (float)(2.0 * A - 1.0) : 0.0f;
-    m[i * 2 + f] = ok ? 1.0f : 0.0f;
+    m[i * RT_MLP_LABELS + f] = ok ? 1.0f : 0.0f;
+    m[i * RT_MLP_LABELS + 2 + f] = S.roots[e] >= 2 ? 1.0f : 0.0f;
   }
 }
 
@@ -58,38 +59,38 @@ __global__ void reset_kernel(int64_t* count) {
   if (threadIdx.x == 0) *count = 0;
 }
 
-// Network outputs -> seed angle and decision per entry; entries declared
-// absent get their (empty) result here.
+// Network outputs -> seed angle and decision per entry: an entry whose
+// existence logit is at or below absent_logit, or whose several-roots logit
+// is above multi_logit, is not seeded (the tracer solves it).
 __global__ void decode_kernel(const float* __restrict__ y, int64_t n, float absent_logit,
-                              double* __restrict__ seed, int32_t* __restrict__ seed_try,
-                              int32_t* __restrict__ verify, int32_t* __restrict__ path,
-                              rt_solve_outputs O) {
+                              float multi_logit, double* __restrict__ seed,
+                              int32_t* __restrict__ seed_try, int32_t* __restrict__ verify,
+                              int32_t* __restrict__ path) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= 2 * n) return;
   const int64_t i = e >> 1;
   const int f = (int)(e & 1);
   const double th = 0.5 * kPi * (1.0 + (double)y[i * RT_MLP_OUT + 4 * f]);
   seed[e] = fmin(fmax(th, 1e-6), kPi - 1e-6);
-  const bool tried = y[i * RT_MLP_OUT + 8 + f] > absent_logit;
+  const bool tried = y[i * RT_MLP_OUT + 8 + f] > absent_logit &&
+                     !(y[i * RT_MLP_OUT + 10 + f] > multi_logit);
   seed_try[e] = tried ? 1 : 0;
   verify[e] = -1;
-  path[e] = tried ? RT_PATH_SURROGATE : RT_PATH_ABSENT;
-  if (!tried) {
-    O.found[e] = 0;
-    O.shots[e] = 0;
-    O.theta[e] = O.miss[e] = O.t[e] = O.s[e] = 0.0;
-    O.as_re[e] = O.as_im[e] = O.ap_re[e] = O.ap_im[e] = 0.0;
-  }
+  path[e] = RT_PATH_SURROGATE;
 }
 
-// Pairs with a tried entry that was not verified -> fallback list.
+// Pairs with an entry that is not verified (not seeded, or its seed failed)
+// -> fallback list, with the families to solve (bit f = family f).
 __global__ void flag_kernel(const int32_t* __restrict__ verify, int64_t n,
-                            int64_t* __restrict__ count, int64_t* __restrict__ idx) {
+                            int64_t* __restrict__ count, int64_t* __restrict__ idx,
+                            uint8_t* __restrict__ fam) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (verify[2 * i] == 0 || verify[2 * i + 1] == 0) {
+  const uint8_t m = (uint8_t)((verify[2 * i] != 1 ? 1 : 0) | (verify[2 * i + 1] != 1 ? 2 : 0));
+  if (m) {
     const unsigned long long k = atomicAdd(reinterpret_cast<unsigned long long*>(count), 1ull);
     idx[k] = i;
+    fam[k] = m;
   }
 }
 
@@ -106,16 +107,19 @@ __global__ void gather_kernel(const int64_t* __restrict__ idx, const int64_t* __
   cdist[i] = dist[p];
 }
 
+// The tracer's results of the fallback entries into place.
 __global__ void scatter_kernel(const int64_t* __restrict__ idx, const int64_t* __restrict__ count,
-                               int64_t n, rt_solve_outputs C, rt_solve_outputs O,
-                               int32_t* __restrict__ path) {
+                               const uint8_t* __restrict__ fam, int64_t n, rt_solve_outputs C,
+                               rt_solve_outputs O, int32_t* __restrict__ path) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || i >= *count) return;
   const int64_t p = idx[i];
   for (int f = 0; f < 2; ++f) {
+    if (!((fam[i] >> f) & 1)) continue;
     const int64_t a = 2 * i + f, e = 2 * p + f;
     O.found[e] = C.found[a];
     O.shots[e] = C.shots[a];
+    O.roots[e] = C.roots[a];
     O.theta[e] = C.theta[a];
     O.miss[e] = C.miss[a];
     O.t[e] = C.t[a];
@@ -148,8 +152,9 @@ struct Layout {
   double* seed;
   int32_t *seed_try, *verify;
   int64_t* idx;
+  uint8_t* fam;
   double *czs, *czr, *cdist;
-  int32_t *c_found, *c_shots;
+  int32_t *c_found, *c_shots, *c_roots;
   double* c_f64[8];
   void* solve_ws;
   size_t solve_bytes;
@@ -182,11 +187,13 @@ rt_status layout(const rt_field* field, int64_t n, const rt_solve_params* fb, ch
   L.seed_try = reinterpret_cast<int32_t*>(take((size_t)nb * 8));
   L.verify = reinterpret_cast<int32_t*>(take((size_t)nb * 8));
   L.idx = reinterpret_cast<int64_t*>(take((size_t)nb * 8));
+  L.fam = reinterpret_cast<uint8_t*>(take((size_t)nb));
   L.czs = reinterpret_cast<double*>(take((size_t)nb * 8));
   L.czr = reinterpret_cast<double*>(take((size_t)nb * 8));
   L.cdist = reinterpret_cast<double*>(take((size_t)nb * 8));
   L.c_found = reinterpret_cast<int32_t*>(take((size_t)nb * 8));
   L.c_shots = reinterpret_cast<int32_t*>(take((size_t)nb * 8));
+  L.c_roots = reinterpret_cast<int32_t*>(take((size_t)nb * 8));
   for (int k = 0; k < 8; ++k) L.c_f64[k] = reinterpret_cast<double*>(take((size_t)nb * 16));
   rt_status st = rt_solve_workspace_bytes(field, nb, fb, &L.solve_bytes);
   if (st != RT_OK) return st;
@@ -224,10 +231,11 @@ extern "C" rt_status rt_surrogate_features(const rt_pairs* pairs, double z0, dou
 
 extern "C" rt_status rt_surrogate_targets(const rt_solve_outputs* solved, int64_t n,
                                           float* targets, float* mask, void* stream) {
-  if (!solved || n < 0 || (n > 0 && (!targets || !mask || !solved->found || !solved->theta ||
+  if (!solved || n < 0 || (n > 0 && (!targets || !mask || !solved->found || !solved->roots ||
+                                     !solved->theta ||
                                      !solved->t || !solved->s || !solved->as_re ||
                                      !solved->as_im || !solved->ap_re || !solved->ap_im))) {
-    rt::set_last_error("null or invalid solve outputs, targets or mask");
+    rt::set_last_error("null or invalid solve outputs, targets or labels");
     return RT_ERR_INVALID_ARG;
   }
   if (n == 0) return RT_OK;
@@ -274,6 +282,7 @@ extern "C" rt_status raytrace_solve_surrogate(const rt_field* field, const rt_bo
     return RT_ERR_INVALID_ARG;
   }
   if (pairs->n > 0 && (!pairs->zs || !pairs->zr || !pairs->dist || !out->found || !out->shots ||
+                       !out->roots ||
                        !out->theta || !out->miss || !out->t || !out->s || !out->as_re ||
                        !out->as_im || !out->ap_re || !out->ap_im)) {
     set_last_error("null pair or output array");
@@ -291,6 +300,7 @@ extern "C" rt_status raytrace_solve_surrogate(const rt_field* field, const rt_bo
   const unsigned g1 = (unsigned)((std::max<int64_t>(n, 1) + 255) / 256);
   const unsigned g2 = (unsigned)((std::max<int64_t>(2 * n, 1) + 255) / 256);
 
+  Range range("raytrace_solve_surrogate");
   hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, L.count);
   HIP_TRY(hipGetLastError());
   // 1. network: features -> outputs
@@ -302,7 +312,7 @@ extern "C" rt_status raytrace_solve_surrogate(const rt_field* field, const rt_bo
     if ((st = rt_mlp_forward(mlp_params, L.x, n, L.y, L.mlp_ws, L.mlp_bytes, stream)) != RT_OK)
       return st;
     hipLaunchKernelGGL(decode_kernel, dim3(g2), dim3(256), 0, s, L.y, n, sp->absent_logit,
-                       L.seed, L.seed_try, L.verify, path, *out);
+                       sp->multi_logit, L.seed, L.seed_try, L.verify, path);
     HIP_TRY(hipGetLastError());
   }
   // 2. seeded secant of the tried entries (stats into out->stats)
@@ -314,23 +324,25 @@ extern "C" rt_status raytrace_solve_surrogate(const rt_field* field, const rt_bo
   memset(&C, 0, sizeof C);
   C.found = L.c_found;
   C.shots = L.c_shots;
+  C.roots = L.c_roots;
   double** f[] = {&C.theta, &C.miss, &C.t, &C.s, &C.as_re, &C.as_im, &C.ap_re, &C.ap_im};
   for (int k = 0; k < 8; ++k) *f[k] = L.c_f64[k];
   C.stats = reinterpret_cast<rt_solve_stats*>(L.fb_stats);
   if (n > 0) {
-    hipLaunchKernelGGL(flag_kernel, dim3(g1), dim3(256), 0, s, L.verify, n, L.count, L.idx);
+    hipLaunchKernelGGL(flag_kernel, dim3(g1), dim3(256), 0, s, L.verify, n, L.count, L.idx,
+                       L.fam);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(gather_kernel, dim3(g1), dim3(256), 0, s, L.idx, L.count, n, pairs->zs,
                        pairs->zr, pairs->dist, L.czs, L.czr, L.cdist);
     HIP_TRY(hipGetLastError());
   }
   const rt_pairs cp = {L.czs, L.czr, L.cdist, n};
-  if ((st = solve_enqueue(field, bnd, tol, lim, &cp, n, L.count, fb, &C, L.solve_ws, stream,
-                          nullptr)) != RT_OK)
+  if ((st = solve_enqueue(field, bnd, tol, lim, &cp, n, L.count, L.fam, fb, &C, L.solve_ws,
+                          stream, nullptr)) != RT_OK)
     return st;
   if (n > 0) {
-    hipLaunchKernelGGL(scatter_kernel, dim3(g1), dim3(256), 0, s, L.idx, L.count, n, C, *out,
-                       path);
+    hipLaunchKernelGGL(scatter_kernel, dim3(g1), dim3(256), 0, s, L.idx, L.count, L.fam, n, C,
+                       *out, path);
     HIP_TRY(hipGetLastError());
   }
   hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, s, L.count, L.fb_stats,

@@ -31,7 +31,8 @@ namespace rt {
 enum : int {
   S_ACC = 0, S_REJ, S_RELOC, S_FORCED, S_EVENTS, S_SPAWNED, S_SUPP_GEN, S_SUPP_AMP,
   S_RECORDS, S_NEEDED, S_NONFINITE, S_MAXGEN, S_INVALID, S_REFILLS, S_SCHED, S_SPILLED,
-  S_FIN,  // rays finished here and not yet added to q->finished (not a stat)
+  S_FIN,   // rays finished here and not yet added to q->finished (not a stat)
+  S_MAXQ,  // largest backlog on this wave's ring (rt_stats.max_queue)
   S_COUNT
 };
 
@@ -335,7 +336,10 @@ __device__ __forceinline__ int32_t boundary_event(const KParams& P, Ray& R, int 
           const uint32_t np = min((uint32_t)__popcll(m), room);
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
           if (rank < np) WQ.ring[(t + rank) % kRing] = (int32_t)c;
-          if ((int)__lane_id() == __ffsll((unsigned long long)m) - 1) *WQ.tail = t + np;
+          if ((int)__lane_id() == __ffsll((unsigned long long)m) - 1) {
+            *WQ.tail = t + np;
+            C.max(S_MAXQ, t + np - h);
+          }
           // The agent-scope release below writes back this XCD's L2; the
           // wave-uniform guard keeps it off the path when no lane spills.
           if (__ballot(rank >= np) != 0) {
@@ -864,6 +868,7 @@ __device__ __forceinline__ void trace_body(const KParams& P) {
       if (i == S_MAXGEN) atomicMax(&s64[i], C.c[i]);
       else atomicAdd(&s64[i], C.c[i]);
     }
+    if (C.c[S_MAXQ]) atomicMax(&s64[offsetof(rt_stats, max_queue) / 8], C.c[S_MAXQ]);
   }
 }
 

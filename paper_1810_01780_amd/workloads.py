@@ -326,7 +326,7 @@ WORKLOADS = {
 
 
 # --- surrogate network inputs -----------------------------------------------
-MLP_DIMS = [(5, 256), (256, 256), (256, 256), (256, 256), (256, 10)]
+MLP_DIMS = [(5, 256), (256, 256), (256, 256), (256, 256), (256, 12)]
 
 
 def mlp_init_params(seed: int = 0) -> np.ndarray:

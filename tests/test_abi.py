@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
                           "raytrace_launch", "rt_collect", "rt_last_error"}
     for n in names:
         assert hasattr(lib, n), n
-    assert B.rt_abi_version() == 6
+    assert B.rt_abi_version() == 7
 
 
 def test_struct_layouts_match_header():

@@ -37,7 +37,7 @@ def _data(B, seed):
     rng = np.random.default_rng(seed)
     x = rng.standard_normal((B, 5)).astype(np.float32)
     t = rng.standard_normal((B, 8)).astype(np.float32)
-    m = (rng.random((B, 2)) < 0.6).astype(np.float32)
+    m = (rng.random((B, 4)) < 0.6).astype(np.float32)
     return x, t, m
 
 
@@ -51,10 +51,10 @@ def test_forward_matches_reference(gpu, B):
     import torch
     print(f"\n[gpu-case] mlp-forward B={B}", flush=True)
     p = W.mlp_init_params(7)
-    p[-10:] = 0.1  # non-zero output biases
+    p[-12:] = 0.1  # non-zero output biases
     net = gpu.DeviceMLP(p, max_batch=B, training=False)
     x, _, _ = _data(B, seed=B)
-    y = torch.zeros((B, 10), dtype=torch.float32, device="cuda")
+    y = torch.zeros((B, 12), dtype=torch.float32, device="cuda")
     net.forward(_dev(x), y)
     torch.cuda.synchronize()
     g = y.cpu().numpy().astype(np.float64)
@@ -124,7 +124,8 @@ def test_training_reduces_loss(gpu):
     t = np.stack([np.sin(2 * x[:, 0]) * x[:, 1], x[:, 2] ** 2, np.cos(x[:, 3]), x[:, 4],
                   x[:, 0] * x[:, 4], np.tanh(x[:, 1] + x[:, 2]), x[:, 3] - x[:, 0], x[:, 1]],
                  axis=1).astype(np.float32)
-    m = np.stack([x[:, 0] > -0.5, x[:, 1] + x[:, 2] > 0], axis=1).astype(np.float32)
+    m = np.stack([x[:, 0] > -0.5, x[:, 1] + x[:, 2] > 0, x[:, 3] > 0.5, x[:, 4] < -0.5],
+                 axis=1).astype(np.float32)
     net = gpu.DeviceMLP(W.mlp_init_params(10), max_batch=B, training=True)
     xd, td, md = _dev(x), _dev(t), _dev(m)
     losses = []

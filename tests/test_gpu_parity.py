@@ -289,7 +289,10 @@ def test_secondaries_shared_between_waves(gpu, oracle_lib, local_queue):
     assert gst["spilled"] > 0
     if local_queue == -1:
         assert gst["spilled"] == gst["spawned"]
+    # the largest backlog on one wave's own queue stays within its length
+    assert gst["max_queue"] == 0 if local_queue == -1 else 1 <= gst["max_queue"] <= local_queue
     base, bst = gpu.trace(sc)
+    assert 1 <= bst["max_queue"] <= 256
     a, b = sort_by_key(base), sort_by_key(got)
     for f in ("key", "x", "z", "s", "t", "as_re", "ap_im", "n_acc", "status"):
         assert np.array_equal(a[f], b[f]), f

@@ -154,8 +154,12 @@ def compare_solves(oracle_lib, g, o, sc, pairs, label, max_found_mismatch=0.005)
     summ = dict(entries=int(fg.size), found_gpu=int(fg.sum()), found_oracle=int(fo.sum()),
                 mismatch=mism, dt_excess=float((dt - bar).max(initial=-1.0)),
                 dtheta=float(np.abs(g["theta"][both] - o["theta"][both]).max(initial=0.0)),
-                shots_equal=float((g["shots"] == o["shots"]).mean()))
+                shots_equal=float((g["shots"] == o["shots"]).mean()),
+                roots_equal=float((g["roots"] == o["roots"]).mean()))
     print(f"[gpu-case] {label}: {summ}", flush=True)
+    # root counts: equal where the found flags agree, at least one per solution
+    assert np.array_equal(g["roots"][fg == fo], o["roots"][fg == fo]), summ
+    assert np.all(g["roots"][fg] >= 1) and np.all(g["roots"][~fg] == 0)
     assert summ["dt_excess"] <= 0.0, summ
     assert summ["dtheta"] <= 1e-4, summ
     assert summ["shots_equal"] >= 0.9, summ
@@ -227,13 +231,18 @@ def test_solve_graph_replay(gpu):
         assert st == ref_st, rep
 
 
-@pytest.mark.parametrize("block,refill", [(64, 1), (128, 64), (192, 7)])
-def test_solve_schedule_independence(gpu, block, refill):
+@pytest.mark.parametrize("block,refill,chunk", [(64, 1, 1), (128, 64, 4), (192, 7, 64),
+                                               (256, 16, 4096)])
+def test_solve_schedule_independence(gpu, block, refill, chunk):
+    """Block size, refill threshold and the scan interleave (chunks of 4 and
+    64 entries; 4,096 > the 192 entries, a single short chunk) change which
+    lane shoots what, not the results."""
     sp = W.solve_pairs(96)
-    _announce(f"solve-sched-{block}-{refill}", sp.n)
+    _announce(f"solve-sched-{block}-{refill}-{chunk}", sp.n)
     base, bst = gpu.solve(sp.scene, sp.zs, sp.zr, sp.dist)
     got, gst = gpu.solve(sp.scene, sp.zs, sp.zr, sp.dist,
-                         tuning=gpu.rt_tuning(block_size=block, refill_threshold=refill))
+                         tuning=gpu.rt_tuning(block_size=block, refill_threshold=refill,
+                                              scan_chunk=chunk))
     for f in base:
         assert np.array_equal(base[f], got[f]), f
     assert bst == gst

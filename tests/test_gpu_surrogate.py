@@ -6,10 +6,11 @@
   raytrace_solve_surrogate on pairs of the two-layer workload, judged by the
   tracer and the oracle: every entry the surrogate path reports is a
   verified solution (|miss| <= verify_tol, confirmed by an oracle shot at its
-  angle), fallback entries equal the tracer's own solve bit for bit,
-  entries declared absent are rarely solvable, first-arrival times agree
-  with the tracer's within 0.1 ns, and the surrogate path is faster than the
-  tracer alone on the same GPU.
+  angle), tracer entries equal the tracer's own solve bit for bit, every
+  entry the tracer solves is solved, first arrivals later than the
+  tracer's by more than 0.1 ns are rarer than the tracer's own against a
+  dense scan, and the surrogate path is faster than the tracer alone on the
+  same GPU.
 """
 import math
 import sys
@@ -67,20 +68,22 @@ def test_seeded_matches_oracle(gpu, oracle_lib):
 @pytest.fixture(scope="module")
 def trained(gpu):
     from paper_1810_01780_amd import surrogate
-    _announce("surrogate training: 64 profiles x 8192 pairs, 3000 steps")
+    _announce("surrogate training: 256 profiles x 8192 pairs, 4000 steps of 8192 rows")
     log = lambda m: print(f"[gpu-case] {m}", flush=True)
-    net, losses = surrogate.default_model(seed=0, n_profiles=64, pairs_per_profile=8192,
-                                          steps=3000, log=log)
+    net, losses = surrogate.default_model(seed=0, n_profiles=256, pairs_per_profile=8192,
+                                          steps=4000, batch=8192, log=log)
     assert losses[-1][1] < 0.2 * losses[0][1]
     return net
 
 
 def test_surrogate_solve_end_to_end(gpu, oracle_lib, trained):
+    """One inference batch of 1,048,576 pairs."""
     import torch
-    n = 65536
+    n = 1 << 20
     sp_ = W.solve_pairs(n)
     _announce(f"surrogate-solve: {n} pairs")
-    sp = gpu.surrogate_params(z0=75.0, dn=0.43, verify_tol=0.01, max_shots=8, absent_logit=-2.0)
+    sp = gpu.surrogate_params(z0=75.0, dn=0.43, verify_tol=0.01, max_shots=8, absent_logit=-2.0,
+                              multi_logit=-3.0)
     # tracer alone
     ref = gpu.DeviceSolve(sp_.scene, sp_.zs, sp_.zr, sp_.dist)
     ref.launch()
@@ -90,35 +93,42 @@ def test_surrogate_solve_end_to_end(gpu, oracle_lib, trained):
     ds.launch(trained.params)
     res, st = ds.collect()
     path = res["path"]
-    sur, fb, ab = path == gpu.RT_PATH_SURROGATE, path == gpu.RT_PATH_TRACER, path == \
-        gpu.RT_PATH_ABSENT
+    sur, fb = path == gpu.RT_PATH_SURROGATE, path == gpu.RT_PATH_TRACER
+    assert np.all(sur | fb)
     # surrogate entries: verified solutions
     ok = sur & (res["found"] == 1)
     assert np.array_equal(ok, sur), "an entry on the surrogate path is not a solution"
     assert np.all(np.abs(res["miss"][sur]) <= 0.01)
+    assert np.all(res["roots"][sur] == 1)
     idx = np.argwhere(sur)
     pick = idx[np.random.default_rng(0).choice(len(idx), min(512, len(idx)), replace=False)]
     rs = oracle_lib.shoot(sp_.scene, sp_.zs[pick[:, 0]], sp_.zr[pick[:, 0]],
                           sp_.dist[pick[:, 0]], res["theta"][pick[:, 0], pick[:, 1]],
                           pick[:, 1].astype(np.int32))
     assert np.all(rs["status"] == 0) and np.all(np.abs(rs["miss"]) <= 0.01 + 1e-9)
-    # fallback entries: the tracer's own results
-    for f in ("found", "theta", "t", "s", "miss", "as_re", "shots"):
+    # fallback entries: the tracer's own results, bit for bit
+    for f in ("found", "theta", "t", "s", "miss", "as_re", "shots", "roots"):
         assert np.array_equal(res[f][fb], rres[f][fb]), f
-    # absent entries: rarely solvable
-    false_absent = int((ab & (rres["found"] == 1)).sum())
-    # first arrivals: travel time within 0.1 ns of the tracer's
+    # the network never decides that an entry has no solution: every entry
+    # the tracer solves is solved here too
+    assert np.all(res["found"][rres["found"] == 1] == 1)
+    # first arrivals: where both have a solution, how often the surrogate's
+    # travel time is later than the tracer's by more than 0.1 ns (the
+    # verified root is another root of the family) or earlier (a root the
+    # tracer's scan missed).  Families with several roots go to the tracer
+    # when the network predicts them; the rest of the time a later arrival
+    # must be rarer than the 64-angle scan's own later arrivals against a
+    # dense scan (0.15 %, tests/test_oracle_solve.py).
     both = sur & (rres["found"] == 1)
-    dt = np.abs(res["t"][both] - rres["t"][both])
-    late = int((dt > 0.1e-9).sum())
-    summ = dict(entries=2 * n, surrogate=int(sur.sum()), fallback_pairs=st["fallback_pairs"],
-                absent=int(ab.sum()), false_absent=false_absent, tracer_found=int(rres["found"].sum()),
-                surrogate_found=int(res["found"].sum()), other_arrival=late,
+    dt = res["t"][both] - rres["t"][both]
+    later, earlier = int((dt > 0.1e-9).sum()), int((dt < -0.1e-9).sum())
+    summ = dict(entries=2 * n, surrogate=int(sur.sum()), tracer_entries=int(fb.sum()),
+                fallback_pairs=st["fallback_pairs"], tracer_found=int(rres["found"].sum()),
+                surrogate_found=int(res["found"].sum()), later=later, earlier=earlier,
                 shots=st["shots"], tracer_shots=rst["shots"])
     print(f"[gpu-case] surrogate-solve: {summ}", flush=True)
-    assert false_absent <= 0.001 * 2 * n
-    assert late <= 0.01 * both.sum()
-    assert res["found"].sum() >= 0.98 * rres["found"].sum()
+    assert later <= 0.0015 * both.sum(), summ
+    assert int(sur.sum()) >= 0.3 * sur.size, summ
     # speed on the same GPU: best of 3 each
     def timed(fn):
         best = 1e9
@@ -133,4 +143,4 @@ def test_surrogate_solve_end_to_end(gpu, oracle_lib, trained):
     t_su = timed(lambda: ds.launch(trained.params))
     print(f"[gpu-case] surrogate-solve: tracer {t_tr * 1e3:.2f} ms, surrogate "
           f"{t_su * 1e3:.2f} ms, gain {t_tr / t_su:.2f}x", flush=True)
-    assert t_su < t_tr / 1.5
+    assert t_su < t_tr / 1.2

@@ -14,14 +14,14 @@ def _batch(B, seed=0):
     rng = np.random.default_rng(seed)
     x = rng.standard_normal((B, 5))
     t = rng.standard_normal((B, 8))
-    m = (rng.random((B, 2)) < 0.6).astype(np.float64)
+    m = (rng.random((B, 4)) < 0.6).astype(np.float64)
     return x, t, m
 
 
 def test_param_count_and_generator():
-    assert M.param_count() == 5 * 256 + 256 + 3 * (256 * 256 + 256) + 256 * 10 + 10 == 201482
+    assert M.param_count() == 5 * 256 + 256 + 3 * (256 * 256 + 256) + 256 * 12 + 12 == 201996
     p = W.mlp_init_params(3)
-    assert p.dtype == np.float32 and p.shape == (201482,)
+    assert p.dtype == np.float32 and p.shape == (201996,)
     assert np.array_equal(p, W.mlp_init_params(3)) and not np.array_equal(p, W.mlp_init_params(4))
 
 
@@ -44,15 +44,24 @@ def test_silu_and_its_derivative():
 
 def test_loss_closed_forms():
     B = 7
-    y = np.zeros((B, 10))
+    y = np.zeros((B, 12))
     t = np.zeros((B, 8))
-    m = np.ones((B, 2))
-    # zero logits: two cross-entropies of log 2 per row, no regression error
-    assert M.loss(y, t, m) == pytest.approx(2 * math.log(2), rel=1e-15)
+    m = np.ones((B, 4))
+    # zero logits: four cross-entropies of log 2 per row, no regression error
+    assert M.loss(y, t, m) == pytest.approx(4 * math.log(2), rel=1e-15)
     t[:, 1] = 3.0
     m[:, 1] = 0.0
     # masked family 1 does not count; family 0 adds 3^2
-    assert M.loss(y, t, m) == pytest.approx(2 * math.log(2) + 9.0, rel=1e-15)
+    assert M.loss(y, t, m) == pytest.approx(4 * math.log(2) + 9.0, rel=1e-15)
+    # a several-roots logit z with label 1 costs log(1 + e^-z), with label 0
+    # log(1 + e^z)
+    y[:, 11] = 2.0
+    m[:, 3] = 1.0
+    l1 = M.loss(y, t, m)
+    m[:, 3] = 0.0
+    l0 = M.loss(y, t, m)
+    assert l1 == pytest.approx(3 * math.log(2) + 9.0 + math.log1p(math.exp(-2.0)), rel=1e-15)
+    assert l0 == pytest.approx(3 * math.log(2) + 9.0 + math.log1p(math.exp(2.0)), rel=1e-15)
 
 
 def test_gradient_matches_finite_differences():
@@ -61,7 +70,7 @@ def test_gradient_matches_finite_differences():
     sample of the others."""
     x, t, m = _batch(6, seed=1)
     p = W.mlp_init_params(1).astype(np.float64)
-    p[-10:] = np.random.default_rng(2).standard_normal(10)  # non-zero output biases
+    p[-12:] = np.random.default_rng(2).standard_normal(12)  # non-zero output biases
     _, g = M.gradients(p, x, t, m, bf16=False)
     lay, total = M.layout()
     rng = np.random.default_rng(3)
