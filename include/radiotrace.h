@@ -382,7 +382,7 @@ rt_status raytrace_launch(const rt_field* field,
  * nothing: no hipMalloc, no hipFree, no allocating library routine; it
  * enqueues kernels on 'stream' like raytrace_launch.  A launch whose
  * rt_workspace_bytes(field, out->capacity) exceeds RT_STATIC_SCRATCH_BYTES
- * (about 8.3 million record slots for analytic fields, fewer with a grid)
+ * (about 5.5 million record slots for analytic fields, fewer with a grid)
  * returns RT_ERR_UNSUPPORTED without enqueuing anything.  Every call on a GPU
  * shares that GPU's array, which keeps the last call's contents (each launch
  * re-initialises what it reads): calls that overlap on one GPU, on any

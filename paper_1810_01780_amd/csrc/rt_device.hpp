@@ -249,30 +249,30 @@ __device__ constexpr int stage_degree(int s) {
 
 // strat_field_rel at stage S without a branch: slow is raised when the
 // exponent is outside the Taylor range of the stage (or NaN); the caller
-// then recomputes the step with strat_field_rel.  dnE0 = dn E0 and
-// gE0 = (dn / z0) E0 are the step's factors of exp(-dz / z0) in n and dn/dz.
-// Media with dn = 0 have inv_z0 = 0 and both factors 0.
+// then recomputes the step with strat_field_rel.  The step's start z0 enters
+// through A0 = a + b z0, and dnE0 = dn E0 and gE0 = (dn / z0) E0 are the
+// step's factors of exp(-dz / z0) in n and dn/dz.  Media with dn = 0 have
+// inv_z0 = 0 and both factors 0.
 template <int S>
-__device__ __forceinline__ void strat_field_stage_fast(const Medium& M, double z0, double dz,
+__device__ __forceinline__ void strat_field_stage_fast(const Medium& M, double A0, double dz,
                                                        double dnE0, double gE0, double& n,
                                                        double& gz, bool& slow) {
   constexpr int D = stage_degree(S);
-  const double z = z0 + dz;
   const double x = -dz * M.inv_z0;
   slow = slow || !(fabs(x) <= taylor_max(D));
   const double p = exp_taylor<D>(x);
-  n = fma(-dnE0, p, fma(M.b, z, M.a));
+  n = fma(-dnE0, p, fma(M.b, dz, A0));
   gz = fma(gE0, p, M.b);
 }
-__device__ __forceinline__ void strat_field_fast_at(int st, const Medium& M, double z0, double dz,
+__device__ __forceinline__ void strat_field_fast_at(int st, const Medium& M, double A0, double dz,
                                                     double dnE0, double gE0, double& n,
                                                     double& gz, bool& slow) {
   switch (st) {
-    case 1: strat_field_stage_fast<1>(M, z0, dz, dnE0, gE0, n, gz, slow); break;
-    case 2: strat_field_stage_fast<2>(M, z0, dz, dnE0, gE0, n, gz, slow); break;
-    case 3: strat_field_stage_fast<3>(M, z0, dz, dnE0, gE0, n, gz, slow); break;
-    case 4: strat_field_stage_fast<4>(M, z0, dz, dnE0, gE0, n, gz, slow); break;
-    default: strat_field_stage_fast<5>(M, z0, dz, dnE0, gE0, n, gz, slow); break;
+    case 1: strat_field_stage_fast<1>(M, A0, dz, dnE0, gE0, n, gz, slow); break;
+    case 2: strat_field_stage_fast<2>(M, A0, dz, dnE0, gE0, n, gz, slow); break;
+    case 3: strat_field_stage_fast<3>(M, A0, dz, dnE0, gE0, n, gz, slow); break;
+    case 4: strat_field_stage_fast<4>(M, A0, dz, dnE0, gE0, n, gz, slow); break;
+    default: strat_field_stage_fast<5>(M, A0, dz, dnE0, gE0, n, gz, slow); break;
   }
 }
 
@@ -285,6 +285,16 @@ struct GridFetch {
   float4 c[8];
   double t[3];
 };
+
+// Node (i, j, k) of the prepared grid: float4 nodes stored in bricks of
+// 2 x 2 x 2 nodes, one 128-byte cache line each, bricks x fastest; within a
+// brick the node's x, y, z parities select its float4.  A cell's eight
+// corners then lie in one to eight lines (3.4 on average) instead of four
+// or more with rows of nodes.
+__host__ __device__ __forceinline__ size_t node_index(int i, int j, int k, int bx, int by) {
+  const size_t brick = ((size_t)(k >> 1) * by + (size_t)(j >> 1)) * bx + (size_t)(i >> 1);
+  return brick * 8 + (size_t)((i & 1) | ((j & 1) << 1) | ((k & 1) << 2));
+}
 
 __device__ __forceinline__ void grid_fetch(const KParams& P, double x, double y, double z,
                                            GridFetch& F) {
@@ -301,11 +311,18 @@ __device__ __forceinline__ void grid_fetch(const KParams& P, double x, double y,
     i0[a] = i;
     F.t[a] = v - (double)i;
   }
-  const size_t sx = 1, sy = (size_t)P.gnx, sz = (size_t)P.gnx * P.gny;
-  const size_t base = (size_t)i0[2] * sz + (size_t)i0[1] * sy + (size_t)i0[0];
+  // per axis, the offsets of the cell's two node planes
+  size_t ox[2], oy[2], oz[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int i = i0[0] + e, j = i0[1] + e, k = i0[2] + e;
+    ox[e] = (size_t)(i >> 1) * 8 + (size_t)(i & 1);
+    oy[e] = (size_t)(j >> 1) * 8 * P.gbx + (size_t)((j & 1) << 1);
+    oz[e] = (size_t)(k >> 1) * 8 * P.gbx * P.gby + (size_t)((k & 1) << 2);
+  }
 #pragma unroll
   for (int q = 0; q < 8; ++q)
-    F.c[q] = nodes[base + ((q & 1) ? sx : 0) + ((q & 2) ? sy : 0) + ((q & 4) ? sz : 0)];
+    F.c[q] = nodes[ox[q & 1] + oy[(q >> 1) & 1] + oz[(q >> 2) & 1]];
 }
 
 __device__ __forceinline__ void grid_blend(const KParams& P, const GridFetch& F, double& n,
@@ -357,7 +374,7 @@ __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], 
                                             double inv_tol, double y5[7], double& err,
                                             bool* slow_out = nullptr) {
   const double E0 = FAST ? exp_rr(-y[2] * M.inv_z0) : (M.dn != 0.0 ? exp(-y[2] * M.inv_z0) : 0.0);
-  const double dnE0 = M.dn * E0, gE0 = M.dn_inv_z0 * E0;
+  const double dnE0 = M.dn * E0, gE0 = M.dn_inv_z0 * E0, A0 = fma(M.b, y[2], M.a);
   bool slow = false;
   if constexpr (MODEL == RT_MODEL_PAPER) {
     // w = unit velocity, renormalised after every accepted step (|w| = 1).
@@ -375,7 +392,7 @@ __device__ __forceinline__ void trial_strat(const Medium& M, const double y[7], 
 #pragma unroll
         for (int i = 0; i + 1 < st; ++i) acc = fma(ck_aa(st, i), kw[i], acc);
         const double dz = h * fma(h, acc, ck_c(st) * y[5]);
-        if constexpr (FAST) strat_field_fast_at(st, M, y[2], dz, dnE0, gE0, n, gz, slow);
+        if constexpr (FAST) strat_field_fast_at(st, M, A0, dz, dnE0, gE0, n, gz, slow);
         else strat_field_rel(M, y[2], dz, E0, n, gz);
       }
       kw[st] = gz * rcp_nr(n);

@@ -184,13 +184,16 @@ rt_status rt_workspace_bytes(const rt_field* field, int64_t capacity, size_t* by
   size_t b = 4096;                                      // queue counters, padded
   b += ((size_t)capacity * 4 + 4095) / 4096 * 4096;     // overflow queue
   b += ((size_t)capacity * 4 + 4095) / 4096 * 4096;     // hand-out order of the primaries
+  b += ((size_t)capacity * 4 + 4095) / 4096 * 4096;     // its per-chunk sorted order
+  b += ((size_t)(capacity / 16384 + 1) * 8 + 4095) / 4096 * 4096;  // chunk keys
   if (field->n_regions > 0 && field->regions && rt::field_uses_grid(field)) {
     const rt_grid& g = field->grid;
     if (g.nx < 2 || g.ny < 2 || g.nz < 2) {
       rt::set_last_error("grid: dims must be >= 2");
       return RT_ERR_INVALID_ARG;
     }
-    b += (size_t)g.nx * g.ny * g.nz * 16;
+    // float4 nodes in bricks of 2 x 2 x 2 (one 128-byte line each)
+    b += (size_t)((g.nx + 1) / 2) * ((g.ny + 1) / 2) * ((g.nz + 1) / 2) * 128;
   }
   *bytes = b;
   return RT_OK;

@@ -198,12 +198,27 @@ __global__ void finish_kernel(KParams P) {
   }
 }
 
-// Hand-out order of the primaries: within each chunk of kOrderChunk
-// consecutive rays, by source and then by a Morton code of the direction's
-// octahedral map (9 bits per axis), ties by index; a bitonic sort of the
-// chunk's 64-bit keys in LDS (128 KiB of the 160 KiB of a CU).  Only the order in which lanes take the rays
-// changes: every ray keeps its record slot and its result.
+// Hand-out order of the primaries: deepest sources first, and rays of one
+// source by a Morton code of the direction's octahedral map (9 bits per
+// axis), so that the lanes of a wave trace neighbouring directions.  In two
+// steps: within each chunk of kOrderChunk consecutive rays, a bitonic sort of
+// 64-bit keys (source depth descending, direction code, index) in LDS
+// (128 KiB of the 160 KiB of a CU); then the full chunks are put in the
+// order of their first keys (chunk_order_kernel, up to kOrderChunk chunks)
+// and the permutation is applied (apply_order_kernel).  Deepest first
+// measured 4-5 % faster than source-index order on the two-layer workload:
+// the rays of the shallow sources, handed out last, leave a shorter tail of
+// lone waves.  Only the order in which lanes take the rays changes: every
+// ray keeps its record slot and its result.
 constexpr int kOrderChunk = 16384;
+
+// 32 high bits of a key that decreases with the depth z (IEEE order made
+// monotone: sign flipped for z >= 0, all bits for z < 0; then complemented).
+__device__ __forceinline__ uint32_t depth_key(double z) {
+  const uint64_t b = (uint64_t)__double_as_longlong(z);
+  const uint64_t up = (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+  return (uint32_t)(~up >> 32);
+}
 
 __device__ __forceinline__ uint32_t spread9(uint32_t v) {  // bits 0..8 -> even bits
   v &= 0x1ffu;
@@ -215,8 +230,12 @@ __device__ __forceinline__ uint32_t spread9(uint32_t v) {  // bits 0..8 -> even 
 }
 
 __global__ void __launch_bounds__(1024) order_kernel(KParams P,
+                                                     const double* __restrict__ src_xyz,
+                                                     int32_t n_src,
                                                      const double* __restrict__ dir_xyz,
-                                                     const int32_t* __restrict__ ray_src) {
+                                                     const int32_t* __restrict__ ray_src,
+                                                     int32_t* __restrict__ perm0,
+                                                     uint64_t* __restrict__ chunk_key) {
   __shared__ unsigned long long key[kOrderChunk];
   const int64_t base = (int64_t)blockIdx.x * kOrderChunk;
   const int n = (int)min((int64_t)kOrderChunk, P.n_primary - base);
@@ -239,8 +258,10 @@ __global__ void __launch_bounds__(1024) order_kernel(KParams P,
       const uint32_t ix = min(511u, (uint32_t)((ox + 1.0) * 256.0));
       const uint32_t iy = min(511u, (uint32_t)((oy + 1.0) * 256.0));
       const uint32_t code = spread9(ix) | (spread9(iy) << 1);
-      k = ((unsigned long long)(uint32_t)ray_src[i] << 32) |
-          ((unsigned long long)code << 14) | (unsigned long long)j;
+      const int32_t s = ray_src[i];  // a ray of no valid source is invalid: any place
+      const uint32_t dk = (s >= 0 && s < n_src) ? depth_key(src_xyz[3 * (int64_t)s + 2]) : 0u;
+      k = ((unsigned long long)dk << 32) | ((unsigned long long)code << 14) |
+          (unsigned long long)j;
     }
     key[j] = k;
   }
@@ -261,7 +282,49 @@ __global__ void __launch_bounds__(1024) order_kernel(KParams P,
     }
   }
   for (int j = threadIdx.x; j < n; j += blockDim.x)
-    P.perm[base + j] = (int32_t)(base + (int64_t)(key[j] & 0x3fffu));
+    perm0[base + j] = (int32_t)(base + (int64_t)(key[j] & 0x3fffu));
+  if (threadIdx.x == 0)
+    chunk_key[blockIdx.x] = (key[0] & 0xffffffff00000000ull) | (unsigned long long)blockIdx.x;
+}
+
+// The full chunks in the order of their first keys (one block; keys padded
+// to a power of two): chunk_key[c] = the c-th chunk to hand out.
+__global__ void __launch_bounds__(1024) chunk_order_kernel(uint64_t* __restrict__ chunk_key,
+                                                           int n_full) {
+  __shared__ unsigned long long key[kOrderChunk];
+  int np = 1;
+  while (np < n_full) np <<= 1;
+  for (int j = threadIdx.x; j < np; j += blockDim.x) key[j] = j < n_full ? chunk_key[j] : ~0ull;
+  __syncthreads();
+  for (int size = 2; size <= np; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < np; t += blockDim.x) {
+        const int u = t ^ stride;
+        if (u > t) {
+          const unsigned long long a = key[t], b = key[u];
+          if ((a > b) == ((t & size) == 0)) {
+            key[t] = b;
+            key[u] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int j = threadIdx.x; j < n_full; j += blockDim.x) chunk_key[j] = key[j];
+}
+
+// Ticket t -> slot: the (t / kOrderChunk)-th chunk of the chunk order, at
+// its (t % kOrderChunk)-th sorted position; a partial last chunk stays last.
+__global__ void apply_order_kernel(KParams P, const int32_t* __restrict__ perm0,
+                                   const uint64_t* __restrict__ chunk_key, int n_full) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= P.n_primary) return;
+  const int64_t c = t / kOrderChunk;
+  const int64_t src = c < n_full
+                          ? (int64_t)(chunk_key[c] & 0xffffffffull) * kOrderChunk + t % kOrderChunk
+                          : t;
+  P.perm[t] = perm0[src];
 }
 
 // FP32 grid -> float4 nodes (n, Dx, Dy, Dz): D is the central difference of
@@ -269,7 +332,7 @@ __global__ void __launch_bounds__(1024) order_kernel(KParams P,
 // grad n = D / (2 spacing) everywhere.  The FP32 differences are exact for
 // values within a factor of two of each other (Sterbenz).
 __global__ void grid_prep_kernel(const float* __restrict__ n, float4* __restrict__ out, int nx,
-                                 int ny, int nz) {
+                                 int ny, int nz, int bx, int by) {
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)nx * ny * nz;
   if (id >= total) return;
@@ -288,7 +351,7 @@ __global__ void grid_prep_kernel(const float* __restrict__ n, float4* __restrict
   if (k == 0) dz = 2.0f * (n[id + sz] - c);
   else if (k == nz - 1) dz = 2.0f * (c - n[id - sz]);
   else dz = n[id + sz] - n[id - sz];
-  out[id] = make_float4(c, dx, dy, dz);
+  out[node_index(i, j, k, bx, by)] = make_float4(c, dx, dy, dz);
 }
 
 // ---------------------------------------------------------------------------
@@ -582,15 +645,23 @@ rt_status launch_trace(const rt_field* field, const rt_boundaries* bnd, const rt
   P.gq = reinterpret_cast<int32_t*>(static_cast<char*>(workspace) + 4096);
   const size_t gq_bytes = ((size_t)out->capacity * 4 + 4095) / 4096 * 4096;
   P.perm = reinterpret_cast<int32_t*>(static_cast<char*>(workspace) + 4096 + gq_bytes);
+  // per-chunk sorted order and the chunks' keys (order_kernel)
+  int32_t* perm0 = reinterpret_cast<int32_t*>(static_cast<char*>(workspace) + 4096 + 2 * gq_bytes);
+  uint64_t* chunk_key =
+      reinterpret_cast<uint64_t*>(static_cast<char*>(workspace) + 4096 + 3 * gq_bytes);
+  const size_t ck_bytes = ((size_t)(out->capacity / kOrderChunk + 1) * 8 + 4095) / 4096 * 4096;
   P.stats = out->stats;
   const bool has_grid = field_uses_grid(field);
   const int kind = (has_grid ? 2 : field_is_general(field) ? 1 : 0) + (P.ev_capacity > 0 ? 3 : 0);
   if (has_grid) {
     const rt_grid& g = field->grid;
-    P.nodes = static_cast<char*>(workspace) + 4096 + 2 * gq_bytes;
+    P.nodes = static_cast<char*>(workspace) + 4096 + 3 * gq_bytes + ck_bytes;
     P.gnx = g.nx;
     P.gny = g.ny;
     P.gnz = g.nz;
+    P.gbx = (g.nx + 1) / 2;
+    P.gby = (g.ny + 1) / 2;
+    P.gbz = (g.nz + 1) / 2;
     const int dims[3] = {g.nx, g.ny, g.nz};
     for (int a = 0; a < 3; ++a) {
       P.gorg[a] = g.origin[a];
@@ -633,7 +704,7 @@ rt_status launch_trace(const rt_field* field, const rt_boundaries* bnd, const rt
     const int64_t total = (int64_t)field->grid.nx * field->grid.ny * field->grid.nz;
     hipLaunchKernelGGL(grid_prep_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
                        field->grid.n, static_cast<float4*>(const_cast<void*>(P.nodes)),
-                       field->grid.nx, field->grid.ny, field->grid.nz);
+                       field->grid.nx, field->grid.ny, field->grid.nz, P.gbx, P.gby);
     HIP_TRY(hipGetLastError());
   }
   if (out->capacity > 0 && !L->resume) {
@@ -642,10 +713,23 @@ rt_status launch_trace(const rt_field* field, const rt_boundaries* bnd, const rt
     HIP_TRY(hipGetLastError());
   }
   if (dirs->n > 0 && !L->resume) {  // a resumed launch keeps the order it had
-    hipLaunchKernelGGL(order_kernel, dim3((unsigned)((dirs->n + kOrderChunk - 1) / kOrderChunk)),
-                       dim3(1024), 0, s, P, dirs->xyz, dirs->src);
+    const int64_t chunks = (dirs->n + kOrderChunk - 1) / kOrderChunk;
+    hipLaunchKernelGGL(order_kernel, dim3((unsigned)chunks), dim3(1024), 0, s, P, src->xyz,
+                       src->n, dirs->xyz, dirs->src, perm0, chunk_key);
+    HIP_TRY(hipGetLastError());
+    int n_full = (int)(dirs->n / kOrderChunk);
+    if (n_full > kOrderChunk) n_full = 0;  // beyond one block's sort: chunks in input order
+    if (n_full >= 2) {
+      hipLaunchKernelGGL(chunk_order_kernel, dim3(1), dim3(1024), 0, s, chunk_key, n_full);
+      HIP_TRY(hipGetLastError());
+    } else {
+      n_full = 0;
+    }
+    hipLaunchKernelGGL(apply_order_kernel, dim3((unsigned)((dirs->n + 255) / 256)), dim3(256), 0,
+                       s, P, perm0, chunk_key, n_full);
     HIP_TRY(hipGetLastError());
   }
+
 
   // persistent grid: every CU filled to its occupancy, fewer blocks for
   // small launches

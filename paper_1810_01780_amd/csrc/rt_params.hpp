@@ -72,6 +72,7 @@ struct KParams {
   // grid: float4 nodes (n, Dx, Dy, Dz) with grad n = D / (2 spacing)
   const void* nodes;
   int32_t gnx, gny, gnz, refill;
+  int32_t gbx, gby, gbz, pad_g;  // bricks of 2 x 2 x 2 nodes along x, y, z
   uint32_t local_limit;  // children a wave keeps before publishing globally
   uint32_t chunk;        // secondary slots a wave reserves at once (0: one per child)
   uint64_t chunk_limit;  // waves stop taking chunks once they reach this slot

@@ -259,6 +259,11 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
   __shared__ unsigned long long s_cnt[4][V_COUNT];
   const Counters C{s_cnt[tid / 64]};
   if (lane < V_COUNT) C.c[lane] = 0;
+  // accepted and rejected steps of the shots each lane has finished (added
+  // to the statistics at the end: the step loop keeps no counters)
+  __shared__ unsigned long long s_sacc[256], s_srej[256];
+  s_sacc[tid] = 0;
+  s_srej[tid] = 0;
   // crossing search of each lane (as in the trace kernel)
   __shared__ double s_a[256], s_Ga[256], s_b[256], s_Gb[256], s_hp[256], s_hn[256];
   __shared__ int32_t s_k[256], s_meta[256];
@@ -311,6 +316,8 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
     // ---- a shot ended: record it, or continue its bracket ----
     if (fin.status >= 0) {
       C.bump(V_SHOTS);
+      s_sacc[tid] += (unsigned long long)R.n_acc;
+      s_srej[tid] += (unsigned long long)R.n_rej;
       const int64_t t = R.slot;
       if constexpr (PHASE == PH_LIST) {
         const rt_shot_outputs& O = V.lo;
@@ -582,16 +589,18 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
 #pragma unroll
       for (int i = 0; i < 7; ++i) finite = finite && isfinite(y5[i]);
       const bool accept = err <= 1.0 || ht <= P.h_min;
-      const double hn = clamp_h(P, ht * step_factor(err, accept));
+      // as in the trace: a full-length step whose error allows growth stays
+      // at h_max without the controller's power (same result)
+      double hn = P.h_max;
+      if (!(accept && err <= 0.5 && ht >= P.h_max))
+        hn = clamp_h(P, ht * step_factor(err, accept));
       if (!finite) {
         fin = ShotEnd{RT_SHOT_LOST, kMissLost};
       } else if (!accept) {
         R.n_rej++;
-        C.bump(V_REJ);
         R.h = hn;
       } else {
         R.n_acc++;
-        C.bump(V_ACC);
         if (err > 1.0) C.bump(V_FORCED);
         if constexpr (MODEL == RT_MODEL_PAPER) {
           const double il = rsqrt_nr(fma(y5[3], y5[3], fma(y5[4], y5[4], y5[5] * y5[5])));
@@ -718,6 +727,18 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
     if (fin.status >= 0) mode = 0;
   }
 
+  {
+    unsigned long long a = s_sacc[tid], r = s_srej[tid];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o);
+      r += __shfl_xor(r, o);
+    }
+    if (lane == 0) {
+      C.c[V_ACC] += a;
+      C.c[V_REJ] += r;
+    }
+  }
   if (lane == 0) {
     for (int i = 0; i < V_COUNT; ++i)
       if (C.c[i]) atomicAdd(&V.stats[i], C.c[i]);

@@ -132,14 +132,17 @@ def test_validate_grid_descriptor():
 
 def test_workspace_bytes():
     d = _descs()
-    # counters, then the overflow queue and the hand-out order (4 B per
-    # record each, padded to 4 KiB), then the grid nodes
-    assert B.rt_workspace_bytes(d.field, 0) == 4096
-    assert B.rt_workspace_bytes(d.field, 1) == 4096 + 2 * 4096
-    assert B.rt_workspace_bytes(d.field, 2048) == 4096 + 2 * 8192
+    # counters, then the overflow queue, the hand-out order and its per-chunk
+    # sorted form (4 B per record each, padded to 4 KiB), the chunk keys
+    # (8 B per 16,384 records, one more, padded), then the grid nodes in
+    # bricks of 2 x 2 x 2 float4
+    assert B.rt_workspace_bytes(d.field, 0) == 4096 + 4096
+    assert B.rt_workspace_bytes(d.field, 1) == 4096 + 3 * 4096 + 4096
+    assert B.rt_workspace_bytes(d.field, 2048) == 4096 + 3 * 8192 + 4096
+    assert B.rt_workspace_bytes(d.field, 1 << 30) == 4096 + 3 * (4 << 30) + 528384
     sc = W.gridded(rays_per_source=1, n_sources=2, nx=4, ny=5, nz=6)
     d = _descs(sc)
-    assert B.rt_workspace_bytes(d.field, 1024) == 4096 + 2 * 4096 + 4 * 5 * 6 * 16
+    assert B.rt_workspace_bytes(d.field, 1024) == 4096 + 3 * 4096 + 4096 + 2 * 3 * 3 * 128
 
 
 def test_collect_maps_statistics():
