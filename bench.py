@@ -284,18 +284,21 @@ def bench_solve(args, log):
                accept_tol_m=prm.accept_tol, slope_max_m_per_rad=prm.slope_max,
                tol=sp.scene.limits.tol, model="paper")
     log(f"workload solve65536: {sp.n} pairs")
-    if args.block or args.refill or args.scan_chunk:
-        tun = binding.rt_tuning(args.block, 0, args.refill, None, None, 0, args.scan_chunk)
+    if args.block or args.refill or args.scan_chunk or args.fused is not None:
+        tun = binding.rt_tuning(block_size=args.block, refill_threshold=args.refill,
+                                scan_chunk=args.scan_chunk, solve_fused=args.fused or 0)
         cfg["tuning"] = "fixed"
     else:
         m = 16384
         sample = binding.DeviceSolve(sp.scene, sp.zs[:m], sp.zr[:m], sp.dist[:m], prm)
         tun, ms = sample.autotune()
         log(f"autotune on {m} pairs: block {tun.block_size} refill {tun.refill_threshold} "
-            f"scan chunk {tun.scan_chunk} ({ms:.2f} ms)")
+            f"scan chunk {tun.scan_chunk} fused {tun.solve_fused} ({ms:.2f} ms)")
         cfg["tuning"] = "autotuned"
         del sample
-    cfg.update(block=tun.block_size, refill=tun.refill_threshold, scan_chunk=tun.scan_chunk)
+    fused = tun.solve_fused == 1 and prm.n_scan <= 64 and prm.max_brackets <= 4
+    cfg.update(block=tun.block_size, refill=tun.refill_threshold, scan_chunk=tun.scan_chunk,
+               launches="fused" if fused else "scan+refine+select")
     ds = binding.DeviceSolve(sp.scene, sp.zs, sp.zr, sp.dist, prm)
     hip = _hip()
 
@@ -309,12 +312,14 @@ def bench_solve(args, log):
         hip.hipEventElapsedTime(ctypes.byref(ms), b, e)
         return ms.value
 
-    # shot-kernel time (scan + refinement) from eager launches, events on the stream
+    # shot-kernel time (the fused launch, or scan + refinement) from eager
+    # launches, events on the stream
     kern = []
     for i in range(args.warmup + 1):
         b, e = event(), event()
-        ds.launch(tuning=binding.rt_tuning(tun.block_size, 0, tun.refill_threshold, b, e, 0,
-                                           tun.scan_chunk))
+        ds.launch(tuning=binding.rt_tuning(
+            block_size=tun.block_size, refill_threshold=tun.refill_threshold, ev_trace_begin=b,
+            ev_trace_end=e, scan_chunk=tun.scan_chunk, solve_fused=tun.solve_fused))
         res, st = ds.collect()
         if i >= args.warmup:
             kern.append(elapsed(b, e))
@@ -345,7 +350,8 @@ def bench_solve(args, log):
     achieved = trials * FLOP_PER_TRIAL[0] / kern_s / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
-            "kernel": "shot_kernel (scan + refine)", "kernel_ms": kern_s * 1e3}
+            "kernel": "shot_kernel (fused scan, refine and select)" if fused
+            else "shot_kernel (scan + refine)", "kernel_ms": kern_s * 1e3}
     cfg.update(shots=st["shots"], trial_steps=trials, accepted_steps=st["accepted"],
                found=st["found"], brackets=st["brackets"])
     log(f"timed {args.steps} graph replays: {wall:.3f} s; shot kernels {kern_s * 1e3:.2f} ms")
@@ -549,6 +555,9 @@ def main():
     ap.add_argument("--refill", type=int, default=0)
     ap.add_argument("--scan-chunk", type=int, default=0,
                     help="solve: entries whose angle scans interleave (0 = autotune)")
+    ap.add_argument("--fused", type=int, default=None, choices=[0, 1],
+                    help="solve: 1 = one fused launch, 0 = scan, refine and select launches "
+                         "(default: autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--cpu-threads", type=int, default=16,

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define RT_ABI_VERSION 7
+#define RT_ABI_VERSION 8
 #define RT_MAX_REGIONS 8
 #define RT_MAX_PLANES 16
 #define RT_MAX_ANOMALIES 8
@@ -303,6 +303,10 @@ typedef struct {
                                scan_chunk entries (1..4096); 0 = 1: each
                                entry's angles consecutively.  Traces ignore it.
                                Results do not depend on it. */
+  int32_t solve_fused;      /* solves: 0 = scan, refinement and selection as
+                               three launches; 1 = one fused persistent
+                               launch when n_scan <= 64 and max_brackets <= 4
+                               (else the three).  Same results either way. */
 } rt_tuning;
 
 /* ABI version (RT_ABI_VERSION of the built library).  Plumbing: no

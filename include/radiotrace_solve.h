@@ -163,12 +163,16 @@ rt_status rt_solve_workspace_bytes(const rt_field* field, int64_t n_pairs,
 
 /* Solve every pair for both families (the receiver/emitter set-up of
  * section 2, by shooting).  Caller-owned device arrays in and out; results
- * [2 * pair + family].  Asynchronous on 'stream': a counter
- * reset, the scan, the refinement and the selection, each a kernel launch
- * (the scan and refinement kernels are persistent: one shot per lane, lanes
- * take new shots from a ticket counter).  Outputs and the workspace must not
- * be shared with an overlapping call.  tuning: block_size and
- * refill_threshold as in raytrace_launch (other fields unused); NULL =
+ * [2 * pair + family].  Asynchronous on 'stream': a counter reset, then
+ * three launches, the scan and the refinement (persistent: one shot per
+ * lane, lanes take new shots from a ticket counter) and the selection; or,
+ * with tuning->solve_fused = 1 and n_scan <= 64, max_brackets <= 4, one
+ * fused persistent launch (each wave holds up to 16 (pair, family)
+ * entries, shoots their scans, refines their brackets and writes their
+ * results).  The results are the same bit for bit either way and for every
+ * tuning.  Outputs and the workspace must not be shared with an
+ * overlapping call.  tuning: block_size and refill_threshold as in
+ * raytrace_launch; scan_chunk; solve_fused; other fields unused; NULL =
  * defaults. */
 rt_status raytrace_solve(const rt_field* field, const rt_boundaries* boundaries, double tol,
                          const rt_step_limits* limits, const rt_pairs* pairs,
@@ -187,7 +191,9 @@ rt_status raytrace_shoot(const rt_field* field, const rt_boundaries* boundaries,
 /* Plumbing, no counterpart in the paper.  Pick launch tuning for
  * raytrace_solve by measurement: every combination of
  * block_size in {64, 128, 192, 256} and refill_threshold in {4, 16, 32, 64}
- * (scan_chunk 1), then scan_chunk in {4, 16, 64} at the best of those, each
+ * in three launches (scan_chunk 1), then scan_chunk in {4, 16, 64} at the
+ * best of those, then the fused launch (solve_fused 1) at each block size
+ * and refill_threshold 16 when n_scan <= 64 and max_brackets <= 4; each
  * runs raytrace_solve once on 'pairs' (a representative sample; its results
  * land in 'out' and are overwritten by each candidate) after one untimed
  * call, timed with HIP events on 'stream'; the fastest is written to *best

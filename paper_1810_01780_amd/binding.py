@@ -127,7 +127,7 @@ class rt_tuning(C.Structure):
     _fields_ = [("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("refill_threshold", C.c_int32), ("ev_trace_begin", C.c_void_p),
                 ("ev_trace_end", C.c_void_p), ("local_queue", C.c_int32),
-                ("scan_chunk", C.c_int32)]
+                ("scan_chunk", C.c_int32), ("solve_fused", C.c_int32)]
 
 
 # --- emitter -> receiver solves (include/radiotrace_solve.h) -----------------
@@ -193,6 +193,8 @@ class rt_surrogate_params(C.Structure):
 
 
 _lib = None
+# RT_ABI_VERSION of the header the structures above follow
+ABI_VERSION = 8
 
 
 def lib() -> C.CDLL:
@@ -212,6 +214,9 @@ def lib() -> C.CDLL:
         L = C.CDLL(_LIB_PATH)
         L.rt_abi_version.restype = C.c_int32
         L.rt_abi_version.argtypes = []
+        if L.rt_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{_LIB_PATH} has ABI version {L.rt_abi_version()}, the binding "
+                               f"expects {ABI_VERSION}: rebuild it")
         L.rt_validate.restype = C.c_int
         L.rt_validate.argtypes = [C.POINTER(rt_field), C.POINTER(rt_boundaries),
                                   C.POINTER(rt_sources), C.POINTER(rt_directions), C.c_double,

@@ -52,7 +52,48 @@ enum : int {
 };
 static_assert(sizeof(rt_solve_stats) == 8 * V_COUNT, "rt_solve_stats layout");
 
-enum : int { PH_LIST = 0, PH_SCAN = 1, PH_REFINE = 2, PH_SEEDED = 3 };
+enum : int { PH_LIST = 0, PH_SCAN = 1, PH_REFINE = 2, PH_SEEDED = 3, PH_FUSED = 4 };
+
+// The fused solve (PH_FUSED): scan, refinement and selection in one
+// persistent launch.  Each wave holds up to kFEnt entries (pair, family) in
+// LDS.  Idle lanes take, in this order, queued brackets, then the next scan
+// angles of the wave's scanning entries (oldest entry first); when those
+// cannot occupy them the wave claims new entries with one fetch_add.  A scan
+// shot's miss goes to the entry's row of the scan table in HBM; the lane
+// whose shot completes the scan finds the sign changes and queues the
+// brackets; the lane that finishes the entry's last bracket writes its
+// result.  A wave depends on no other wave, so the launch ends when every
+// wave has finished its entries and no entry is left to claim.  Each shot
+// and each bracket is computed exactly as in the three launches (scan,
+// refine, select), so the results are the same.  It is not the default: on
+// the 65,536-pair solve it took 80 ms against 67 ms for the three launches
+// (the same shots in ~4 % more wave iterations, each dearer: the table
+// logic runs between trials and the kernel holds more registers); the
+// autotuner still tries it.
+constexpr int kFEnt = 16;   // entries a wave holds
+constexpr int kFScan = 64;  // largest n_scan of a fused solve
+constexpr int kFBr = 4;     // largest max_brackets of a fused solve
+constexpr int kFQ = kFEnt * kFBr;
+constexpr int32_t kFBracket = 1 << 16;  // lane task: bracket (else scan angle)
+static_assert(kFEnt <= 32 && kFScan <= 128 && kFBr <= 16, "fused table encodings");
+struct FusedWave {
+  int64_t pf[kFEnt];       // entry: 2 pair + family
+  int32_t done[kFEnt];     // scan shots finished
+  int32_t open[kFEnt];     // brackets still refining
+  int32_t nb[kFEnt];       // brackets found
+  int32_t klast[kFEnt];    // scan index of the last bracket's upper end
+  int32_t bshots[kFEnt];   // refinement shots of its finished brackets
+  int32_t roots[kFEnt];    // admissible roots so far
+  int32_t best_b[kFEnt];   // bracket of the first arrival so far, -1 none
+  double best_t[kFEnt];    // its travel time
+  int8_t bk[kFEnt][kFBr];  // scan index of each bracket's upper end
+  int8_t sq[kFEnt];        // ring: entries with scan angles left, oldest first
+  uint16_t q[kFQ];         // ring: brackets to refine, entry << 4 | bracket
+  uint32_t used;           // entry slots in use (bit e)
+  uint32_t sh, st;         // scan ring head and tail
+  int32_t sk;              // next angle of the entry at the scan ring's head
+  uint32_t qh, qt;         // bracket ring head and tail
+};
 
 struct KSolve {
   const double *zs, *zr, *dist;  // per pair (scan, refine, select) or per shot (list)
@@ -250,6 +291,27 @@ __device__ __forceinline__ double illinois_next(double a, double Ga, double b, d
   return b - Gb * (b - a) / (Gb - Ga);
 }
 
+// Fused solve: entry slot e of a wave has no bracket left; write what the
+// select phase writes (the first arrival's fields are already in place) and
+// free the slot.
+__device__ __forceinline__ void fused_finish(const KSolve& V, FusedWave& F, int e,
+                                             const Counters& C) {
+  const rt_solve_outputs& O = V.so;
+  const int64_t pf = F.pf[e];
+  const int nb = F.nb[e];
+  const bool found = F.best_b[e] >= 0;
+  O.shots[pf] = (nb >= V.max_brackets ? F.klast[e] + 1 : V.n_scan) + F.bshots[e];
+  O.found[pf] = found ? 1 : 0;
+  O.roots[pf] = F.roots[e];
+  if (found) {
+    atomicAdd(&C.c[V_FOUND], 1ull);
+  } else {
+    O.theta[pf] = O.miss[pf] = O.t[pf] = O.s[pf] = 0.0;
+    O.as_re[pf] = O.as_im[pf] = O.ap_re[pf] = O.ap_im[pf] = 0.0;
+  }
+  __hip_atomic_fetch_and(&F.used, ~(1u << e), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 template <int MODEL, int PHASE>
 __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
   for (int i = threadIdx.x; i < P.n_regions; i += blockDim.x) s_reg[i] = P.reg[i];
@@ -273,12 +335,20 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
   // being shot, and (iterations << 2 | last side + 1)
   // (the seeded phase keeps its previous angle and miss in s_ra, s_rGa and
   // the shots taken in s_rm)
-  constexpr int kR = (PHASE == PH_REFINE || PHASE == PH_SEEDED) ? 256 : 1;
+  constexpr int kR = (PHASE == PH_REFINE || PHASE == PH_SEEDED || PHASE == PH_FUSED) ? 256 : 1;
   __shared__ double s_ra[kR], s_rGa[kR];
   __shared__ double s_rb[kR], s_rGb[kR];
   __shared__ double s_rc[kR];
   __shared__ double s_rma[kR], s_rmb[kR];
   __shared__ int32_t s_rm[kR];
+  // fused solve: the entries each wave holds
+  __shared__ FusedWave s_fw[PHASE == PH_FUSED ? 4 : 1];
+  FusedWave& F = s_fw[PHASE == PH_FUSED ? tid / 64 : 0];
+  if (PHASE == PH_FUSED && lane == 0) {
+    F.used = 0;
+    F.sh = F.st = F.qh = F.qt = 0;
+    F.sk = 0;
+  }
   __syncthreads();
   int64_t n_pairs = V.n, n_tasks = V.n_tasks;
   if (V.n_dev) {
@@ -381,7 +451,48 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
           for (int i = 0; i < 4; ++i) s_amp[i][tid] = a4[i];
           mode = 0;
         }
+      } else if (PHASE == PH_FUSED && !(t & kFBracket)) {
+        // fused: a scan shot of entry slot e, angle k; the shot that
+        // completes the scan turns the entry's sign changes into brackets
+        const int e = (int)((t >> 8) & 0xff), k = (int)(t & 0xff);
+        const double* m = V.scan_miss + F.pf[e] * V.n_scan;
+        V.scan_miss[F.pf[e] * V.n_scan + k] = fin.miss;
+        // the miss is visible to the wave's lanes before the count moves
+        // (an entry's shots and its completion all run in one wave, so
+        // work-group scope orders them; agent scope would write back and
+        // invalidate the XCD's L2 at each shot)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        const int before = __hip_atomic_fetch_add(&F.done[e], 1, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (before + 1 == V.n_scan) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+          int nb = 0, klast = -1;
+          double prev = m[0];
+          for (int j = 1; j < V.n_scan && nb < V.max_brackets; ++j) {
+            const double cur = m[j];
+            if (miss_sign(cur) != miss_sign(prev)) {
+              F.bk[e][nb] = (int8_t)j;
+              klast = j;
+              ++nb;
+            }
+            prev = cur;
+          }
+          F.nb[e] = nb;
+          F.klast[e] = klast;
+          F.open[e] = nb;
+          if (nb == 0) {
+            fused_finish(V, F, e, C);
+          } else {
+            atomicAdd(&C.c[V_BRACKETS], (unsigned long long)nb);
+            const uint32_t q0 = __hip_atomic_fetch_add(&F.qt, (uint32_t)nb, __ATOMIC_ACQ_REL,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            for (int b = 0; b < nb; ++b) F.q[(q0 + b) % kFQ] = (uint16_t)((e << 4) | b);
+          }
+        }
+        R.slot = -1;
       } else {
+        // one Illinois iteration of a bracket (refine phase, or a bracket of
+        // the fused solve)
         int meta = s_rm[tid];
         int last = (meta & 3) - 1;
         const int it = (meta >> 2) + 1;
@@ -407,16 +518,51 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
             done = true;
         }
         if (done) {
-          V.b_theta[t] = c;
-          V.b_miss[t] = fin.miss;
-          V.b_t[t] = R.y[6];
-          V.b_s[t] = R.s;
-          V.b_as_re[t] = s_amp[0][tid];
-          V.b_as_im[t] = s_amp[1][tid];
-          V.b_ap_re[t] = s_amp[2][tid];
-          V.b_ap_im[t] = s_amp[3][tid];
-          V.b_status[t] = fin.status;
-          V.b_shots[t] = it;
+          if constexpr (PHASE == PH_FUSED) {
+            // the bracket's root into its entry, one lane of the wave at a
+            // time; the first arrival so far is written to the outputs
+            const int e = (int)((t >> 8) & 0xff), bi = (int)(t & 0xf);
+            const bool adm = fin.status == RT_SHOT_RECEIVER && fabs(fin.miss) <= V.accept_tol;
+            for (uint64_t m = __ballot(1); m; m &= m - 1) {
+              if (lane == __ffsll((unsigned long long)m) - 1) {
+                F.bshots[e] += it;
+                if (adm) {
+                  F.roots[e]++;
+                  const double tt = R.y[6];
+                  if (F.best_b[e] < 0 || tt < F.best_t[e] ||
+                      (tt == F.best_t[e] && bi < F.best_b[e])) {
+                    F.best_b[e] = bi;
+                    F.best_t[e] = tt;
+                    const rt_solve_outputs& O = V.so;
+                    const int64_t pf = F.pf[e];
+                    O.theta[pf] = c;
+                    O.miss[pf] = fin.miss;
+                    O.t[pf] = tt;
+                    O.s[pf] = R.s;
+                    O.as_re[pf] = s_amp[0][tid];
+                    O.as_im[pf] = s_amp[1][tid];
+                    O.ap_re[pf] = s_amp[2][tid];
+                    O.ap_im[pf] = s_amp[3][tid];
+                  }
+                }
+                if (--F.open[e] == 0) fused_finish(V, F, e, C);
+              }
+              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+              __builtin_amdgcn_wave_barrier();
+              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            }
+          } else {
+            V.b_theta[t] = c;
+            V.b_miss[t] = fin.miss;
+            V.b_t[t] = R.y[6];
+            V.b_s[t] = R.s;
+            V.b_as_re[t] = s_amp[0][tid];
+            V.b_as_im[t] = s_amp[1][tid];
+            V.b_ap_re[t] = s_amp[2][tid];
+            V.b_ap_im[t] = s_amp[3][tid];
+            V.b_status[t] = fin.status;
+            V.b_shots[t] = it;
+          }
           R.slot = -1;
         } else {
           s_ra[tid] = a;
@@ -438,7 +584,147 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
       fin.status = -1;
     }
     // ---- idle lanes take tasks ----
-    if (!exhausted) {
+    if constexpr (PHASE == PH_FUSED) {
+      // Every lane reads the wave's table (LDS of this wave only, updated
+      // above) and computes the same claims and hand-out; lane 0 writes the
+      // table back.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      const bool lane_idle = R.slot < 0;
+      const uint64_t idle = __ballot(lane_idle);
+      const uint32_t nidle = (uint32_t)__popcll(idle);
+      if (nidle > 0 && (nidle >= (uint32_t)V.refill || nidle == 64)) {
+        const uint32_t ns = (uint32_t)V.n_scan;
+        const uint32_t qh = F.qh, nq = F.qt - qh;
+        uint32_t sh = F.sh, st = F.st, used = F.used;
+        uint32_t sk = (uint32_t)F.sk;
+        uint32_t avail = nq + (sh != st ? ns - sk + (st - sh - 1) * ns : 0u);
+        // claim entries while the wave's work cannot occupy the idle lanes
+        if (!exhausted && avail < nidle) {
+          const uint32_t c = min((uint32_t)(kFEnt - __popc(used)), (nidle - avail + ns - 1) / ns);
+          if (c > 0) {
+            const int64_t n_ent = 2 * n_pairs;
+            unsigned long long base = 0;
+            if (lane == 0)
+              base = __hip_atomic_fetch_add(&V.tickets[PHASE], (uint64_t)c, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+            base = __shfl(base, 0);
+            if (base + c >= (uint64_t)n_ent) exhausted = true;
+            const uint32_t was = used;
+            for (uint32_t i = 0; i < c && base + i < (uint64_t)n_ent; ++i) {
+              const int64_t pf = (int64_t)(base + i);
+              const int32_t pair = (int32_t)(pf >> 1), fam = (int32_t)(pf & 1);
+              const bool ok = pair_ok(P, V.zs[pair], V.zr[pair], V.dist[pair]);
+              const bool want = !V.fam_mask || ((V.fam_mask[pair] >> fam) & 1);
+              if (!ok || !want) {
+                // no scan: an invalid pair, or a family not asked for
+                if (lane == 0) {
+                  const rt_solve_outputs& O = V.so;
+                  O.found[pf] = 0;
+                  O.shots[pf] = ok ? V.n_scan : 0;
+                  O.roots[pf] = 0;
+                  O.theta[pf] = O.miss[pf] = O.t[pf] = O.s[pf] = 0.0;
+                  O.as_re[pf] = O.as_im[pf] = O.ap_re[pf] = O.ap_im[pf] = 0.0;
+                  if (!ok && fam == 0) atomicAdd(&C.c[V_INVALID], 1ull);
+                }
+                continue;
+              }
+              const int e = __builtin_ctz(~used);  // c <= free slots
+              used |= 1u << e;
+              if (lane == 0) {
+                F.pf[e] = pf;
+                F.done[e] = 0;
+                F.open[e] = 0;
+                F.nb[e] = 0;
+                F.klast[e] = -1;
+                F.bshots[e] = 0;
+                F.roots[e] = 0;
+                F.best_b[e] = -1;
+                F.sq[st % kFEnt] = (int8_t)e;
+              }
+              if (sh == st) sk = 0;
+              ++st;
+              avail += ns;
+            }
+            if (lane == 0 && used != was)
+              __hip_atomic_fetch_or(&F.used, used & ~was, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+          }
+        }
+        // hand out: queued brackets first, then scan angles, oldest entry first
+        const uint32_t rank = (uint32_t)__popcll(idle & lanemask_lt());
+        const uint32_t nbk = min(nq, nidle);
+        int32_t task = -1;
+        if (lane_idle && rank < nbk) {
+          const int32_t qe = (int32_t)F.q[(qh + rank) % kFQ];
+          task = kFBracket | ((qe >> 4) << 8) | (qe & 0xf);
+        }
+        uint32_t given = nbk;
+        while (given < nidle && sh != st) {
+          const int32_t e = F.sq[sh % kFEnt];
+          const uint32_t take = min(ns - sk, nidle - given);
+          if (lane_idle && rank >= given && rank < given + take)
+            task = (e << 8) | (int32_t)(sk + rank - given);
+          given += take;
+          sk += take;
+          if (sk == ns) {
+            ++sh;
+            sk = 0;
+          }
+        }
+        if (lane == 0) {
+          F.qh = qh + nbk;
+          F.sh = sh;
+          F.st = st;
+          F.sk = (int32_t)sk;
+        }
+        if (task >= 0) {
+          const int e = (task >> 8) & 0xff;
+          const int64_t pf = F.pf[e];
+          S.pair = (int32_t)(pf >> 1);
+          S.fam = (int32_t)(pf & 1);
+          S.D = V.dist[S.pair];
+          const double zs = V.zs[S.pair], zr = V.zr[S.pair];
+          double theta;
+          if (task & kFBracket) {
+            const int bi = task & 0xf;
+            const int k = F.bk[e][bi];
+            const double* m = V.scan_miss + pf * V.n_scan;
+            const double a = ((double)(k - 1) + 0.5) * V.dtheta;
+            const double bb = ((double)k + 0.5) * V.dtheta;
+            const double Ga = m[k - 1], Gb = m[k];
+            s_ra[tid] = a;
+            s_rGa[tid] = Ga;
+            s_rb[tid] = bb;
+            s_rGb[tid] = Gb;
+            s_rma[tid] = Ga;
+            s_rmb[tid] = Gb;
+            s_rm[tid] = 1;  // no iterations, last side 0
+            theta = illinois_next(a, Ga, bb, Gb);
+            s_rc[tid] = theta;
+          } else {
+            theta = ((double)(task & 0xff) + 0.5) * V.dtheta;
+          }
+          R.slot = task;
+          double a4[4];
+          start_shot<MODEL>(P, R, S, zs, zr, theta, a4);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) s_amp[i][tid] = a4[i];
+          mode = 0;
+        }
+      }
+      if (__ballot(R.slot >= 0) == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (exhausted && F.used == 0) break;
+        continue;
+      }
+    } else if (!exhausted) {
       const bool lane_idle = R.slot < 0;
       const uint64_t idle = __ballot(lane_idle);
       const uint32_t nidle = (uint32_t)__popcll(idle);
@@ -755,7 +1041,7 @@ shot_kernel(KParams P, KSolve V) {
 __global__ void solve_reset_kernel(KSolve V) {
   const int i = threadIdx.x;
   if (i < V_COUNT) V.stats[i] = 0;
-  if (i < 4) V.tickets[i] = 0;
+  if (i < 5) V.tickets[i] = 0;
 }
 
 // The admissible refined root with the smallest travel time, per (pair,
@@ -939,7 +1225,8 @@ rt_status check_pairs_outputs(const rt_pairs* pairs, const rt_solve_outputs* out
   return RT_OK;
 }
 
-rt_status tuning_of(const rt_tuning* tuning, int& block, int& refill, int& chunk) {
+rt_status tuning_of(const rt_tuning* tuning, int& block, int& refill, int& chunk,
+                    int* fused = nullptr) {
   block = tuning && tuning->block_size ? tuning->block_size : 256;
   if (block < 64 || block > 256 || block % 64) {
     set_last_error("block_size must be 64, 128, 192 or 256");
@@ -955,6 +1242,12 @@ rt_status tuning_of(const rt_tuning* tuning, int& block, int& refill, int& chunk
     set_last_error("scan_chunk must be 1..4096");
     return RT_ERR_INVALID_ARG;
   }
+  const int sf = tuning ? tuning->solve_fused : 0;
+  if (sf != 0 && sf != 1) {
+    set_last_error("solve_fused must be 0 (three launches) or 1 (one fused launch)");
+    return RT_ERR_INVALID_ARG;
+  }
+  if (fused) *fused = sf;
   return RT_OK;
 }
 
@@ -980,13 +1273,14 @@ rt_status solve_enqueue(const rt_field* field, const rt_boundaries* bnd, double 
                         const rt_solve_params* prm, const rt_solve_outputs* out, void* workspace,
                         void* stream, const rt_tuning* tuning) {
   rt_status st;
-  int block = 0, refill = 0, chunk = 0, n_cu = 0;
-  if ((st = tuning_of(tuning, block, refill, chunk)) != RT_OK) return st;
+  int block = 0, refill = 0, chunk = 0, want_fused = 0, n_cu = 0;
+  if ((st = tuning_of(tuning, block, refill, chunk, &want_fused)) != RT_OK) return st;
   KParams P;
   if ((st = pack_params(field, bnd, tol, L, P)) != RT_OK) return st;
   if ((st = device_cus(n_cu)) != RT_OK) return st;
 
   const int64_t n = n_cap, K = prm->n_scan, B = prm->max_brackets;
+  const bool fused = want_fused && K <= kFScan && B <= kFBr;
   // a lane holds its task index in 32 bits
   if (2 * n * std::max(K, B) > (int64_t)0x7fffffff) {
     set_last_error("pairs x 2 x max(n_scan, max_brackets) = %lld exceeds 2^31 - 1 tasks",
@@ -1038,6 +1332,12 @@ rt_status solve_enqueue(const rt_field* field, const rt_boundaries* bnd, double 
   V.n_tasks = 2 * n * K;
   if (tuning && tuning->ev_trace_begin)
     HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(tuning->ev_trace_begin), s));
+  if (fused) {
+    HIP_TRY(launch_shots<PH_FUSED>(P, V, n_cu, block, s));
+    if (tuning && tuning->ev_trace_end)
+      HIP_TRY(hipEventRecord(static_cast<hipEvent_t>(tuning->ev_trace_end), s));
+    return RT_OK;
+  }
   HIP_TRY(launch_shots<PH_SCAN>(P, V, n_cu, block, s));
   V.n_tasks = 2 * n * B;
   HIP_TRY(launch_shots<PH_REFINE>(P, V, n_cu, block, s));
@@ -1254,8 +1554,9 @@ extern "C" rt_status rt_solve_autotune(const rt_field* field, const rt_boundarie
       *best = c;
     }
   };
-  // block size x refill threshold with each entry's scan in one piece, then
-  // the scan interleave at the best of those
+  // three launches: block size x refill threshold with each entry's scan
+  // in one piece, then the scan interleave at the best of those; then the
+  // fused launch at each block size (where the scan fits it)
   for (int bi = 0; st == RT_OK && bi < 4; ++bi)
     for (int ri = 0; st == RT_OK && ri < 4; ++ri) {
       cand.block_size = kBlocks[bi];
@@ -1265,6 +1566,14 @@ extern "C" rt_status rt_solve_autotune(const rt_field* field, const rt_boundarie
   for (int ci = 1; st == RT_OK && ci < 4; ++ci) {
     cand = *best;
     cand.scan_chunk = kChunks[ci];
+    trial(cand);
+  }
+  const bool fusable = prm && prm->n_scan <= kFScan && prm->max_brackets <= kFBr;
+  for (int bi = 0; st == RT_OK && fusable && bi < 4; ++bi) {
+    memset(&cand, 0, sizeof cand);
+    cand.block_size = kBlocks[bi];
+    cand.refill_threshold = 16;
+    cand.solve_fused = 1;
     trial(cand);
   }
   (void)hipEventDestroy(e0);

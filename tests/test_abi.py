@@ -29,7 +29,8 @@ def test_library_exports_every_declared_symbol():
                           "raytrace_launch", "rt_collect", "rt_last_error"}
     for n in names:
         assert hasattr(lib, n), n
-    assert B.rt_abi_version() == 7
+    assert B.rt_abi_version() == B.ABI_VERSION == 8
+    assert C.sizeof(B.rt_tuning) == 48 and B.rt_tuning.solve_fused.offset == 40
 
 
 def test_struct_layouts_match_header():

@@ -231,21 +231,66 @@ def test_solve_graph_replay(gpu):
         assert st == ref_st, rep
 
 
-@pytest.mark.parametrize("block,refill,chunk", [(64, 1, 1), (128, 64, 4), (192, 7, 64),
-                                               (256, 16, 4096)])
-def test_solve_schedule_independence(gpu, block, refill, chunk):
-    """Block size, refill threshold and the scan interleave (chunks of 4 and
-    64 entries; 4,096 > the 192 entries, a single short chunk) change which
-    lane shoots what, not the results."""
+@pytest.mark.parametrize("block,refill,chunk,fused", [
+    (64, 1, 1, 0), (128, 64, 4, 0), (192, 7, 64, 0), (256, 16, 4096, 0),
+    (64, 4, 0, 1), (128, 0, 0, 1), (192, 64, 0, 1), (256, 1, 0, 1)])
+def test_solve_schedule_independence(gpu, block, refill, chunk, fused):
+    """Block size, refill threshold, the scan interleave (chunks of 4 and
+    64 entries; 4,096 > the 192 entries, a single short chunk) and the
+    fused launch with its block size and refill threshold change which lane
+    shoots what, not the results."""
     sp = W.solve_pairs(96)
-    _announce(f"solve-sched-{block}-{refill}-{chunk}", sp.n)
+    _announce(f"solve-sched-{block}-{refill}-{chunk}-{fused}", sp.n)
     base, bst = gpu.solve(sp.scene, sp.zs, sp.zr, sp.dist)
     got, gst = gpu.solve(sp.scene, sp.zs, sp.zr, sp.dist,
                          tuning=gpu.rt_tuning(block_size=block, refill_threshold=refill,
-                                              scan_chunk=chunk))
+                                              scan_chunk=chunk, solve_fused=fused))
     for f in base:
         assert np.array_equal(base[f], got[f]), f
     assert bst == gst
+
+
+@pytest.mark.parametrize("model,n_scan,brackets,slope", [
+    (W.MODEL_PAPER, 64, 4, None), (W.MODEL_EXACT, 64, 4, None), (W.MODEL_PAPER, 16, 1, None),
+    (W.MODEL_EXACT, 40, 2, 0.0), (W.MODEL_PAPER, 2, 1, None)])
+def test_solve_fused_matches_three_launches(gpu, oracle_lib, model, n_scan, brackets, slope):
+    """The fused launch (scan, refinement and selection in one persistent
+    kernel) against the scan, refine and select launches: every output and
+    every statistic bit for bit, for scans that stop at the bracket limit
+    (one bracket of 16 angles), the smallest scan (2 angles) and no slope
+    bound; the results also against the oracle."""
+    sp = W.solve_pairs(160, model=model)
+    label = f"solve-fused-m{model}-{n_scan}-{brackets}-{slope}"
+    _announce(label, sp.n)
+    kw = {} if slope is None else dict(slope_max=slope)
+    prm = gpu.solve_params(n_scan=n_scan, max_brackets=brackets, **kw)
+    three, st3 = gpu.solve(sp.scene, sp.zs, sp.zr, sp.dist, params=prm,
+                           tuning=gpu.rt_tuning(solve_fused=0))
+    fused, stf = gpu.solve(sp.scene, sp.zs, sp.zr, sp.dist, params=prm,
+                           tuning=gpu.rt_tuning(solve_fused=1))
+    for f in three:
+        assert np.array_equal(three[f], fused[f]), f
+    assert st3 == stf
+    o = oracle_lib.solve(sp.scene, sp.zs, sp.zr, sp.dist, n_scan=n_scan,
+                         max_brackets=brackets, **kw)
+    compare_solves(oracle_lib, fused, o, sp.scene, (sp.zs, sp.zr, sp.dist), label)
+
+
+def test_solve_fused_limits(gpu):
+    """Scans of more than 64 angles or more than 4 brackets per entry take
+    the three launches whatever the tuning asks; solve_fused other than 0
+    or 1 is an error."""
+    sp = W.solve_pairs(48)
+    _announce("solve-fused-limits", sp.n)
+    prm = gpu.solve_params(n_scan=96, max_brackets=6)
+    a, sa = gpu.solve(sp.scene, sp.zs, sp.zr, sp.dist, params=prm)
+    b, sb = gpu.solve(sp.scene, sp.zs, sp.zr, sp.dist, params=prm,
+                      tuning=gpu.rt_tuning(solve_fused=1))
+    for f in a:
+        assert np.array_equal(a[f], b[f]), f
+    assert sa == sb
+    with pytest.raises(RuntimeError, match="solve_fused"):
+        gpu.solve(sp.scene, sp.zs, sp.zr, sp.dist, tuning=gpu.rt_tuning(solve_fused=2))
 
 
 def test_solve_full_size_sampled(gpu, oracle_lib):
