@@ -97,6 +97,42 @@ def test_fresnel_special_cases(oracle_lib):
     assert ct == pytest.approx(math.cos(0.7), abs=1e-15)
 
 
+def fresnel_by_angles(n1, n2, th):
+    """The four coefficients below the critical angle in Fresnel's angle
+    forms (Born & Wolf §1.5): r_s = -sin(i - t)/sin(i + t), r_p = tan(i -
+    t)/tan(i + t), t_s = 2 sin t cos i / sin(i + t), t_p = t_s / cos(i - t);
+    the limits at normal incidence are (n1 - n2)/(n1 + n2) for r_s, its
+    negative for r_p, and 2 n1/(n1 + n2) for both t."""
+    t = math.asin(n1 * math.sin(th) / n2)
+    if th == 0.0:
+        r = (n1 - n2) / (n1 + n2)
+        return r, -r, 2 * n1 / (n1 + n2), 2 * n1 / (n1 + n2)
+    rs = -math.sin(th - t) / math.sin(th + t)
+    rp = math.tan(th - t) / math.tan(th + t)
+    ts = 2.0 * math.sin(t) * math.cos(th) / math.sin(th + t)
+    return rs, rp, ts, ts / math.cos(th - t)
+
+
+@pytest.mark.parametrize("n1,n2", [(1.0, 1.78), (1.35, 1.0), (1.78, 1.79), (1.5, 1.31)])
+def test_fresnel_matches_angle_forms(oracle_lib, n1, n2):
+    """Every coefficient, with its sign, at every angle below the critical
+    one, against a formulation written in angles instead of cosines: a
+    mistake in any term of the oracle's cosine form (a swapped index, a sign,
+    a p coefficient built from the s denominator) fails it."""
+    crit = math.asin(n2 / n1) if n2 < n1 else math.pi / 2
+    for th in np.concatenate([[0.0], np.linspace(1e-3, crit * 0.995, 61)]):
+        rs, rp, ts, tp, ct, tir = oracle_lib.fresnel(n1, n2, math.cos(th))
+        assert not tir and rs.imag == rp.imag == ts.imag == tp.imag == 0.0
+        want = fresnel_by_angles(n1, n2, th)
+        for got, w, name in zip((rs.real, rp.real, ts.real, tp.real), want, "rs rp ts tp".split()):
+            assert got == pytest.approx(w, abs=2e-13), (n1, n2, th, name)
+    # the check itself separates the s and p forms (a p coefficient built
+    # from the s denominator would pass at normal incidence only)
+    th = 0.6
+    rs, rp, *_ = fresnel_by_angles(1.0, 1.78, th)
+    assert abs(rs - rp) > 0.05 and abs(rs + rp) > 0.05
+
+
 def test_fresnel_stokes_relations(oracle_lib):
     # r(n1->n2, i) = -r(n2->n1, t) and t t' = 1 - r^2 (Stokes)
     n1, n2 = 1.0, 1.78
