@@ -236,6 +236,40 @@ def trace(scene, roots=None, threads: int | None = None, capacity: int | None = 
     return out, stats
 
 
+class TrialLog(C.Structure):
+    _fields_ = [("h", C.POINTER(C.c_double)), ("err", C.POINTER(C.c_double)),
+                ("outcome", C.POINTER(C.c_int32)), ("cap", C.c_int64), ("n", C.c_int64)]
+
+
+def trace_log(scene, roots, cap: int = 1 << 20):
+    """The step controller's trials of the listed roots' trees, in order, on
+    one thread: (h, err / tol, outcome: 0 rejected, 1 accepted, 2 forced)."""
+    L = lib()
+    L.orc_trace_log.restype = C.c_int
+    L.orc_trace_log.argtypes = [C.POINTER(Problem), C.POINTER(C.c_int64), C.c_int64,
+                                C.POINTER(Records), C.POINTER(Stats), C.POINTER(TrialLog)]
+    prep = _Prepared(scene)
+    ra = np.ascontiguousarray(roots, dtype=np.int64)
+    capacity = max(16, 8 * len(ra) + 64)
+    arrs = {f: np.zeros(capacity, np.float64) for f in F64_FIELDS}
+    arrs.update({f: np.zeros(capacity, np.uint64) for f in U64_FIELDS})
+    arrs.update({f: np.zeros(capacity, np.int32) for f in I32_FIELDS})
+    rec = Records(*([_ptr(arrs[f], C.c_double) for f in F64_FIELDS]
+                    + [_ptr(arrs[f], C.c_uint64) for f in U64_FIELDS]
+                    + [_ptr(arrs[f], C.c_int32) for f in I32_FIELDS]
+                    + [capacity]))
+    h, err = np.zeros(cap, np.float64), np.zeros(cap, np.float64)
+    outcome = np.zeros(cap, np.int32)
+    log = TrialLog(_ptr(h, C.c_double), _ptr(err, C.c_double), _ptr(outcome, C.c_int32), cap, 0)
+    st = Stats()
+    rc = L.orc_trace_log(C.byref(prep.P), _ptr(ra, C.c_int64), len(ra), C.byref(rec),
+                         C.byref(st), C.byref(log))
+    if rc != 0:
+        raise RuntimeError(f"oracle: trace_log returned {rc}")
+    n = log.n
+    return h[:n].copy(), err[:n].copy(), outcome[:n].copy()
+
+
 def _trace_events(scene, roots, threads, capacity, ev_capacity=None):
     L = lib()
     prep = _Prepared(scene)

@@ -138,6 +138,24 @@ int orc_trace_events(const orc_problem* P, const int64_t* roots, int64_t n_roots
                      orc_records* out, orc_stats* stats, orc_events* ev,
                      int64_t* n_events, int n_threads);
 
+/* The step controller's record of the trials of a trace (test
+ * instrumentation: the controller is a convention the paper does not fix,
+ * and its constants are checked against the order of the method).  Every
+ * trial step of the normal stepping (not of the crossing search) appends its
+ * length, its error ratio (error norm / tol) and its outcome (0 rejected, 1
+ * accepted, 2 forced at h_min), while n < cap. */
+typedef struct {
+  double* h;
+  double* err;
+  int32_t* outcome;
+  int64_t cap, n;
+} orc_trial_log;
+
+/* orc_trace of the listed roots on one thread, logging their trials in
+ * order (one root's whole tree, then the next). */
+int orc_trace_log(const orc_problem* P, const int64_t* roots, int64_t n_roots,
+                  orc_records* out, orc_stats* stats, orc_trial_log* log);
+
 /* Single Cash-Karp trial step of the ray ODE from y0 (7 components) with step
  * h in region reg: writes the 5th-order result and the embedded error vector. */
 void orc_ck_trial(const orc_problem* P, int32_t reg, const double y0[7],

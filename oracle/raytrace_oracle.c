@@ -420,7 +420,17 @@ typedef struct {
   int64_t* rec_counter; /* shared */
   orc_events* ev;       /* NULL: no event records */
   int64_t* ev_counter;  /* shared */
+  orc_trial_log* log;   /* NULL: no trial log */
 } worker_t;
+
+static void log_trial(worker_t* W, double h, double err, int32_t outcome) {
+  orc_trial_log* L = W->log;
+  if (!L || L->n >= L->cap) return;
+  L->h[L->n] = h;
+  L->err[L->n] = err;
+  L->outcome[L->n] = outcome;
+  L->n++;
+}
 
 /* Event record of a Fresnel event of ray r at boundary k (r holds the state
  * on the boundary and the incident amplitudes; u the incident direction). */
@@ -631,6 +641,7 @@ static void trace_tree(worker_t* W, const ray_t* root) {
         status = ORC_ST_NONFINITE;
         break;
       }
+      log_trial(W, hp, err, !(err <= 1.0) ? (hp <= P->h_min ? 2 : 0) : 1);
       if (!(err <= 1.0) && !(hp <= P->h_min)) {
         /* rejected: shrink and retry */
         r.n_rej++;
@@ -841,9 +852,9 @@ int orc_trace(const orc_problem* P, const int64_t* roots, int64_t n_roots,
   return orc_trace_events(P, roots, n_roots, out, stats, NULL, &n_events, n_threads);
 }
 
-int orc_trace_events(const orc_problem* P, const int64_t* roots, int64_t n_roots,
-                     orc_records* out, orc_stats* stats, orc_events* ev,
-                     int64_t* n_events, int n_threads) {
+static int trace_impl(const orc_problem* P, const int64_t* roots, int64_t n_roots,
+                      orc_records* out, orc_stats* stats, orc_events* ev, int64_t* n_events,
+                      int n_threads, orc_trial_log* log) {
   scene_t S;
   if (P->max_gen < 1 || P->max_gen > 4 || P->n_planes > 16) return -2;
   build_scene(P, &S);
@@ -857,6 +868,7 @@ int orc_trace_events(const orc_problem* P, const int64_t* roots, int64_t n_roots
     jobs[t].W.rec_counter = &counter;
     jobs[t].W.ev = ev;
     jobs[t].W.ev_counter = &ev_counter;
+    jobs[t].W.log = log;
     jobs[t].roots = roots;
     jobs[t].n_roots = n_roots;
     jobs[t].next = &next;
@@ -888,6 +900,19 @@ int orc_trace_events(const orc_problem* P, const int64_t* roots, int64_t n_roots
   free(jobs);
   if (counter > out->capacity) return -1;
   return ev && ev_counter > ev->capacity ? -3 : 0;
+}
+
+int orc_trace_events(const orc_problem* P, const int64_t* roots, int64_t n_roots,
+                     orc_records* out, orc_stats* stats, orc_events* ev,
+                     int64_t* n_events, int n_threads) {
+  return trace_impl(P, roots, n_roots, out, stats, ev, n_events, n_threads, NULL);
+}
+
+int orc_trace_log(const orc_problem* P, const int64_t* roots, int64_t n_roots,
+                  orc_records* out, orc_stats* stats, orc_trial_log* log) {
+  int64_t n_events;
+  if (log) log->n = 0;
+  return trace_impl(P, roots, n_roots, out, stats, NULL, &n_events, 1, log);
 }
 
 /* ======================================================================== */

@@ -165,6 +165,59 @@ def test_fresnel_total_internal_reflection(oracle_lib):
 
 
 # ---------------------------------------------------------------------------
+# Step controller (the accuracy discussion of section 2: the minimum step
+# length and the tolerance set the accuracy; the controller law is a
+# convention): its exponents and safety factor, from the trials it logs
+# ---------------------------------------------------------------------------
+def controller_trials(z0, tol, h_init):
+    reg = W.Region(a=1.78, dn=0.43, z0=z0)
+    dirs = [launch(a) for a in np.linspace(100, 170, 32)]
+    sc = scene([reg], src=(0.0, 0.0, 300.0), dirs=dirs, tol=tol, h_max=10.0, h_init=h_init,
+               s_max=400.0, h_min=1e-4)
+    return oracle_mod().trace_log(sc, np.arange(len(dirs)))
+
+
+def oracle_mod():
+    import oracle
+    return oracle
+
+
+def test_controller_retry_after_reject_follows_the_order(oracle_lib):
+    """The error ratio of a Cash-Karp step scales as h^4 (|dr|/h of an
+    embedded fifth/fourth-order pair), so a rejected trial with ratio err
+    shrunk by 0.9 err^(-1/4) is retried at 0.9^4 err (h'/h)^4 ... = 0.9^4 =
+    0.656, whatever err was: the retries land there (a -1/5 exponent would
+    give 0.656 err^(1/5), 0.9 to 1.1 for the errors here; a safety factor of
+    0.8 or 0.95 would give 0.41 or 0.81)."""
+    h, err, oc = controller_trials(75.0, 1e-11, 0.0)
+    idx = [i for i in range(len(h) - 1) if oc[i] == 0 and 5.0 < err[i] < 6000.0]
+    assert len(idx) >= 10
+    retry = err[np.array(idx) + 1]
+    assert np.all((retry > 0.62) & (retry < 0.72)), retry
+
+
+def test_controller_growth_law(oracle_lib):
+    """After an accepted trial the next step is h min(5, 0.9 err^(-1/5)):
+    the logged (err, h'/h) pairs of uncapped growth lie on that line in log
+    space (slope -1/5, intercept log 0.9), and below err = (0.9/5)^5 the
+    factor is 5."""
+    h, err, oc = controller_trials(40.0, 1e-11, 0.1)
+    nxt = np.arange(1, len(h))
+    cur = nxt - 1
+    # a ray's first trial is h_init; its last one is clipped to land on s_max
+    last = np.append(h[2:] == 0.1, True)
+    same_ray = (h[nxt] != 0.1) & (oc[cur] != 0) & ~last
+    free = same_ray & (h[nxt] < 9.99) & (err[cur] > 2e-4)
+    x, y = np.log(err[cur][free]), np.log(h[nxt][free] / h[cur][free])
+    assert free.sum() >= 50
+    slope, icpt = np.polyfit(x, y, 1)
+    assert slope == pytest.approx(-0.2, abs=2e-3) and math.exp(icpt) == pytest.approx(0.9, rel=2e-3)
+    capped = same_ray & (h[nxt] < 9.99) & (err[cur] < 1.8e-4)
+    if capped.any():
+        assert np.allclose(h[nxt][capped] / h[cur][capped], 5.0, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
 # Propagation in simple media
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("model", [W.MODEL_PAPER, W.MODEL_EXACT])
