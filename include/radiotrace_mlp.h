@@ -68,9 +68,17 @@ rt_status rt_mlp_pack(const float* params, void* workspace, size_t workspace_byt
                       void* stream);
 
 /* y[B][12] = network(x[B][5]) with the packed weights; biases are read from
- * 'params'.  1 <= batch <= the workspace's batch. */
+ * 'params'.  1 <= batch <= the workspace's batch.  One launch for the whole
+ * network (the activations of a tile of 128 rows stay on chip between the
+ * layers). */
 rt_status rt_mlp_forward(const float* params, const float* x, int64_t batch, float* y,
                          void* workspace, size_t workspace_bytes, void* stream);
+
+/* Plumbing: the same forward as one matrix-core launch per layer, the
+ * activations going through the workspace; results equal rt_mlp_forward's
+ * bit for bit (the same products in the same order). */
+rt_status rt_mlp_forward_layers(const float* params, const float* x, int64_t batch, float* y,
+                                void* workspace, size_t workspace_bytes, void* stream);
 
 /* Forward and backward pass of the loss above: grad[rt_mlp_param_count()]
  * receives dL/dparams (overwritten), *loss (device, one float) the loss.

@@ -275,6 +275,9 @@ def lib() -> C.CDLL:
         L.rt_mlp_forward.restype = C.c_int
         L.rt_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                      C.c_size_t, C.c_void_p]
+        L.rt_mlp_forward_layers.restype = C.c_int
+        L.rt_mlp_forward_layers.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                            C.c_void_p, C.c_size_t, C.c_void_p]
         L.rt_mlp_gradients.restype = C.c_int
         L.rt_mlp_gradients.argtypes = [C.c_void_p] * 4 + [C.c_int64, C.c_void_p, C.c_void_p,
                                                          C.c_void_p, C.c_size_t, C.c_void_p]
@@ -702,6 +705,13 @@ def rt_mlp_forward(params, x, batch, y, workspace, workspace_bytes, stream) -> i
                                     C.c_size_t(workspace_bytes), C.c_void_p(stream)))
 
 
+def rt_mlp_forward_layers(params, x, batch, y, workspace, workspace_bytes, stream) -> int:
+    return int(lib().rt_mlp_forward_layers(C.c_void_p(params), C.c_void_p(x),
+                                           C.c_int64(batch), C.c_void_p(y),
+                                           C.c_void_p(workspace), C.c_size_t(workspace_bytes),
+                                           C.c_void_p(stream)))
+
+
 def rt_mlp_gradients(params, x, targets, mask, batch, grad, loss, workspace, workspace_bytes,
                      stream) -> int:
     return int(lib().rt_mlp_gradients(
@@ -753,11 +763,13 @@ class DeviceMLP:
         self._check(rt_mlp_pack(self.params.data_ptr(), self.workspace.data_ptr(),
                                 self.ws_bytes, self._stream()))
 
-    def forward(self, x, y):
-        """x: device FP32 [B][5] tensor; y: device FP32 [B][10] tensor (written)."""
+    def forward(self, x, y, layers: bool = False):
+        """x: device FP32 [B][5] tensor; y: device FP32 [B][12] tensor
+        (written); layers=True: one launch per layer (rt_mlp_forward_layers)."""
         B = int(x.shape[0])
-        self._check(rt_mlp_forward(self.params.data_ptr(), x.data_ptr(), B, y.data_ptr(),
-                                   self.workspace.data_ptr(), self.ws_bytes, self._stream()))
+        fn = rt_mlp_forward_layers if layers else rt_mlp_forward
+        self._check(fn(self.params.data_ptr(), x.data_ptr(), B, y.data_ptr(),
+                       self.workspace.data_ptr(), self.ws_bytes, self._stream()))
 
     def gradients(self, x, t, m):
         """Fills self.grad and self.loss for a batch of device tensors."""

@@ -35,9 +35,17 @@ constexpr int kOut[kLayers] = {RT_MLP_WIDTH, RT_MLP_WIDTH, RT_MLP_WIDTH, RT_MLP_
 constexpr int pad16(int x) { return (x + 15) / 16 * 16; }
 constexpr int64_t pad16l(int64_t x) { return (x + 15) / 16 * 16; }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
+// The logistic function from the hardware base-2 exponential and
+// reciprocal (about 1 ulp each; e^-z overflowing to +inf gives 0, the
+// limit): relative errors near 1e-7, far below the BF16 rounding (2^-9)
+// that every activation then takes, and a fraction of the instructions of
+// an IEEE division and the library exponential.
+__device__ __forceinline__ float sigmoid(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z * -1.4426950408889634f));
+}
+__device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
 __device__ __forceinline__ float silu_grad(float z) {
-  const float s = 1.0f / (1.0f + expf(-z));
+  const float s = sigmoid(z);
   return s * (1.0f + z * (1.0f - s));
 }
 
@@ -160,6 +168,135 @@ __global__ void __launch_bounds__(256) gemm_nt_kernel(GemmArgs g) {
   }
 }
 
+// Inference of the whole network in one launch.  A block of four waves takes
+// 128 rows of the batch; their activations stay in LDS from layer to layer
+// (BF16, rows padded to kActLd values so that the 32 rows a wave's lanes
+// read at one k land in different banks).  Wave w computes columns 64 w ...
+// 64 w + 63 of each hidden layer for all 128 rows, reading those columns of
+// the layer's weights from L2 (each weight is read once per block); the
+// output layer gives wave w rows 32 w ... 32 w + 31.  Every output element is
+// accumulated by the same MFMA sequence over k as in gemm_nt_kernel and
+// finished by the same epilogue, so the result equals the layer-by-layer
+// launches bit for bit; what it saves is the round trip of every activation
+// through HBM (2 x 512 MB per hidden layer at a million rows).
+constexpr int kInferRows = 128;
+constexpr int kActLd = RT_MLP_WIDTH + 8;
+struct InferArgs {
+  const bf16* wb[kLayers];    // packed weights [out][ldw]
+  int ldw[kLayers];
+  const float* bias[kLayers];
+};
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) mlp_infer_kernel(const bf16* __restrict__ x0, InferArgs g,
+                                                        int64_t B, float* __restrict__ y) {
+  static_assert(RT_MLP_WIDTH == 256 && RT_MLP_HIDDEN == 4 && RT_MLP_OUT <= 32,
+                "the fused inference tiles a 256-wide network");
+  __shared__ bf16 act[kInferRows * kActLd];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane & 31, kh = (lane >> 5) * 8;
+  const int64_t rowb = (int64_t)blockIdx.x * kInferRows;
+  const bf16x8 zero = {};
+  for (int h = 0; h < RT_MLP_HIDDEN; ++h) {
+    const int col0 = w * 64;
+    const bf16* Wl = g.wb[h];
+    const int ldw = g.ldw[h];
+    const bf16* wrow[2] = {Wl + (int64_t)(col0 + r) * ldw + kh,
+                           Wl + (int64_t)(col0 + 32 + r) * ldw + kh};
+    f32x16 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+    if (h == 0) {
+      // the 16 (padded) input features: one k step, A from the batch
+      bf16x8 a[4], b[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t grow = rowb + i * 32 + r;
+        a[i] = grow < B ? *reinterpret_cast<const bf16x8*>(x0 + grow * 16 + kh) : zero;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(wrow[j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    } else {
+      // K = 256 from the LDS activations; the weights of step k + 16 are
+      // loaded before the products of step k
+      bf16x8 b[2], bn[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(wrow[j]);
+#pragma unroll
+      for (int k = 0; k < RT_MLP_WIDTH; k += 16) {
+        if (k + 16 < RT_MLP_WIDTH) {
+#pragma unroll
+          for (int j = 0; j < 2; ++j) bn[j] = *reinterpret_cast<const bf16x8*>(wrow[j] + k + 16);
+        }
+        bf16x8 a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          a[i] = *reinterpret_cast<const bf16x8*>(act + (i * 32 + r) * kActLd + k + kh);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = bn[j];
+      }
+    }
+    __syncthreads();  // every wave has read this layer's input
+    // lane holds column col0 + 32 j + (lane & 31) and, for v = 0..15, row
+    // 32 i + 8 (v / 4) + 4 (lane / 32) + v % 4
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = col0 + j * 32 + r;
+      const float bj = g.bias[h][col];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rb = i * 32 + q * 8 + (lane >> 5) * 4;
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            act[(rb + u) * kActLd + col] = (bf16)silu(acc[i][j][q * 4 + u] + bj);
+        }
+    }
+    __syncthreads();
+  }
+  // output layer: rows 32 w ... 32 w + 31, columns 0 ... 31 (RT_MLP_OUT used)
+  {
+    const bf16* Wl = g.wb[RT_MLP_HIDDEN];
+    const int ldw = g.ldw[RT_MLP_HIDDEN];
+    const bool okb = r < RT_MLP_OUT;
+    f32x16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    for (int k = 0; k < RT_MLP_WIDTH; k += 16) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(act + (w * 32 + r) * kActLd + k + kh);
+      const bf16x8 b = okb ? *reinterpret_cast<const bf16x8*>(Wl + (int64_t)r * ldw + k + kh)
+                           : zero;
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    if (okb) {
+      const float bo = g.bias[RT_MLP_HIDDEN][r];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rb = w * 32 + q * 8 + (lane >> 5) * 4;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t grow = rowb + rb + u;
+          if (grow < B) y[grow * RT_MLP_OUT + r] = acc[q * 4 + u] + bo;
+        }
+      }
+    }
+  }
+}
+
 // Features [B][5] FP32 -> x0 [B][16] BF16 (zero-padded) and, for training,
 // x0T [16][Bp] (zero beyond B).
 __global__ void features_kernel(const float* __restrict__ x, int64_t B, int64_t Bp,
@@ -267,20 +404,26 @@ __global__ void __launch_bounds__(256) silu_back_kernel(const float* __restrict_
   }
 }
 
-// out[r] = sum over the Bp columns of row r of a BF16 matrix (bias gradients).
+// out[r] = sum over the n columns of row r of a BF16 matrix (bias gradients):
+// 16-byte loads of 8 values (rows start 16-byte aligned: ld a multiple of 8),
+// then the wave sums and the four waves' sums.
 __global__ void __launch_bounds__(256) rowsum_kernel(const bf16* __restrict__ X, int64_t ld,
                                                      int64_t n, float* __restrict__ out) {
-  __shared__ float red[256];
+  __shared__ float red[4];
   const bf16* row = X + (int64_t)blockIdx.x * ld;
   float s = 0.0f;
-  for (int64_t i = threadIdx.x; i < n; i += 256) s += (float)row[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-    __syncthreads();
+  const int64_t n8 = n / 8;
+  for (int64_t i = threadIdx.x; i < n8; i += 256) {
+    const bf16x8 v = *reinterpret_cast<const bf16x8*>(row + 8 * i);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += (float)v[u];
   }
-  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+  for (int64_t i = 8 * n8 + threadIdx.x; i < n; i += 256) s += (float)row[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // out[i] = sum over s < S of part[s n + i]: the slices of a split-K product,
@@ -290,7 +433,16 @@ __global__ void __launch_bounds__(256) splitk_sum_kernel(const float* __restrict
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float acc = part[i];
-  for (int z = 1; z < S; ++z) acc += part[(int64_t)z * n + i];
+  int z = 1;
+  // eight slices' loads in flight, added in slice order
+  for (; z + 8 <= S; z += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(z + u) * n + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; z < S; ++z) acc += part[(int64_t)z * n + i];
   out[i] = acc;
 }
 
@@ -515,6 +667,33 @@ extern "C" rt_status rt_mlp_pack(const float* params, void* ws, size_t bytes, vo
 
 extern "C" rt_status rt_mlp_forward(const float* params, const float* x, int64_t B, float* y,
                                     void* ws, size_t bytes, void* stream) {
+  using namespace rt::mlp;
+  rt_status st = check_ws(ws, bytes, B, false);
+  if (st != RT_OK) return st;
+  if (!params || !x || !y) {
+    rt::set_last_error("null params, x or y");
+    return RT_ERR_INVALID_ARG;
+  }
+  const Offsets o = param_offsets();
+  const Layout L = layout(static_cast<char*>(ws), B, false);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(features_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, x, B,
+                     B, L.x0, (bf16*)nullptr);
+  HIP_TRY(hipGetLastError());
+  InferArgs g;
+  for (int l = 0; l < kLayers; ++l) {
+    g.wb[l] = L.wb[l];
+    g.ldw[l] = pad16(kIn[l]);
+    g.bias[l] = params + o.b[l];
+  }
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)((B + kInferRows - 1) / kInferRows)),
+                     dim3(256), 0, s, L.x0, g, B, y);
+  HIP_TRY(hipGetLastError());
+  return RT_OK;
+}
+
+extern "C" rt_status rt_mlp_forward_layers(const float* params, const float* x, int64_t B,
+                                           float* y, void* ws, size_t bytes, void* stream) {
   using namespace rt::mlp;
   rt_status st = check_ws(ws, bytes, B, false);
   if (st != RT_OK) return st;

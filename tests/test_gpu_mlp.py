@@ -46,6 +46,29 @@ def _dev(a):
     return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
 
 
+@pytest.mark.parametrize("B", [1, 127, 128, 129, 1000, 65536 + 77])
+def test_fused_forward_equals_layer_launches(gpu, B):
+    """The one-launch forward (activations kept in LDS per 128-row tile)
+    against one launch per layer: the same MFMA products in the same order
+    and the same epilogues, so every output bit for bit, for batches below,
+    at and above one tile and a ragged last tile."""
+    import torch
+    print(f"\n[gpu-case] mlp-fused B={B}", flush=True)
+    p = W.mlp_init_params(11)
+    p[-12:] = 0.05
+    net = gpu.DeviceMLP(p, max_batch=B, training=False)
+    x, _, _ = _data(B, seed=B + 3)
+    xd = _dev(x * 2.0)
+    y1 = torch.full((B, 12), -7.0, dtype=torch.float32, device="cuda")
+    y2 = torch.full((B, 12), -9.0, dtype=torch.float32, device="cuda")
+    net.forward(xd, y1)
+    net.forward(xd, y2, layers=True)
+    torch.cuda.synchronize()
+    a, b = y1.cpu().numpy(), y2.cpu().numpy()
+    assert np.isfinite(a).all()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), np.abs(a - b).max()
+
+
 @pytest.mark.parametrize("B", [1, 37, 1000, 4096])
 def test_forward_matches_reference(gpu, B):
     import torch
