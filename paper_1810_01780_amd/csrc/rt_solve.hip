@@ -66,7 +66,7 @@ enum : int { PH_LIST = 0, PH_SCAN = 1, PH_REFINE = 2, PH_SEEDED = 3, PH_FUSED = 
 // wave has finished its entries and no entry is left to claim.  Each shot
 // and each bracket is computed exactly as in the three launches (scan,
 // refine, select), so the results are the same.  It is not the default: on
-// the 65,536-pair solve it took 80 ms against 67 ms for the three launches
+// the 65,536-pair solve it took 76 ms against 69 ms for the three launches
 // (the same shots in ~4 % more wave iterations, each dearer: the table
 // logic runs between trials and the kernel holds more registers); the
 // autotuner still tries it.
@@ -588,13 +588,13 @@ __device__ __forceinline__ void shot_body(const KParams& P, const KSolve& V) {
       // Every lane reads the wave's table (LDS of this wave only, updated
       // above) and computes the same claims and hand-out; lane 0 writes the
       // table back.
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       const bool lane_idle = R.slot < 0;
       const uint64_t idle = __ballot(lane_idle);
       const uint32_t nidle = (uint32_t)__popcll(idle);
       if (nidle > 0 && (nidle >= (uint32_t)V.refill || nidle == 64)) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         const uint32_t ns = (uint32_t)V.n_scan;
         const uint32_t qh = F.qh, nq = F.qt - qh;
         uint32_t sh = F.sh, st = F.st, used = F.used;
