@@ -114,7 +114,10 @@ typedef struct {
  * taken by central differences (one-sided at the edges).  The node
  * differences are formed in FP32, which is exact when all values lie within
  * a factor of two of each other (true for refractive indices in [1, 2)).
- * Positions outside the grid are clamped onto it.  nx, ny, nz >= 2. */
+ * Positions outside the grid are clamped onto it.  nx, ny, nz >= 2, and
+ * the prepared nodes (16 bytes each, in 2 x 2 x 2 bricks) under 4 GiB:
+ * ceil(nx/2) ceil(ny/2) ceil(nz/2) x 128 < 2^32 (about 2.7e8 nodes;
+ * RT_ERR_UNSUPPORTED beyond). */
 typedef struct {
   const float* n; /* device, nz*ny*nx floats */
   int32_t nx, ny, nz;

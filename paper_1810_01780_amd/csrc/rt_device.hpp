@@ -311,18 +311,22 @@ __device__ __forceinline__ void grid_fetch(const KParams& P, double x, double y,
     i0[a] = i;
     F.t[a] = v - (double)i;
   }
-  // per axis, the offsets of the cell's two node planes
-  size_t ox[2], oy[2], oz[2];
+  // per axis, the byte offsets of the cell's two node planes (32 bits:
+  // the node array is under 4 GiB)
+  const char* base = static_cast<const char*>(P.nodes);
+  const uint32_t sy = (uint32_t)P.gbx * 128u, sz = sy * (uint32_t)P.gby;
+  uint32_t ox[2], oy[2], oz[2];
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
-    const int i = i0[0] + e, j = i0[1] + e, k = i0[2] + e;
-    ox[e] = (size_t)(i >> 1) * 8 + (size_t)(i & 1);
-    oy[e] = (size_t)(j >> 1) * 8 * P.gbx + (size_t)((j & 1) << 1);
-    oz[e] = (size_t)(k >> 1) * 8 * P.gbx * P.gby + (size_t)((k & 1) << 2);
+    const uint32_t i = (uint32_t)(i0[0] + e), j = (uint32_t)(i0[1] + e), k = (uint32_t)(i0[2] + e);
+    ox[e] = ((i >> 1) << 7) | ((i & 1u) << 4);
+    oy[e] = (j >> 1) * sy + ((j & 1u) << 5);
+    oz[e] = (k >> 1) * sz + ((k & 1u) << 6);
   }
 #pragma unroll
   for (int q = 0; q < 8; ++q)
-    F.c[q] = nodes[ox[q & 1] + oy[(q >> 1) & 1] + oz[(q >> 2) & 1]];
+    F.c[q] = *reinterpret_cast<const float4*>(base + (ox[q & 1] + oy[(q >> 1) & 1] +
+                                                      oz[(q >> 2) & 1]));
 }
 
 __device__ __forceinline__ void grid_blend(const KParams& P, const GridFetch& F, double& n,

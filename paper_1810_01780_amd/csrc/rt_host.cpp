@@ -85,7 +85,10 @@ rt_status validate(const rt_field* field, const rt_boundaries* bnd, const rt_sou
     const rt_grid& g = field->grid;
     if (!g.n) FAIL(RT_ERR_INVALID_ARG, "grid: null data pointer");
     if (g.nx < 2 || g.ny < 2 || g.nz < 2) FAIL(RT_ERR_INVALID_ARG, "grid: dims must be >= 2");
-    if ((double)g.nx * g.ny * g.nz > 4.0e9) FAIL(RT_ERR_UNSUPPORTED, "grid: too many nodes");
+    // the prepared nodes (2 x 2 x 2 bricks of 128 bytes) are addressed with
+    // 32-bit byte offsets
+    if ((double)((g.nx + 1) / 2) * ((g.ny + 1) / 2) * ((g.nz + 1) / 2) * 128.0 > 4294967295.0)
+      FAIL(RT_ERR_UNSUPPORTED, "grid: the prepared nodes would exceed 4 GiB (about 2.7e8 nodes)");
     for (int a = 0; a < 3; ++a) {
       if (!(g.spacing[a] > 0.0) || !std::isfinite(g.spacing[a]))
         FAIL(RT_ERR_INVALID_ARG, "grid: spacing must be > 0");

@@ -129,6 +129,14 @@ def test_validate_grid_descriptor():
     d.field.grid.nz = 4
     d.field.grid.spacing = (C.c_double * 3)(10.0, 0.0, 10.0)
     assert _validate(d) == B.RT_ERR_INVALID_ARG
+    # the prepared nodes are addressed with 32-bit byte offsets: 512 x 512 x
+    # 128 = 2^25 bricks of 128 bytes are one byte too many (nz = 255 still
+    # needs 128 brick layers), 127 layers are accepted
+    d.field.grid.spacing = (C.c_double * 3)(10.0, 10.0, 10.0)
+    d.field.grid.nx, d.field.grid.ny = 1024, 1024
+    for nz, want in ((256, B.RT_ERR_UNSUPPORTED), (255, B.RT_ERR_UNSUPPORTED), (254, B.RT_OK)):
+        d.field.grid.nz = nz
+        assert _validate(d) == want, nz
 
 
 def test_workspace_bytes():
