@@ -155,8 +155,10 @@ def test_gridded_small_grid_exact_model(gpu, oracle_lib):
     got, gst = gpu.trace(sc)
     ref, rst = oracle_lib.trace(sc)
     ref2, _ = oracle_lib.trace(perturbed(sc))
+    # tol 1e-6 on a small grid: its sensitive rays moved 1.2e-6 (positions)
+    # and 1.2e-5 (amplitudes) on the GPU
     summ = compare_conditioned(got, ref, ref2, sc.limits.tol, label="grid-small-exact",
-                               amp_dir_sens=AMP_DIR_SENS_GRID)
+                               amp_dir_sens=AMP_DIR_SENS_GRID, ill_cap=1e-5, amp_cap=1e-4)
     print(f"[gpu-case] grid-small-exact: {summ}", flush=True)
     assert summ["well_conditioned"] > 0.5 * sc.n_rays
 
@@ -312,7 +314,10 @@ def test_two_layer_full_size_all_roots(gpu, oracle_lib):
     print("[gpu-case] twolayer-full: GPU done, oracle running", flush=True)
     ref, rst = oracle_lib.trace(sc)
     ref2, _ = oracle_lib.trace(perturbed(sc))
-    summ = compare_conditioned(got, ref, ref2, sc.limits.tol, label="twolayer-full")
+    # the rays the oracle itself cannot reproduce under 1e-15 perturbations
+    # (grazing a boundary) moved at most 2.7e-10 on the GPU
+    summ = compare_conditioned(got, ref, ref2, sc.limits.tol, label="twolayer-full",
+                               ill_cap=1e-8, amp_cap=1e-9)
     print(f"[gpu-case] twolayer-full: {summ}; stats {gst}", flush=True)
     assert gst["records"] == gst["needed"] and gst["sched_errors"] == 0
     assert summ["well_conditioned"] >= 0.95 * len(ref["key"])
@@ -335,8 +340,9 @@ def test_gridded_full_size_all_roots_tol1e6(gpu, oracle_lib):
     # which acts on a ray like a change of its start of ~1e-14: the
     # classifying perturbation has that size here
     ref2, _ = oracle_lib.trace(perturbed(sc, 1e-14))
+    # at tol 1e-6 the sensitive rays moved at most 1.0e-9 on the GPU
     summ = compare_conditioned(got, ref, ref2, sc.limits.tol, label="grid256-full-tol1e-6",
-                               amp_dir_sens=AMP_DIR_SENS_GRID)
+                               amp_dir_sens=AMP_DIR_SENS_GRID, ill_cap=1e-7, amp_cap=1e-8)
     print(f"[gpu-case] grid256-full-tol1e-6: {summ}; stats {gst}", flush=True)
     assert summ["well_conditioned"] >= 0.95 * sc.n_rays
     for f in ("accepted", "rejected", "events", "records"):
