@@ -202,24 +202,27 @@ def test_solve_invalid_and_empty(gpu):
     assert g0["found"].shape == (0, 2) and st0["shots"] == 0
 
 
-def test_solve_graph_replay(gpu):
-    """The whole solve captured into a graph and replayed: every replay gives
-    the eager result exactly (the same shots run, whichever lane runs them)."""
+@pytest.mark.parametrize("fused", [0, 1])
+def test_solve_graph_replay(gpu, fused):
+    """The whole solve (three launches, or the fused launch) captured into a
+    graph and replayed: every replay gives the eager result exactly (the same
+    shots run, whichever lane runs them)."""
     import torch
     sp = W.solve_pairs(128)
-    _announce("solve-graph", sp.n)
+    _announce(f"solve-graph-fused{fused}", sp.n)
+    tun = gpu.rt_tuning(solve_fused=fused)
     ds = gpu.DeviceSolve(sp.scene, sp.zs, sp.zr, sp.dist)
-    ds.launch()
+    ds.launch(tuning=tun)
     ref, ref_st = ds.collect()
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
-        ds.launch(stream=s)  # warm-up on the capture stream
+        ds.launch(stream=s, tuning=tun)  # warm-up on the capture stream
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     with torch.cuda.graph(g):
-        ds.launch()
+        ds.launch(tuning=tun)
     for rep in range(3):
         for t in ds.res.values():
             t.fill_(-7)  # eager work between replays
