@@ -174,7 +174,10 @@ rt_status rt_surrogate_workspace_bytes(const rt_field* field, int64_t n_pairs,
  * for raytrace_solve; path [2 n] (device) receives RT_PATH_*;
  * *fallback_pairs (device, one int64) the number of pairs with an entry
  * solved by the tracer; out->stats the shots and steps of the seeded phase
- * plus the fallback solve. */
+ * plus the fallback solve.  tuning (may be NULL): block size and refill
+ * threshold of the seeded phase and of the tracer's solve, whose scan
+ * interleave and fused launch it also sets (results do not depend on it);
+ * its events are not recorded. */
 rt_status raytrace_solve_surrogate(const rt_field* field, const rt_boundaries* boundaries,
                                    double tol, const rt_step_limits* limits,
                                    const rt_pairs* pairs, const rt_solve_params* fallback,

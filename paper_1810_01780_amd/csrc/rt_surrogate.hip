@@ -337,8 +337,17 @@ extern "C" rt_status raytrace_solve_surrogate(const rt_field* field, const rt_bo
     HIP_TRY(hipGetLastError());
   }
   const rt_pairs cp = {L.czs, L.czr, L.cdist, n};
+  // the caller's launch tuning serves the tracer's solve too (block size,
+  // refill threshold, scan interleave, fused launch); its events are not
+  // recorded by this call
+  rt_tuning ft;
+  memset(&ft, 0, sizeof ft);
+  if (tuning) {
+    ft = *tuning;
+    ft.ev_trace_begin = ft.ev_trace_end = nullptr;
+  }
   if ((st = solve_enqueue(field, bnd, tol, lim, &cp, n, L.count, L.fam, fb, &C, L.solve_ws,
-                          stream, nullptr)) != RT_OK)
+                          stream, tuning ? &ft : nullptr)) != RT_OK)
     return st;
   if (n > 0) {
     hipLaunchKernelGGL(scatter_kernel, dim3(g1), dim3(256), 0, s, L.idx, L.count, L.fam, n, C,

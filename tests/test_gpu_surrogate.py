@@ -144,3 +144,23 @@ def test_surrogate_solve_end_to_end(gpu, oracle_lib, trained):
     print(f"[gpu-case] surrogate-solve: tracer {t_tr * 1e3:.2f} ms, surrogate "
           f"{t_su * 1e3:.2f} ms, gain {t_tr / t_su:.2f}x", flush=True)
     assert t_su < t_tr / 1.2
+
+
+def test_surrogate_solve_fused_tracer(gpu, trained):
+    """The surrogate solve with its tracer entries solved by the fused launch
+    (pair count read on the device, families masked) gives the outputs of
+    the default three launches bit for bit."""
+    n = 65536
+    sp_ = W.solve_pairs(n)
+    _announce(f"surrogate-solve fused tracer: {n} pairs")
+    sp = gpu.surrogate_params(z0=75.0, dn=0.43, verify_tol=0.01, max_shots=8, absent_logit=-2.0,
+                              multi_logit=-3.0)
+    ds = gpu.DeviceSurrogateSolve(sp_.scene, sp_.zs, sp_.zr, sp_.dist, sp)
+    ds.launch(trained.params)
+    a, sa = ds.collect()
+    ds.launch(trained.params, tuning=gpu.rt_tuning(solve_fused=1))
+    b, sb = ds.collect()
+    assert (a["path"] == gpu.RT_PATH_TRACER).sum() > 1000
+    for f in a:
+        assert np.array_equal(a[f], b[f]), f
+    assert sa == sb
