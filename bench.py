@@ -147,6 +147,20 @@ def _hip():
     return lib
 
 
+def device_info():
+    """The GPU the run used: name, compute units, peak engine clock."""
+    import torch
+    hip = _hip()
+    v = ctypes.c_int()
+    dev = torch.cuda.current_device()
+    info = {"name": torch.cuda.get_device_name(dev)}
+    for key, attr in (("compute_units", 63), ("clock_mhz", 5)):
+        # hipDeviceAttributeMultiprocessorCount, hipDeviceAttributeClockRate (kHz)
+        if hip.hipDeviceGetAttribute(ctypes.byref(v), attr, dev) == 0:
+            info[key] = v.value // 1000 if key == "clock_mhz" else v.value
+    return info
+
+
 def make_scene(name):
     from paper_1810_01780_amd import workloads as W
     if name == "twolayer":
@@ -686,7 +700,7 @@ def main():
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": cfg,
-           "roofline": roof}
+           "roofline": roof, "device": device_info()}
     if args.workload == "twolayer" and not args.no_solves:
         # the metric's second part: emitter -> receiver solves/s of the
         # surrogate path and of the tracer alone, on a 1,048,576-pair batch
