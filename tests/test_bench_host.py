@@ -50,6 +50,25 @@ def test_traffic_only_for_the_measured_sources(monkeypatch):
     assert bench.measured_traffic("curved") is None    # never measured
 
 
+def test_executed_fp64_from_counters(monkeypatch):
+    """Executed FP64 counts every lane of each FP64 instruction, FMA as two
+    operations, and is reported only for the measured sources."""
+    d = bench.kernel_digest()
+    monkeypatch.setattr(bench, "EXEC_FP64", {"twolayer": (10.0, 4.0, 2.0, 1.0, 64, d),
+                                             "grid256": (1.0, 1.0, 1.0, 1.0, 1, "f" * 64)})
+    e = bench.executed_fp64("twolayer", 2.0)
+    assert e["flop_per_trial"] == pytest.approx(64 * (20 + 4 + 2 + 1) / 64)
+    assert e["tflops"] == pytest.approx(64 * 27 / 2.0 / 1e12)
+    assert e["frac"] == pytest.approx(e["tflops"] / bench.PEAK_FP64_VECTOR_TFLOPS)
+    assert bench.executed_fp64("grid256", 1.0) is None
+    assert bench.executed_fp64("curved", 1.0) is None
+    # the committed figures belong to the committed trace sources
+    for w, t in bench.EXEC_FP64.items():
+        assert t[5] == d, w
+    for w, t in bench.TRAFFIC.items():
+        assert t[2] == d, w
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
