@@ -62,11 +62,15 @@ def test_executed_fp64_from_counters(monkeypatch):
     assert e["frac"] == pytest.approx(e["tflops"] / bench.PEAK_FP64_VECTOR_TFLOPS)
     assert bench.executed_fp64("grid256", 1.0) is None
     assert bench.executed_fp64("curved", 1.0) is None
-    # the committed figures belong to the committed trace sources
-    for w, t in bench.EXEC_FP64.items():
-        assert t[5] == d, w
-    for w, t in bench.TRAFFIC.items():
-        assert t[2] == d, w
+
+
+def test_counter_constants_belong_to_the_committed_sources():
+    """The traffic, L2 and FP64 counts in bench.py were measured on the trace
+    sources as committed (a kernel change must re-measure them)."""
+    d = bench.kernel_digest()
+    for table, at in ((bench.TRAFFIC, 2), (bench.L2_HIT, 2), (bench.EXEC_FP64, 5)):
+        for w, t in table.items():
+            assert t[at] == d, w
 
 
 def test_more_than_one_gpu_is_refused():
