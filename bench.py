@@ -59,10 +59,10 @@ BYTES_PER_TRIAL_GRID = 768
 # code: comments and whitespace removed); after a change to the code the
 # traffic is reported as null until measured again.
 TRAFFIC = {  # workload -> (fetch bytes, write bytes, digest)
-    "twolayer": (2.9229e+09, 4.1196e+09,
-                 "d0c66a5d7ff95ea049644ffe0d7b62480964ee1ca908a70cd22fc8c3ff52ee3b"),
-    "grid256": (1.2435e+11, 2.5716e+09,
-                "d0c66a5d7ff95ea049644ffe0d7b62480964ee1ca908a70cd22fc8c3ff52ee3b"),
+    "twolayer": (2.9294e+09, 4.1181e+09,
+                 "89e253342b7b13119e670cac1e30a8686dabadd1e05632db276fd97c85f56764"),
+    "grid256": (1.0167e+11, 2.5759e+09,
+                "89e253342b7b13119e670cac1e30a8686dabadd1e05632db276fd97c85f56764"),
 }
 TRACE_SOURCES = ("rt_kernels.hip", "rt_strat.hip", "rt_trace.hpp", "rt_device.hpp",
                  "rt_params.hpp")
@@ -92,8 +92,8 @@ def kernel_digest(sources=None):
 # L2 hit fraction of the trace kernel's requests (rocprofv3 TCC_HIT_sum,
 # TCC_MISS_sum of one launch), valid for the listed code digest like TRAFFIC.
 L2_HIT = {  # workload -> (hits, misses, digest)
-    "grid256": (4.7757e+09, 1.0491e+09,
-                "d0c66a5d7ff95ea049644ffe0d7b62480964ee1ca908a70cd22fc8c3ff52ee3b"),
+    "grid256": (3.9961e+09, 8.7349e+08,
+                "89e253342b7b13119e670cac1e30a8686dabadd1e05632db276fd97c85f56764"),
 }
 
 # FP64 instructions the trace kernel issues per launch (rocprofv3
@@ -102,8 +102,8 @@ L2_HIT = {  # workload -> (hits, misses, digest)
 # listed code digest like TRAFFIC.  The headline FLOP/s counts the method's
 # work per trial (FLOP_PER_TRIAL); this is what the kernel executes for it.
 EXEC_FP64 = {  # workload -> (fma, mul, add, trans, trial steps, digest)
-    "twolayer": (4.49615e9, 1.33804e9, 2.1842e8, 2.2128e8, 1621800464,
-                 "d0c66a5d7ff95ea049644ffe0d7b62480964ee1ca908a70cd22fc8c3ff52ee3b"),
+    "twolayer": (4.49195e9, 1.33698e9, 2.18356e8, 2.21103e8, 1621800464,
+                 "89e253342b7b13119e670cac1e30a8686dabadd1e05632db276fd97c85f56764"),
 }
 
 

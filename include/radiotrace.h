@@ -292,8 +292,8 @@ typedef struct {
   int32_t block_size;       /* threads per block: 64, 128, 192 or 256; 0 = 256 */
   int32_t blocks_per_cu;    /* resident blocks per CU; 0 = occupancy maximum */
   int32_t refill_threshold; /* a wave refills when at least this many of its
-                               64 lanes are idle (1..64); 0 = 32 for traces,
-                               16 for solves */
+                               64 lanes are idle (1..64); 0 = 32 for traces
+                               (48 for gridded media), 16 for solves */
   void* ev_trace_begin;     /* hipEvent_t recorded just before the trace
                                kernel, or NULL */
   void* ev_trace_end;       /* hipEvent_t recorded just after it, or NULL */
