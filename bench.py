@@ -307,7 +307,7 @@ def bench_solve(args, log):
     50-2000 m, receiver depth 0-200 m, distance 10 m - 3 km) in the two-layer
     firn model, direct and surface-reflected solution of each.  A step is one
     raytrace_solve of the whole batch replayed from a captured graph, with the
-    launch tuning chosen by rt_solve_autotune on a 16,384-pair sample."""
+    launch tuning chosen by rt_solve_autotune on the whole batch."""
     import torch
     from paper_1810_01780_amd import binding
     from paper_1810_01780_amd import workloads as W
@@ -323,7 +323,9 @@ def bench_solve(args, log):
                                 scan_chunk=args.scan_chunk, solve_fused=args.fused or 0)
         cfg["tuning"] = "fixed"
     else:
-        m = 16384
+        # the whole batch: a 16,384-pair sample picked tunings 6 % apart from
+        # run to run on the full solve
+        m = sp.n
         sample = binding.DeviceSolve(sp.scene, sp.zs[:m], sp.zr[:m], sp.dist[:m], prm)
         tun, ms = sample.autotune()
         log(f"autotune on {m} pairs: block {tun.block_size} refill {tun.refill_threshold} "
