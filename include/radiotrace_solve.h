@@ -194,9 +194,10 @@ rt_status raytrace_shoot(const rt_field* field, const rt_boundaries* boundaries,
  * in three launches (scan_chunk 1), then scan_chunk in {4, 16, 64} at the
  * best of those, then the fused launch (solve_fused 1) at each block size
  * and refill_threshold 16 when n_scan <= 64 and max_brackets <= 4; each
- * runs raytrace_solve once on 'pairs' (a representative sample; its results
- * land in 'out' and are overwritten by each candidate) after one untimed
- * call, timed with HIP events on 'stream'; the fastest is written to *best
+ * runs raytrace_solve twice on 'pairs' (a representative sample; its results
+ * land in 'out' and are overwritten by each candidate), after one untimed
+ * call for the whole search, timed with HIP events on 'stream', its faster
+ * run counting; the fastest candidate is written to *best
  * (other fields zero) and its time in ms to *best_ms (may be NULL).  This
  * call blocks the host until each candidate finishes, so it cannot be
  * captured into a graph: tune first, then capture raytrace_solve with the

@@ -1535,22 +1535,28 @@ extern "C" rt_status rt_solve_autotune(const rt_field* field, const rt_boundarie
   cand.scan_chunk = 1;
   st = raytrace_solve(field, bnd, tol, L, pairs, prm, out, workspace, workspace_bytes, stream,
                       &cand);
+  // each candidate is timed twice and its faster run counts (the launch
+  // tunings differ by a few per cent, about the spread of single runs)
   auto trial = [&](const rt_tuning& c) {
-    hipError_t e = hipEventRecord(e0, s);
-    if (e == hipSuccess)
-      st = raytrace_solve(field, bnd, tol, L, pairs, prm, out, workspace, workspace_bytes,
-                          stream, &c);
-    if (e == hipSuccess && st == RT_OK) e = hipEventRecord(e1, s);
-    if (e == hipSuccess && st == RT_OK) e = hipEventSynchronize(e1);
-    float ms = 0.0f;
-    if (e == hipSuccess && st == RT_OK) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e != hipSuccess) {
-      set_last_error("autotune timing: %s", hipGetErrorString(e));
-      st = RT_ERR_DEVICE;
-      return;
+    float best_c = -1.0f;
+    for (int rep = 0; rep < 2 && st == RT_OK; ++rep) {
+      hipError_t e = hipEventRecord(e0, s);
+      if (e == hipSuccess)
+        st = raytrace_solve(field, bnd, tol, L, pairs, prm, out, workspace, workspace_bytes,
+                            stream, &c);
+      if (e == hipSuccess && st == RT_OK) e = hipEventRecord(e1, s);
+      if (e == hipSuccess && st == RT_OK) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess && st == RT_OK) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        set_last_error("autotune timing: %s", hipGetErrorString(e));
+        st = RT_ERR_DEVICE;
+        return;
+      }
+      if (st == RT_OK && (best_c < 0.0f || ms < best_c)) best_c = ms;
     }
-    if (st == RT_OK && (best_t < 0.0f || ms < best_t)) {
-      best_t = ms;
+    if (st == RT_OK && (best_t < 0.0f || best_c < best_t)) {
+      best_t = best_c;
       *best = c;
     }
   };
