@@ -21,13 +21,19 @@
  * the polarisation convention and the ray-tree bookkeeping open; this file
  * takes one explicit reading of each (see the comments at each step).
  *
- * Parity unpinned (conventions with no value in the paper and no closed form
- * to check them against): the crossing search's stopping tolerances (|g| <=
- * 1e-10 m, bracket 1e-14 h, 60 trials) and the start value of the search for
- * a ray leaving the boundary it stands on; the solver's scan and stopping
- * constants (angle scan, Illinois stopping widths and slope bound).  Every
- * other function is pinned by the CPU tests (closed forms, conservation
- * laws, Fresnel identities, convergence orders, the paper's accuracy study).
+ * Constants with no value in the paper (conventions): the crossing search's
+ * stopping tolerances (|g| <= 1e-10 m, bracket 1e-14 h, 60 trials) and the
+ * start value of the search for a ray leaving the boundary it stands on; the
+ * solver's scan and stopping constants (angle scan, Illinois stopping widths
+ * and slope bound).  The constants themselves are not pinned; the functions
+ * that use them are, through their results: crossing points against the
+ * closed-form line-plane intersection and the chord through a spherical
+ * void, solver roots against the straight-line and mirror solutions of a
+ * constant medium and the closed form of the exponential profile, the scan
+ * against a dense scan, the slope bound against the roots it may drop.
+ * Every other function is pinned by the CPU tests (closed forms,
+ * conservation laws, Fresnel identities, convergence orders, the paper's
+ * accuracy study).
  *
  * Nothing here is shared with the GPU library.
  */
