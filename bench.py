@@ -411,8 +411,9 @@ def surrogate_run(n_pairs, steps, warmup, log, net=None):
     are solved as one batch, by the captured raytrace_solve_surrogate graph
     (network inference on the whole batch, seeded secant with shot
     verification, tracer for every other entry) and by the tracer's captured
-    raytrace_solve graph; each is replayed warmup + steps times, the steps
-    timed.  Returns the measured figures and the entry classification."""
+    raytrace_solve graph, both with the tracer launch tuning that
+    rt_solve_autotune picks on the batch's first 65,536 pairs; each is
+    replayed warmup + steps times, the steps timed.  Returns the measured figures and the entry classification."""
     import numpy as np
     import torch
     from paper_1810_01780_amd import binding
@@ -427,6 +428,18 @@ def surrogate_run(n_pairs, steps, warmup, log, net=None):
     sp = W.solve_pairs(n_pairs)
     prm = binding.solve_params()
     spar = binding.surrogate_params(z0=75.0, dn=0.43)
+    # one launch tuning for the tracer's solve in both graphs (the surrogate's
+    # tracer entries and the tracer alone), picked by rt_solve_autotune on the
+    # batch's first 65,536 pairs
+    m = min(sp.n, 1 << 16)
+    sample = binding.DeviceSolve(sp.scene, sp.zs[:m], sp.zr[:m], sp.dist[:m], prm)
+    tun, _ = sample.autotune()
+    del sample
+    out.update(tuning=dict(block=tun.block_size, refill=tun.refill_threshold,
+                           scan_chunk=tun.scan_chunk, fused=tun.solve_fused,
+                           picked_on_pairs=m))
+    log(f"tracer tuning (autotuned on {m} pairs): block {tun.block_size} refill "
+        f"{tun.refill_threshold} scan chunk {tun.scan_chunk} fused {tun.solve_fused}")
     ds = binding.DeviceSurrogateSolve(sp.scene, sp.zs, sp.zr, sp.dist, spar, prm)
     tr = binding.DeviceSolve(sp.scene, sp.zs, sp.zr, sp.dist, prm)
 
@@ -442,8 +455,8 @@ def surrogate_run(n_pairs, steps, warmup, log, net=None):
             fn(None)
         return g
 
-    g_su = graph_of(lambda s: ds.launch(net.params, stream=s))
-    g_tr = graph_of(lambda s: tr.launch(stream=s))
+    g_su = graph_of(lambda s: ds.launch(net.params, stream=s, tuning=tun))
+    g_tr = graph_of(lambda s: tr.launch(stream=s, tuning=tun))
 
     def timed(g):
         for _ in range(warmup):
