@@ -402,7 +402,7 @@ def bench_solve(args, log):
     print(json.dumps(out), flush=True)
 
 
-def surrogate_run(n_pairs, steps, warmup, log, net=None):
+def surrogate_run(n_pairs, steps, warmup, log, net=None, multi_logit=-10.0):
     """Surrogate-seeded solves against the tracer alone on the same GPU.
 
     The network is trained first (the default recipe: tracer solves of
@@ -427,7 +427,7 @@ def surrogate_run(n_pairs, steps, warmup, log, net=None):
                    training_s=round(time.perf_counter() - t0, 1), final_loss=losses[-1][1])
     sp = W.solve_pairs(n_pairs)
     prm = binding.solve_params()
-    spar = binding.surrogate_params(z0=75.0, dn=0.43)
+    spar = binding.surrogate_params(z0=75.0, dn=0.43, multi_logit=multi_logit)
     # one launch tuning for the tracer's solve in both graphs (the surrogate's
     # tracer entries and the tracer alone), picked by rt_solve_autotune on the
     # batch's first 65,536 pairs
@@ -518,7 +518,8 @@ def surrogate_run(n_pairs, steps, warmup, log, net=None):
 def bench_surrogate(args, log):
     """Surrogate-seeded solves of a 1,048,576-pair batch (surrogate_run); the
     JSON line carries the tracer's rate on the same pairs and GPU."""
-    r, _, sp = surrogate_run(1 << 20, args.steps, args.warmup, log)
+    r, _, sp = surrogate_run(1 << 20, args.steps, args.warmup, log,
+                             multi_logit=args.multi_logit)
     t_su = r["surrogate_ms"] / 1e3
     achieved = r["trial_steps"] * FLOP_PER_TRIAL[0] / t_su / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
@@ -607,6 +608,8 @@ def main():
     ap.add_argument("--fused", type=int, default=None, choices=[0, 1],
                     help="solve: 1 = one fused launch, 0 = scan, refine and select launches "
                          "(default: autotune)")
+    ap.add_argument("--multi-logit", type=float, default=-10.0,
+                    help="surrogate: several-roots logit above which the tracer solves an entry")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--cpu-threads", type=int, default=16,

@@ -132,7 +132,9 @@ typedef struct {
   float absent_logit;  /* existence logit at or below which an entry is not
                           seeded (the tracer solves it) */
   float multi_logit;   /* several-roots logit above which an entry is not
-                          seeded (the tracer picks its first arrival) */
+                          seeded (the tracer picks its first arrival); a
+                          low value such as -10 sends every family the
+                          network is unsure of to the tracer */
 } rt_surrogate_params;
 
 /* How each entry [2 pair + family] of a surrogate solve was decided. */

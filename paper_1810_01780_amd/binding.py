@@ -792,7 +792,7 @@ class DeviceMLP:
 
 # --- surrogate-seeded solves ----------------------------------------------------
 def surrogate_params(z0=75.0, dn=0.43, verify_tol=0.01, dseed=1e-4, max_shots=8,
-                     absent_logit=-2.0, multi_logit=-3.0):
+                     absent_logit=-2.0, multi_logit=-10.0):
     return rt_surrogate_params(z0, dn, verify_tol, dseed, max_shots, absent_logit, multi_logit)
 
 

@@ -7,10 +7,9 @@
   tracer and the oracle: every entry the surrogate path reports is a
   verified solution (|miss| <= verify_tol, confirmed by an oracle shot at its
   angle), tracer entries equal the tracer's own solve bit for bit, every
-  entry the tracer solves is solved, first arrivals later than the
-  tracer's by more than 0.1 ns are rarer than the tracer's own against a
-  dense scan, and the surrogate path is faster than the tracer alone on the
-  same GPU.
+  entry the tracer solves is solved, no first arrival is later than the
+  tracer's by more than 0.1 ns, and the surrogate path is faster than the
+  tracer alone on the same GPU.
 """
 import math
 import sys
@@ -83,7 +82,7 @@ def test_surrogate_solve_end_to_end(gpu, oracle_lib, trained):
     sp_ = W.solve_pairs(n)
     _announce(f"surrogate-solve: {n} pairs")
     sp = gpu.surrogate_params(z0=75.0, dn=0.43, verify_tol=0.01, max_shots=8, absent_logit=-2.0,
-                              multi_logit=-3.0)
+                              multi_logit=-10.0)
     # tracer alone
     ref = gpu.DeviceSolve(sp_.scene, sp_.zs, sp_.zr, sp_.dist)
     ref.launch()
@@ -115,10 +114,10 @@ def test_surrogate_solve_end_to_end(gpu, oracle_lib, trained):
     # first arrivals: where both have a solution, how often the surrogate's
     # travel time is later than the tracer's by more than 0.1 ns (the
     # verified root is another root of the family) or earlier (a root the
-    # tracer's scan missed).  Families with several roots go to the tracer
-    # when the network predicts them; the rest of the time a later arrival
-    # must be rarer than the 64-angle scan's own later arrivals against a
-    # dense scan (0.15 %, tests/test_oracle_solve.py).
+    # tracer's scan missed).  With the several-roots threshold at -10 every
+    # family the network is unsure of goes to the tracer: no later arrival
+    # is allowed (0 measured on this batch, with this network and with the
+    # larger benchmark one).
     both = sur & (rres["found"] == 1)
     dt = res["t"][both] - rres["t"][both]
     later, earlier = int((dt > 0.1e-9).sum()), int((dt < -0.1e-9).sum())
@@ -127,7 +126,7 @@ def test_surrogate_solve_end_to_end(gpu, oracle_lib, trained):
                 surrogate_found=int(res["found"].sum()), later=later, earlier=earlier,
                 shots=st["shots"], tracer_shots=rst["shots"])
     print(f"[gpu-case] surrogate-solve: {summ}", flush=True)
-    assert later <= 0.0015 * both.sum(), summ
+    assert later == 0, summ
     assert int(sur.sum()) >= 0.3 * sur.size, summ
     # speed on the same GPU: best of 3 each
     def timed(fn):
@@ -154,7 +153,7 @@ def test_surrogate_solve_fused_tracer(gpu, trained):
     sp_ = W.solve_pairs(n)
     _announce(f"surrogate-solve fused tracer: {n} pairs")
     sp = gpu.surrogate_params(z0=75.0, dn=0.43, verify_tol=0.01, max_shots=8, absent_logit=-2.0,
-                              multi_logit=-3.0)
+                              multi_logit=-10.0)
     ds = gpu.DeviceSurrogateSolve(sp_.scene, sp_.zs, sp_.zr, sp_.dist, sp)
     ds.launch(trained.params)
     a, sa = ds.collect()
